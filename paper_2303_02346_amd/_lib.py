@@ -1,0 +1,84 @@
+"""ctypes binding of libmpm.so (include/mpm.h): argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpm.so")
+
+MPM_OK, MPM_EINVAL, MPM_EWORKSPACE, MPM_EHIP, MPM_EDOMAIN, MPM_ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class MpmMaterial(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("mu", ctypes.c_float), ("lambda_", ctypes.c_float),
+                ("viscosity", ctypes.c_float), ("friction_deg", ctypes.c_float), ("cohesion", ctypes.c_float),
+                ("p_vol", ctypes.c_float), ("p_mass", ctypes.c_float)]
+
+
+class MpmState(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("F", ctypes.c_void_p), ("J", ctypes.c_void_p), ("mat", ctypes.c_void_p)]
+
+
+class MpmDesc(ctypes.Structure):
+    _fields_ = [("n_grid", ctypes.c_int32), ("dt", ctypes.c_float), ("gravity", ctypes.c_float * 3),
+                ("bound", ctypes.c_int32), ("n_particles", ctypes.c_int32), ("n_materials", ctypes.c_int32),
+                ("materials", ctypes.POINTER(MpmMaterial)), ("n_scenes", ctypes.c_int32),
+                ("scene_offsets", ctypes.POINTER(ctypes.c_int64)), ("cyl_radius", ctypes.POINTER(ctypes.c_float)),
+                ("cyl_pos0", ctypes.POINTER(ctypes.c_float)), ("cyl_rot0", ctypes.POINTER(ctypes.c_float)),
+                ("contact_band", ctypes.c_float), ("contact_friction", ctypes.c_float),
+                ("horizon", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("requires_grad", ctypes.c_int32)]
+
+
+EXPORTS = ["mpm_workspace_bytes", "mpm_create", "mpm_set_state", "mpm_set_actions", "mpm_step",
+           "mpm_step_backward", "mpm_loss_blob", "mpm_clock", "mpm_last_error_bits", "mpm_destroy",
+           "mpm_strerror"]
+
+_lib = None
+
+
+class MpmError(RuntimeError):
+    def __init__(self, status: int, where: str, bits: int = 0):
+        self.status = status
+        self.bits = bits
+        super().__init__(f"{where}: {lib().mpm_strerror(status).decode()} (status {status}, error bits {bits})")
+
+
+def lib():
+    """Load libmpm.so.  There is no fallback: a missing library is an error."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2303_02346_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    L.mpm_workspace_bytes.argtypes = [ctypes.POINTER(MpmDesc)]
+    L.mpm_workspace_bytes.restype = ctypes.c_size_t
+    L.mpm_create.argtypes = [ctypes.POINTER(MpmDesc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.mpm_set_state.argtypes = [vp, ctypes.POINTER(MpmState)]
+    L.mpm_set_actions.argtypes = [vp, i32, i32, vp]
+    L.mpm_step.argtypes = [vp, i32]
+    L.mpm_step_backward.argtypes = [vp, ctypes.POINTER(MpmState), vp, ctypes.POINTER(MpmState)]
+    L.mpm_loss_blob.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_float, vp, ctypes.POINTER(MpmState)]
+    L.mpm_clock.argtypes = [vp, ctypes.POINTER(i32)]
+    L.mpm_last_error_bits.argtypes = [vp, ctypes.POINTER(i32)]
+    L.mpm_destroy.argtypes = [vp]
+    L.mpm_strerror.argtypes = [ctypes.c_int]
+    L.mpm_strerror.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("mpm_workspace_bytes", "mpm_strerror"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int, where: str, ctx=None):
+    if status != MPM_OK:
+        bits = 0
+        if ctx is not None and status == MPM_EDOMAIN:
+            b = ctypes.c_int32(0)
+            lib().mpm_last_error_bits(ctx, ctypes.byref(b))
+            bits = b.value
+        raise MpmError(status, where, bits)

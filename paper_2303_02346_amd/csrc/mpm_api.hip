@@ -1,0 +1,388 @@
+// C ABI of the MLS-MPM step (declared in include/mpm.h): workspace planning,
+// context state, step/backward orchestration and error handling.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+#include <new>
+#include <vector>
+
+#include "../../include/mpm.h"
+#include "mpm_internal.h"
+#include "mpm_fast.h"
+
+using namespace mpm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Layout {
+  size_t mats, offs, pscene, cyl_radius, err, mmv, vgrid, vbar, mmvb, pose, act, acc, ckpt, seg, adj0, adj1, scratch;
+  size_t fast;
+  size_t total;
+  int n_ckpt;
+};
+
+bool desc_ok(const mpm_desc* d) {
+  if (!d) return false;
+  if (d->n_grid < 8 || d->n_grid > 1024) return false;
+  if (d->n_particles < 1 || d->n_materials < 1 || d->n_materials > 256 || !d->materials) return false;
+  if (d->n_scenes < 1) return false;
+  if (d->n_scenes > 1 && !d->scene_offsets) return false;
+  if (!d->cyl_radius || !d->cyl_pos0 || !d->cyl_rot0) return false;
+  if (!(d->dt > 0.f) || d->horizon < 1 || d->bound < 0) return false;
+  if (d->requires_grad && d->ckpt_every < 1) return false;
+  if (d->scene_offsets) {
+    if (d->scene_offsets[0] != 0 || d->scene_offsets[d->n_scenes] != d->n_particles) return false;
+    for (int s = 0; s < d->n_scenes; s++)
+      if (d->scene_offsets[s + 1] < d->scene_offsets[s]) return false;
+  }
+  size_t nodes = (size_t)d->n_grid * d->n_grid * d->n_grid * d->n_scenes;
+  if (nodes > ((size_t)1 << 34)) return false;
+  return true;
+}
+
+Layout plan(const mpm_desc* d) {
+  Layout L;
+  size_t N = d->n_particles, S = d->n_scenes, T = d->horizon;
+  size_t nodes = (size_t)d->n_grid * d->n_grid * d->n_grid * S;
+  size_t st = align_up(STATE_FLOATS * N * sizeof(float));
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o += align_up(b); return r; };
+  L.mats = take(256 * sizeof(MatDev));
+  L.offs = take((S + 1) * sizeof(int64_t));
+  L.pscene = take(N * sizeof(int));
+  L.cyl_radius = take(S * sizeof(float));
+  L.err = take(64);
+  L.mmv = take(nodes * sizeof(float4));
+  L.vgrid = take(nodes * sizeof(float4));
+  L.pose = take((T + 1) * S * POSE_DOUBLES * sizeof(double));
+  L.act = take(T * S * 6 * sizeof(float));
+  L.scratch = take(64);
+  L.fast = take(fast_workspace_bytes(d->n_grid, (int)S, (int)N));
+  if (d->requires_grad) {
+    int k = d->ckpt_every;
+    L.n_ckpt = (int)((T + k - 1) / k) + 1;
+    L.vbar = take(nodes * sizeof(float4));
+    L.mmvb = take(nodes * sizeof(float4));
+    L.acc = take(T * S * ACC_DOUBLES * sizeof(double));
+    L.ckpt = take(st * L.n_ckpt);
+    L.seg = take(st * (size_t)(k + 1));
+    L.adj0 = take(st);
+    L.adj1 = take(st);
+  } else {
+    L.n_ckpt = 0;
+    L.vbar = L.mmvb = L.acc = L.ckpt = L.seg = L.adj0 = L.adj1 = 0;
+  }
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct mpm_ctx {
+  mpm_desc d;
+  Layout L;
+  hipStream_t stream;
+  char* ws;
+  std::vector<MatDev> mats;
+  std::vector<float> cyl_pos0, cyl_rot0, cyl_radius;
+  std::vector<char> act_set;
+  mpm_state user;
+  bool has_state;
+  int t;
+  int last_err_bits;
+  size_t state_bytes;
+  FastPath fast;
+};
+
+static int hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_EHIP; }
+
+static StepParams make_params(mpm_ctx* c) {
+  StepParams P;
+  P.n_grid = c->d.n_grid;
+  P.n_scenes = c->d.n_scenes;
+  P.n_particles = c->d.n_particles;
+  P.bound = c->d.bound;
+  P.dx = 1.0f / c->d.n_grid;
+  P.inv_dx = (float)c->d.n_grid;
+  P.dt = c->d.dt;
+  for (int k = 0; k < 3; k++) P.grav[k] = c->d.gravity[k];
+  P.band = c->d.contact_band;
+  P.friction = c->d.contact_friction;
+  P.mats = (const MatDev*)(c->ws + c->L.mats);
+  P.mat = c->user.mat;
+  P.pscene = (const int*)(c->ws + c->L.pscene);
+  P.cyl_radius = (const float*)(c->ws + c->L.cyl_radius);
+  P.err = (int*)(c->ws + c->L.err);
+  return P;
+}
+
+static PState user_pstate(const mpm_state* s, int N) {
+  PState p;
+  p.x = s->x; p.v = s->v; p.C = s->C; p.F = s->F; p.J = s->J; p.N = N;
+  return p;
+}
+
+static float4* G(mpm_ctx* c, size_t off) { return (float4*)(c->ws + off); }
+
+// Read and clear the device error word; the call's only host synchronisation.
+static int finish(mpm_ctx* c) {
+  int* err = (int*)(c->ws + c->L.err);
+  int host = 0;
+  if (hipMemcpyAsync(&host, err, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return MPM_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return MPM_EHIP;
+  if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+  if (host) {
+    c->last_err_bits = host;
+    if (hipMemsetAsync(err, 0, sizeof(int), c->stream) != hipSuccess) return MPM_EHIP;
+    return MPM_EDOMAIN;
+  }
+  return MPM_OK;
+}
+
+extern "C" {
+
+size_t mpm_workspace_bytes(const mpm_desc* d) {
+  if (!desc_ok(d)) return 0;
+  return plan(d).total;
+}
+
+int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* stream, mpm_ctx** out) {
+  if (!out) return MPM_EINVAL;
+  *out = nullptr;
+  if (!desc_ok(d) || !workspace_dev) return MPM_EINVAL;
+  if (((uintptr_t)workspace_dev) % ALIGN) return MPM_EINVAL;
+  Layout L = plan(d);
+  if (ws_bytes < L.total) return MPM_EWORKSPACE;
+  mpm_ctx* c = new (std::nothrow) mpm_ctx();
+  if (!c) return MPM_EINVAL;
+  c->d = *d;
+  c->L = L;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace_dev;
+  c->has_state = false;
+  c->t = 0;
+  c->last_err_bits = 0;
+  c->state_bytes = align_up(STATE_FLOATS * (size_t)d->n_particles * sizeof(float));
+  int S = d->n_scenes;
+  c->mats.resize(256);
+  memset(c->mats.data(), 0, 256 * sizeof(MatDev));
+  for (int m = 0; m < d->n_materials; m++) {
+    const mpm_material& src = d->materials[m];
+    if (src.kind < 0 || src.kind > 2 || !(src.p_mass > 0.f) || !(src.p_vol > 0.f)) { delete c; return MPM_EINVAL; }
+    MatDev& M = c->mats[m];
+    M.kind = src.kind;
+    M.mu = src.mu;
+    M.lam = src.lambda;
+    M.eta = src.viscosity;
+    double sphi = sin(src.friction_deg * M_PI / 180.0);
+    M.alpha = (float)(sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi));
+    M.kappa = src.mu > 0.f ? (float)((3.0 * src.lambda + 2.0 * src.mu) / (2.0 * src.mu)) : 0.f;
+    M.coh = src.cohesion;
+    M.vol = src.p_vol;
+    M.mass = src.p_mass;
+    if (src.kind == MPM_SAND_DP && !(src.mu > 0.f)) { delete c; return MPM_EINVAL; }
+  }
+  c->cyl_radius.assign(d->cyl_radius, d->cyl_radius + S);
+  c->cyl_pos0.assign(d->cyl_pos0, d->cyl_pos0 + 3 * S);
+  c->cyl_rot0.assign(d->cyl_rot0, d->cyl_rot0 + 9 * S);
+  c->act_set.assign(d->horizon, 0);
+  // static tables
+  std::vector<int64_t> offs(S + 1);
+  if (d->scene_offsets) for (int s = 0; s <= S; s++) offs[s] = d->scene_offsets[s];
+  else { offs[0] = 0; offs[1] = d->n_particles; }
+  int rc = MPM_OK;
+  if (hipMemcpyAsync(c->ws + L.mats, c->mats.data(), 256 * sizeof(MatDev), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->ws + L.offs, offs.data(), (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->ws + L.cyl_radius, c->cyl_radius.data(), S * sizeof(float), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ws + L.err, 0, 64, c->stream) != hipSuccess)
+    rc = MPM_EHIP;
+  if (rc == MPM_OK) {
+    launch_scene_index((const int64_t*)(c->ws + L.offs), S, d->n_particles, (int*)(c->ws + L.pscene), c->stream);
+    launch_zero(c->ws + L.vgrid, (size_t)d->n_grid * d->n_grid * d->n_grid * S * sizeof(float4), c->stream);
+    rc = fast_init(c->fast, c->ws + L.fast, d->n_grid, S, d->n_particles, c->stream);
+    fast_bind_grid(c->fast, G(c, L.mmv), G(c, L.vgrid));
+  }
+  if (rc == MPM_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = MPM_EHIP;
+  if (rc != MPM_OK) { delete c; return rc; }
+  *out = c;
+  return MPM_OK;
+}
+
+int mpm_set_state(mpm_ctx* c, const mpm_state* st) {
+  if (!c || !st || !st->x || !st->v || !st->C || !st->F || !st->J || !st->mat) return MPM_EINVAL;
+  c->user = *st;
+  c->has_state = true;
+  c->t = 0;
+  int S = c->d.n_scenes;
+  std::vector<double> pose0((size_t)S * POSE_DOUBLES);
+  for (int s = 0; s < S; s++) {
+    for (int k = 0; k < 3; k++) pose0[s * POSE_DOUBLES + k] = c->cyl_pos0[3 * s + k];
+    for (int k = 0; k < 9; k++) pose0[s * POSE_DOUBLES + 3 + k] = c->cyl_rot0[9 * s + k];
+  }
+  if (hipMemcpyAsync(c->ws + c->L.pose, pose0.data(), pose0.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return MPM_EHIP;
+  fast_invalidate(c->fast);
+  // pose0 is a host temporary: wait for the copy
+  return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+int mpm_set_actions(mpm_ctx* c, int32_t t0, int32_t n, const float* actions_dev) {
+  if (!c || !actions_dev || t0 < 0 || n < 1 || t0 + n > c->d.horizon) return MPM_EINVAL;
+  size_t row = (size_t)c->d.n_scenes * 6 * sizeof(float);
+  if (hipMemcpyAsync(c->ws + c->L.act + (size_t)t0 * row, actions_dev, (size_t)n * row, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return MPM_EHIP;
+  for (int t = t0; t < t0 + n; t++) c->act_set[t] = 1;
+  return MPM_OK;
+}
+
+static const double* pose_at(mpm_ctx* c, int t) {
+  return (const double*)(c->ws + c->L.pose) + (size_t)t * c->d.n_scenes * POSE_DOUBLES;
+}
+static const float* act_at(mpm_ctx* c, int t) {
+  return (const float*)(c->ws + c->L.act) + (size_t)t * c->d.n_scenes * 6;
+}
+
+// One plain step: state `in` -> `out` (may alias).
+static void plain_step(mpm_ctx* c, const StepParams& P, const PState& in, const PState& out, int t) {
+  size_t nodes = (size_t)c->d.n_grid * c->d.n_grid * c->d.n_grid * c->d.n_scenes;
+  launch_zero(G(c, c->L.mmv), nodes * sizeof(float4), c->stream);
+  launch_p2g_plain(in, P, G(c, c->L.mmv), c->stream);
+  launch_grid_plain(P, G(c, c->L.mmv), G(c, c->L.vgrid), pose_at(c, t), act_at(c, t), c->stream);
+  launch_g2p_plain(in, out, P, G(c, c->L.vgrid), c->stream);
+}
+
+int mpm_step(mpm_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 0) return MPM_EINVAL;
+  if (!c->has_state) return MPM_ESTATE;
+  if (n_steps == 0) return MPM_OK;
+  if (c->t + n_steps > c->d.horizon) return MPM_EINVAL;
+  for (int t = c->t; t < c->t + n_steps; t++)
+    if (!c->act_set[t]) return MPM_ESTATE;
+  StepParams P = make_params(c);
+  const int N = c->d.n_particles;
+  PState us = user_pstate(&c->user, N);
+  launch_pose(c->d.n_scenes, c->t, n_steps, c->d.dt, (const float*)(c->ws + c->L.act), (double*)(c->ws + c->L.pose), c->stream);
+  if (c->d.requires_grad) {
+    // plain path, recording checkpoints every k steps
+    int k = c->d.ckpt_every;
+    for (int t = c->t; t < c->t + n_steps; t++) {
+      if (t % k == 0) {
+        PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)(t / k) * c->state_bytes), N);
+        launch_copy_state(us, ck, c->stream);
+      }
+      plain_step(c, P, us, us, t);
+    }
+  } else {
+    int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream);
+    if (rc != MPM_OK) return rc;
+  }
+  c->t += n_steps;
+  if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+  return finish(c);
+}
+
+int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_dev, mpm_state* grad_0) {
+  if (!c || !grad_T || !grad_T->x || !grad_T->v || !grad_actions_dev) return MPM_EINVAL;
+  if (!c->has_state || !c->d.requires_grad || c->t < 1) return MPM_ESTATE;
+  const int N = c->d.n_particles;
+  const int T = c->t;
+  const int k = c->d.ckpt_every;
+  const int S = c->d.n_scenes;
+  StepParams P = make_params(c);
+  size_t nodes = (size_t)c->d.n_grid * c->d.n_grid * c->d.n_grid * S;
+  hipStream_t s = c->stream;
+  PState a_cur = packed_state((float*)(c->ws + c->L.adj0), N);
+  PState a_nxt = packed_state((float*)(c->ws + c->L.adj1), N);
+  // seed with dL/d(state_T); missing components are zero
+  launch_zero(c->ws + c->L.adj0, c->state_bytes, s);
+  size_t fN = (size_t)N * sizeof(float);
+  if (hipMemcpyAsync(a_cur.x, grad_T->x, 3 * fN, hipMemcpyDeviceToDevice, s) != hipSuccess) return MPM_EHIP;
+  if (hipMemcpyAsync(a_cur.v, grad_T->v, 3 * fN, hipMemcpyDeviceToDevice, s) != hipSuccess) return MPM_EHIP;
+  if (grad_T->C && hipMemcpyAsync(a_cur.C, grad_T->C, 9 * fN, hipMemcpyDeviceToDevice, s) != hipSuccess) return MPM_EHIP;
+  if (grad_T->F && hipMemcpyAsync(a_cur.F, grad_T->F, 9 * fN, hipMemcpyDeviceToDevice, s) != hipSuccess) return MPM_EHIP;
+  if (grad_T->J && hipMemcpyAsync(a_cur.J, grad_T->J, fN, hipMemcpyDeviceToDevice, s) != hipSuccess) return MPM_EHIP;
+  double* acc = (double*)(c->ws + c->L.acc);
+  launch_zero(acc, align_up((size_t)T * S * ACC_DOUBLES * sizeof(double)), s);
+  int n_seg = (T + k - 1) / k;
+  for (int seg = n_seg - 1; seg >= 0; seg--) {
+    int ts = seg * k, te = ts + k < T ? ts + k : T;
+    PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)seg * c->state_bytes), N);
+    PState s0 = packed_state((float*)(c->ws + c->L.seg), N);
+    launch_copy_state(ck, s0, s);
+    for (int t = ts; t < te - 1; t++) {
+      PState a = packed_state((float*)(c->ws + c->L.seg + (size_t)(t - ts) * c->state_bytes), N);
+      PState b = packed_state((float*)(c->ws + c->L.seg + (size_t)(t - ts + 1) * c->state_bytes), N);
+      plain_step(c, P, a, b, t);
+    }
+    for (int t = te - 1; t >= ts; t--) {
+      PState st = packed_state((float*)(c->ws + c->L.seg + (size_t)(t - ts) * c->state_bytes), N);
+      launch_zero(G(c, c->L.mmv), nodes * sizeof(float4), s);
+      launch_p2g_plain(st, P, G(c, c->L.mmv), s);
+      launch_grid_plain(P, G(c, c->L.mmv), G(c, c->L.vgrid), pose_at(c, t), act_at(c, t), s);
+      launch_zero(G(c, c->L.vbar), nodes * sizeof(float4), s);
+      launch_g2p_adj_plain(st, a_cur, a_nxt, P, G(c, c->L.vgrid), G(c, c->L.vbar), s);
+      launch_grid_adj_plain(P, G(c, c->L.mmv), G(c, c->L.vbar), G(c, c->L.mmvb), pose_at(c, t), act_at(c, t),
+                            acc + (size_t)t * S * ACC_DOUBLES, s);
+      launch_p2g_adj_plain(st, a_nxt, P, G(c, c->L.mmvb), s);
+      PState tmp = a_cur; a_cur = a_nxt; a_nxt = tmp;
+    }
+  }
+  launch_pose_adj(S, T, c->d.dt, (const float*)(c->ws + c->L.act), (const double*)(c->ws + c->L.pose), acc,
+                  grad_actions_dev, s);
+  if (grad_0) {
+    if (!grad_0->x || !grad_0->v || !grad_0->C || !grad_0->F || !grad_0->J) return MPM_EINVAL;
+    PState g0 = user_pstate(grad_0, N);
+    launch_copy_state(a_cur, g0, s);
+  }
+  if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+  return finish(c);
+}
+
+int mpm_loss_blob(mpm_ctx* c, const float mu_g[3], float sigma_g, float* loss_dev, mpm_state* grad_out) {
+  if (!c || !mu_g || !loss_dev) return MPM_EINVAL;
+  if (!c->has_state) return MPM_ESTATE;
+  StepParams P = make_params(c);
+  PState us = user_pstate(&c->user, c->d.n_particles);
+  double* scratch = (double*)(c->ws + c->L.scratch);
+  launch_zero(scratch, 64, c->stream);
+  launch_loss_blob(P, us, mu_g[0], mu_g[1], mu_g[2], sigma_g, scratch, loss_dev,
+                   (grad_out && grad_out->x) ? grad_out->x : nullptr, c->stream);
+  if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+  return finish(c);
+}
+
+int mpm_clock(const mpm_ctx* c, int32_t* t_out) {
+  if (!c || !t_out) return MPM_EINVAL;
+  *t_out = c->t;
+  return MPM_OK;
+}
+
+int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out) {
+  if (!c || !bits_out) return MPM_EINVAL;
+  *bits_out = c->last_err_bits;
+  return MPM_OK;
+}
+
+int mpm_destroy(mpm_ctx* c) {
+  if (!c) return MPM_EINVAL;
+  fast_destroy(c->fast);
+  delete c;
+  return MPM_OK;
+}
+
+const char* mpm_strerror(int status) {
+  switch (status) {
+    case MPM_OK: return "ok";
+    case MPM_EINVAL: return "invalid argument";
+    case MPM_EWORKSPACE: return "workspace too small";
+    case MPM_EHIP: return "HIP runtime error";
+    case MPM_EDOMAIN: return "simulation left its valid domain (particle outside grid, non-finite value or sand sigma <= 0)";
+    case MPM_ESTATE: return "call out of order (no state, missing actions or no recorded forward)";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal structures shared by the HIP kernels and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpm {
+
+enum { KIND_ELASTIC = 0, KIND_LIQUID = 1, KIND_SAND = 2 };
+enum { ERR_OUTSIDE = 1, ERR_NONFINITE = 2, ERR_SAND_SIGMA = 4, ERR_TILE = 8 };
+
+// Per-material constants as the kernels use them (alpha, kappa precomputed).
+struct MatDev {
+  int kind;
+  float mu, lam, eta;
+  float alpha, kappa, coh;
+  float vol, mass;
+  float pad[3];
+};
+
+// Particle state, structure of arrays: component k of particle p at ptr[k*N + p].
+struct PState {
+  float* x;   // 3
+  float* v;   // 3
+  float* C;   // 9
+  float* F;   // 9
+  float* J;   // 1
+  int N;
+};
+
+// Floats per particle in a packed state buffer (x, v, C, F, J).
+constexpr int STATE_FLOATS = 25;
+
+inline PState packed_state(float* base, int N) {
+  PState s;
+  s.x = base;
+  s.v = base + 3 * (size_t)N;
+  s.C = base + 6 * (size_t)N;
+  s.F = base + 15 * (size_t)N;
+  s.J = base + 24 * (size_t)N;
+  s.N = N;
+  return s;
+}
+
+struct StepParams {
+  int n_grid, n_scenes, n_particles, bound;
+  float dx, inv_dx, dt;
+  float grav[3];
+  float band, friction;
+  const MatDev* mats;      // [n_materials]
+  const uint8_t* mat;      // [N] material index
+  const int* pscene;       // [N] scene index
+  const float* cyl_radius; // [n_scenes]
+  int* err;                // device error word
+};
+
+// Pose history entry: c (3), R (9) in FP64.
+constexpr int POSE_DOUBLES = 12;
+// Per-step, per-scene local adjoint accumulators:
+// u (3), w (3), c (3), axis a = R e_y (3).
+constexpr int ACC_DOUBLES = 12;
+
+// ---- launch wrappers (mpm_kernels.hip) ----
+void launch_pose(int n_scenes, int t0, int n, float dt, const float* act, double* pose, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_p2g_plain(const PState& st, const StepParams& P, float4* mmv, hipStream_t s);
+void launch_grid_plain(const StepParams& P, const float4* mmv, float4* vgrid, const double* pose_t,
+                       const float* act_t, hipStream_t s);
+void launch_g2p_plain(const PState& in, const PState& out, const StepParams& P, const float4* vgrid, hipStream_t s);
+
+void launch_g2p_adj_plain(const PState& st, const PState& bar_next, const PState& bar, const StepParams& P,
+                          const float4* vgrid, float4* vbar_grid, hipStream_t s);
+void launch_grid_adj_plain(const StepParams& P, const float4* mmv, const float4* vbar_grid, float4* mmv_bar,
+                           const double* pose_t, const float* act_t, double* acc_t, hipStream_t s);
+void launch_p2g_adj_plain(const PState& st, const PState& bar, const StepParams& P, const float4* mmv_bar,
+                          hipStream_t s);
+void launch_pose_adj(int n_scenes, int T, float dt, const float* act, const double* pose, const double* acc,
+                     float* grad_act, hipStream_t s);
+
+void launch_loss_blob(const StepParams& P, const PState& st, float mx, float my, float mz, float sigma,
+                      double* scratch, float* loss, float* gx, hipStream_t s);
+void launch_copy_state(const PState& src, const PState& dst, hipStream_t s);
+void launch_scene_index(const int64_t* offs_dev, int n_scenes, int N, int* pscene, hipStream_t s);
+
+}  // namespace mpm

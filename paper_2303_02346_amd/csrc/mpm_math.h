@@ -1,0 +1,195 @@
+// Device math for the MLS-MPM kernels: 3x3 helpers, an FP64 signed SVD and
+// the isotropic-function derivatives used by the constitutive adjoints.
+//
+// Matrices are row-major arrays of 9 (element a*3+b).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mpm {
+
+#define MPM_DI __device__ __forceinline__
+
+template <typename T> MPM_DI void mat_eye(T* A) {
+#pragma unroll
+  for (int i = 0; i < 9; i++) A[i] = (i % 4 == 0) ? T(1) : T(0);
+}
+
+// C = A B
+template <typename T> MPM_DI void matmul(const T* A, const T* B, T* C) {
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) C[i * 3 + j] = A[i * 3] * B[j] + A[i * 3 + 1] * B[3 + j] + A[i * 3 + 2] * B[6 + j];
+}
+// C = A B^T
+template <typename T> MPM_DI void matmul_nt(const T* A, const T* B, T* C) {
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) C[i * 3 + j] = A[i * 3] * B[j * 3] + A[i * 3 + 1] * B[j * 3 + 1] + A[i * 3 + 2] * B[j * 3 + 2];
+}
+// C = A^T B
+template <typename T> MPM_DI void matmul_tn(const T* A, const T* B, T* C) {
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) C[i * 3 + j] = A[i] * B[j] + A[3 + i] * B[3 + j] + A[6 + i] * B[6 + j];
+}
+template <typename T> MPM_DI T det3(const T* A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+// cofactor matrix: cof(A) = det(A) A^{-T}
+template <typename T> MPM_DI void cof3(const T* A, T* K) {
+  K[0] = A[4] * A[8] - A[5] * A[7];
+  K[1] = A[5] * A[6] - A[3] * A[8];
+  K[2] = A[3] * A[7] - A[4] * A[6];
+  K[3] = A[2] * A[7] - A[1] * A[8];
+  K[4] = A[0] * A[8] - A[2] * A[6];
+  K[5] = A[1] * A[6] - A[0] * A[7];
+  K[6] = A[1] * A[5] - A[2] * A[4];
+  K[7] = A[2] * A[3] - A[0] * A[5];
+  K[8] = A[0] * A[4] - A[1] * A[3];
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (Golub and
+// Van Loan, "Matrix Computations", section 8.5): A <- J^T A J, V <- V J.
+// ---------------------------------------------------------------------------
+MPM_DI void jacobi_rotate(double* A, double* V, int p, int q) {
+  double apq = A[p * 3 + q];
+  if (apq == 0.0) return;
+  double app = A[p * 3 + p], aqq = A[q * 3 + q];
+  double tau = (aqq - app) / (2.0 * apq);
+  double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  double c = 1.0 / sqrt(1.0 + t * t);
+  double s = t * c;
+  A[p * 3 + p] = app - t * apq;
+  A[q * 3 + q] = aqq + t * apq;
+  A[p * 3 + q] = 0.0;
+  A[q * 3 + p] = 0.0;
+  int r = 3 - p - q;
+  double arp = A[r * 3 + p], arq = A[r * 3 + q];
+  double nrp = c * arp - s * arq, nrq = s * arp + c * arq;
+  A[r * 3 + p] = nrp; A[p * 3 + r] = nrp;
+  A[r * 3 + q] = nrq; A[q * 3 + r] = nrq;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    double vp = V[k * 3 + p], vq = V[k * 3 + q];
+    V[k * 3 + p] = c * vp - s * vq;
+    V[k * 3 + q] = s * vp + c * vq;
+  }
+}
+
+// Signed SVD F = U diag(s) V^T with U, V in SO(3), s0 >= s1 >= |s2|, and the
+// sign of det F carried by s2.  V and s^2 come from the eigen-decomposition
+// of F^T F; U from the columns of F V (Gram-Schmidt, u2 = u0 x u1).
+MPM_DI void svd3(const double* F, double* U, double* s, double* V) {
+  double A[9];
+  matmul_tn(F, F, A);
+  mat_eye(V);
+  double scale = A[0] * A[0] + A[4] * A[4] + A[8] * A[8] + 1e-300;
+  for (int sweep = 0; sweep < 12; sweep++) {
+    double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    if (off <= 1e-32 * scale) break;
+    jacobi_rotate(A, V, 0, 1);
+    jacobi_rotate(A, V, 0, 2);
+    jacobi_rotate(A, V, 1, 2);
+  }
+  double lam[3] = {A[0], A[4], A[8]};
+  // sort descending, permuting the columns of V
+#pragma unroll
+  for (int pass = 0; pass < 2; pass++) {
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      if (lam[i] < lam[i + 1]) {
+        double tl = lam[i]; lam[i] = lam[i + 1]; lam[i + 1] = tl;
+#pragma unroll
+        for (int k = 0; k < 3; k++) { double tv = V[k * 3 + i]; V[k * 3 + i] = V[k * 3 + i + 1]; V[k * 3 + i + 1] = tv; }
+      }
+    }
+  }
+  if (det3(V) < 0.0) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) V[k * 3 + 2] = -V[k * 3 + 2];
+  }
+  double B[9];
+  matmul(F, V, B);
+  double b0[3] = {B[0], B[3], B[6]}, b1[3] = {B[1], B[4], B[7]}, b2[3] = {B[2], B[5], B[8]};
+  double n0 = sqrt(b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2]);
+  double u0[3], u1[3], u2[3];
+  if (n0 > 1e-300) { u0[0] = b0[0] / n0; u0[1] = b0[1] / n0; u0[2] = b0[2] / n0; }
+  else { u0[0] = 1; u0[1] = 0; u0[2] = 0; }
+  double d01 = u0[0] * b1[0] + u0[1] * b1[1] + u0[2] * b1[2];
+  double w1[3] = {b1[0] - d01 * u0[0], b1[1] - d01 * u0[1], b1[2] - d01 * u0[2]};
+  double n1 = sqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2]);
+  if (n1 > 1e-14 * (n0 + 1e-300)) { u1[0] = w1[0] / n1; u1[1] = w1[1] / n1; u1[2] = w1[2] / n1; }
+  else {
+    // any unit vector orthogonal to u0
+    double a[3] = {0, 0, 0};
+    int k = (fabs(u0[0]) < 0.57) ? 0 : ((fabs(u0[1]) < 0.57) ? 1 : 2);
+    a[k] = 1.0;
+    double d = a[0] * u0[0] + a[1] * u0[1] + a[2] * u0[2];
+    w1[0] = a[0] - d * u0[0]; w1[1] = a[1] - d * u0[1]; w1[2] = a[2] - d * u0[2];
+    double nn = sqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2]);
+    u1[0] = w1[0] / nn; u1[1] = w1[1] / nn; u1[2] = w1[2] / nn;
+    n1 = u1[0] * b1[0] + u1[1] * b1[1] + u1[2] * b1[2];
+  }
+  u2[0] = u0[1] * u1[2] - u0[2] * u1[1];
+  u2[1] = u0[2] * u1[0] - u0[0] * u1[2];
+  u2[2] = u0[0] * u1[1] - u0[1] * u1[0];
+  s[0] = n0;
+  s[1] = n1;
+  s[2] = u2[0] * b2[0] + u2[1] * b2[1] + u2[2] * b2[2];
+#pragma unroll
+  for (int k = 0; k < 3; k++) { U[k * 3 + 0] = u0[k]; U[k * 3 + 1] = u1[k]; U[k * 3 + 2] = u2[k]; }
+}
+
+// U diag(g) V^T
+MPM_DI void usv(const double* U, const double* g, const double* V, double* out) {
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+      out[i * 3 + j] = U[i * 3] * g[0] * V[j * 3] + U[i * 3 + 1] * g[1] * V[j * 3 + 1] + U[i * 3 + 2] * g[2] * V[j * 3 + 2];
+}
+
+// Adjoint of an isotropic map Phi(F) = U diag(g(s)) V^T.  Given Phibar,
+// returns Fbar = U Abar V^T with M = U^T Phibar V and
+//   Abar_kk = sum_i M_ii dg[i][k]
+//   Abar_ij = sdd[i][j] (M_ij + M_ji)/2 + (g_i + g_j)/(s_i + s_j) (M_ij - M_ji)/2
+// where sdd[i][j] is the divided difference (g_i - g_j)/(s_i - s_j) supplied
+// by the caller in a form that is exact at s_i = s_j.
+MPM_DI void iso_adjoint(const double* U, const double* s, const double* V, const double* g, const double* dg,
+                        const double* sdd, const double* Pbar, double* Fbar) {
+  double T1[9], M[9];
+  matmul_tn(U, Pbar, T1);
+  matmul(T1, V, M);
+  double A[9];
+#pragma unroll
+  for (int k = 0; k < 3; k++) A[k * 4] = M[0] * dg[0 * 3 + k] + M[4] * dg[1 * 3 + k] + M[8] * dg[2 * 3 + k];
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      if (i == j) continue;
+      double t = (g[i] + g[j]) / (s[i] + s[j]);
+      A[i * 3 + j] = sdd[i * 3 + j] * 0.5 * (M[i * 3 + j] + M[j * 3 + i]) + t * 0.5 * (M[i * 3 + j] - M[j * 3 + i]);
+    }
+  matmul(U, A, T1);
+  matmul_nt(T1, V, Fbar);
+}
+
+// (log a - log b)/(a - b) for a, b > 0, exact as a -> b.
+MPM_DI double log_divdiff(double a, double b) {
+  double x = (a - b) / b;
+  if (fabs(x) < 1e-4) return (1.0 - x * (0.5 - x * (1.0 / 3.0 - 0.25 * x))) / b;
+  return log1p(x) / (a - b);
+}
+
+// expm1(beta d) / expm1(d), exact as d -> 0.
+MPM_DI double expm1_ratio(double beta, double d) {
+  if (fabs(d) < 1e-6) return beta * (1.0 + 0.5 * (beta - 1.0) * d);
+  return expm1(beta * d) / expm1(d);
+}
+
+}  // namespace mpm

@@ -1,0 +1,245 @@
+"""Python front end of libmpm: torch supplies device memory and the stream,
+every step of the simulation runs in the library's HIP kernels.
+
+Simulator     -- one context (one scene, or many independent scenes batched
+                 in one launch) over torch-allocated buffers.
+MpmRollout    -- torch.autograd.Function: actions -> final positions and
+                 velocities, backward through mpm_step_backward.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Union
+
+import numpy as np
+import torch
+
+from . import _lib
+from .scenes import Scene, concat_scenes
+
+STATE_ROWS = 25   # x(3) v(3) C(9) F(9) J(1), each row of length N
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Simulator:
+    """A libmpm context for one scene or a batch of independent scenes.
+
+    The state lives in ``self.buf`` (float32, shape (25, N), rows x, v, C, F,
+    J) on the GPU; ``x``, ``v`` ... are views.  All arithmetic happens in the
+    library; this class only allocates and passes pointers.
+    """
+
+    def __init__(self, scenes: Union[Scene, Sequence[Scene]], requires_grad: bool = False, ckpt_every: int = 16,
+                 horizon: Optional[int] = None, device: str = "cuda"):
+        if isinstance(scenes, Scene):
+            scenes = [scenes]
+        self.scenes = list(scenes)
+        sc0 = self.scenes[0]
+        for sc in self.scenes:
+            if sc.n_grid != sc0.n_grid or sc.dt != sc0.dt:
+                raise ValueError("batched scenes must share n_grid and dt")
+        self.device = torch.device(device)
+        self.S = len(self.scenes)
+        arrs, offs, mats = concat_scenes(self.scenes)
+        self.N = int(offs[-1])
+        self.offsets = offs
+        self.horizon = int(horizon if horizon is not None else max(sc.horizon for sc in self.scenes))
+        self._mats = (_lib.MpmMaterial * len(mats))()
+        for i, m in enumerate(mats):
+            self._mats[i] = _lib.MpmMaterial(m.kind, m.mu, m.lam, m.viscosity, m.friction_deg, m.cohesion, m.p_vol, m.p_mass)
+        self._offs = (ctypes.c_int64 * (self.S + 1))(*[int(o) for o in offs])
+        self._rad = (ctypes.c_float * self.S)(*[float(sc.cyl_radius) for sc in self.scenes])
+        self._pos = (ctypes.c_float * (3 * self.S))(*np.concatenate([np.asarray(sc.cyl_pos0, np.float64) for sc in self.scenes]).tolist())
+        self._rot = (ctypes.c_float * (9 * self.S))(*np.concatenate([np.asarray(sc.cyl_rot0, np.float64).reshape(-1) for sc in self.scenes]).tolist())
+        d = _lib.MpmDesc()
+        d.n_grid = sc0.n_grid
+        d.dt = sc0.dt
+        for k in range(3):
+            d.gravity[k] = sc0.gravity[k]
+        d.bound = sc0.bound
+        d.n_particles = self.N
+        d.n_materials = len(mats)
+        d.materials = ctypes.cast(self._mats, ctypes.POINTER(_lib.MpmMaterial))
+        d.n_scenes = self.S
+        d.scene_offsets = ctypes.cast(self._offs, ctypes.POINTER(ctypes.c_int64)) if self.S > 1 else None
+        d.cyl_radius = ctypes.cast(self._rad, ctypes.POINTER(ctypes.c_float))
+        d.cyl_pos0 = ctypes.cast(self._pos, ctypes.POINTER(ctypes.c_float))
+        d.cyl_rot0 = ctypes.cast(self._rot, ctypes.POINTER(ctypes.c_float))
+        d.contact_band = sc0.contact_band
+        d.contact_friction = sc0.contact_friction
+        d.horizon = self.horizon
+        d.ckpt_every = ckpt_every
+        d.requires_grad = 1 if requires_grad else 0
+        self.desc = d
+        self.requires_grad = requires_grad
+        L = _lib.lib()
+        ws = L.mpm_workspace_bytes(ctypes.byref(d))
+        if ws == 0:
+            raise ValueError("invalid scene description")
+        self.ws_bytes = int(ws)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        _lib.check(L.mpm_create(ctypes.byref(d), ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(self.ws_bytes),
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)), "mpm_create")
+        self.ctx = ctx
+        self.buf = torch.zeros(STATE_ROWS, self.N, dtype=torch.float32, device=self.device)
+        self.mat = torch.from_numpy(arrs["mat"].astype(np.uint8)).to(self.device)
+        self._init_arrays = arrs
+        self.actions = torch.zeros(self.horizon, self.S, 6, dtype=torch.float32, device=self.device)
+        acts = np.zeros((self.horizon, self.S, 6))
+        for s, sc in enumerate(self.scenes):
+            acts[: sc.horizon, s] = sc.actions[: self.horizon]
+        self.actions.copy_(torch.from_numpy(acts))
+        self.reset()
+
+    # ---- views -------------------------------------------------------------
+    @property
+    def x(self):
+        return self.buf[0:3]
+
+    @property
+    def v(self):
+        return self.buf[3:6]
+
+    @property
+    def C(self):
+        return self.buf[6:15]
+
+    @property
+    def F(self):
+        return self.buf[15:24]
+
+    @property
+    def J(self):
+        return self.buf[24]
+
+    def state_struct(self, buf: Optional[torch.Tensor] = None, with_mat: bool = True) -> _lib.MpmState:
+        b = self.buf if buf is None else buf
+        return _lib.MpmState(b[0].data_ptr(), b[3].data_ptr(), b[6].data_ptr(), b[15].data_ptr(), b[24].data_ptr(),
+                             self.mat.data_ptr() if with_mat else None)
+
+    # ---- calls -------------------------------------------------------------
+    def load(self, arrs=None):
+        """Copy initial particle arrays (host, float64 from the scene
+        generator) into the device state, FP32."""
+        a = self._init_arrays if arrs is None else arrs
+        N = self.N
+        host = np.empty((STATE_ROWS, N), np.float32)
+        host[0:3] = a["x"].T
+        host[3:6] = a["v"].T
+        host[6:15] = a["C"].reshape(N, 9).T
+        host[15:24] = a["F"].reshape(N, 9).T
+        host[24] = a["J"]
+        self.buf.copy_(torch.from_numpy(host))
+
+    def reset(self, arrs=None):
+        self.load(arrs)
+        self.set_state()
+        self.set_actions(self.actions)
+
+    def set_state(self):
+        self._state = self.state_struct()
+        _lib.check(_lib.lib().mpm_set_state(self.ctx, ctypes.byref(self._state)), "mpm_set_state", self.ctx)
+
+    def set_actions(self, actions: torch.Tensor, t0: int = 0):
+        a = actions.to(self.device, torch.float32).reshape(-1, self.S, 6).contiguous()
+        self._act_keep = a
+        _lib.check(_lib.lib().mpm_set_actions(self.ctx, t0, a.shape[0], ctypes.c_void_p(a.data_ptr())), "mpm_set_actions", self.ctx)
+
+    def step(self, n: int):
+        _lib.check(_lib.lib().mpm_step(self.ctx, int(n)), "mpm_step", self.ctx)
+
+    def clock(self) -> int:
+        t = ctypes.c_int32(0)
+        _lib.check(_lib.lib().mpm_clock(self.ctx, ctypes.byref(t)), "mpm_clock")
+        return t.value
+
+    def backward(self, grad_x: torch.Tensor, grad_v: torch.Tensor, want_grad0: bool = False):
+        """grad_x, grad_v: (3, N) adjoints of the current state.  Returns
+        dL/d(actions) (t, S, 6) and optionally dL/d(state_0) (25, N)."""
+        T = self.clock()
+        gT = torch.zeros(STATE_ROWS, self.N, dtype=torch.float32, device=self.device)
+        gT[0:3] = grad_x
+        gT[3:6] = grad_v
+        gs = self.state_struct(gT, with_mat=False)
+        ga = torch.zeros(T, self.S, 6, dtype=torch.float32, device=self.device)
+        g0 = torch.zeros_like(gT) if want_grad0 else None
+        g0s = self.state_struct(g0, with_mat=False) if want_grad0 else None
+        _lib.check(_lib.lib().mpm_step_backward(self.ctx, ctypes.byref(gs), ctypes.c_void_p(ga.data_ptr()),
+                                                ctypes.byref(g0s) if g0s is not None else None),
+                   "mpm_step_backward", self.ctx)
+        return (ga, g0) if want_grad0 else ga
+
+    def loss_blob(self, mu, sigma: float, want_grad: bool = True):
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        mu_c = (ctypes.c_float * 3)(*[float(m) for m in mu])
+        g = torch.zeros(STATE_ROWS, self.N, dtype=torch.float32, device=self.device) if want_grad else None
+        gs = self.state_struct(g, with_mat=False) if want_grad else None
+        _lib.check(_lib.lib().mpm_loss_blob(self.ctx, mu_c, ctypes.c_float(sigma), ctypes.c_void_p(loss.data_ptr()),
+                                            ctypes.byref(gs) if gs is not None else None), "mpm_loss_blob", self.ctx)
+        return (loss, g) if want_grad else loss
+
+    def positions(self) -> np.ndarray:
+        return self.x.T.double().cpu().numpy()
+
+    def state_numpy(self):
+        b = self.buf.double().cpu().numpy()
+        N = self.N
+        return {"x": b[0:3].T.copy(), "v": b[3:6].T.copy(), "C": b[6:15].T.reshape(N, 3, 3).copy(),
+                "F": b[15:24].T.reshape(N, 3, 3).copy(), "J": b[24].copy()}
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            _lib.lib().mpm_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MpmRollout(torch.autograd.Function):
+    """actions (T, S, 6) -> (x_T, v_T) each (3, N); the backward runs the
+    hand-written adjoint with checkpoint recompute (mpm_step_backward)."""
+
+    @staticmethod
+    def forward(ctx, actions: torch.Tensor, sim: Simulator):
+        if not sim.requires_grad:
+            raise ValueError("MpmRollout needs a Simulator created with requires_grad=True")
+        sim.load()
+        sim.set_state()
+        sim.set_actions(actions.detach())
+        sim.step(actions.shape[0])
+        ctx.sim = sim
+        return sim.x.clone(), sim.v.clone()
+
+    @staticmethod
+    def backward(ctx, gx, gv):
+        sim = ctx.sim
+        gx = torch.zeros(3, sim.N, device=sim.device) if gx is None else gx.contiguous()
+        gv = torch.zeros(3, sim.N, device=sim.device) if gv is None else gv.contiguous()
+        ga = sim.backward(gx, gv)
+        return ga, None
+
+
+class BlobLoss(torch.autograd.Function):
+    """Blob loss of the simulator's current state (HIP kernel), with dL/dx."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, sim: Simulator, mu, sigma: float):
+        loss, g = sim.loss_blob(mu, sigma, want_grad=True)
+        ctx.save_for_backward(g[0:3].clone())
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, gl):
+        (gx,) = ctx.saved_tensors
+        return gl * gx, None, None, None

@@ -1,0 +1,191 @@
+"""GPU parity: the HIP step (through the C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Tolerance (positions after 100 steps): ||X_gpu - X_ref||_F / ||X_ref||_F
+<= 1e-4, the relative tolerance the build targets for the FP32 step with
+FP64 SVD/polar.  Gradients: ||g_gpu - g_ref|| / ||g_ref||.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mpm_oracle as O
+from paper_2303_02346_amd import scenes
+from paper_2303_02346_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def sim_of(sc, **kw):
+    from paper_2303_02346_amd.sim import Simulator
+    return Simulator(sc, **kw)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def oracle_state(sc, steps):
+    st = O.rollout(sc, steps=steps)
+    return {k: v.detach().numpy() for k, v in st.items()}
+
+
+def compare_states(gpu, ref, liquid, tol_x=1e-5, tol=1e-3):
+    ex = rel(gpu["x"], ref["x"])
+    ev = rel(gpu["v"], ref["v"])
+    eC = rel(gpu["C"], ref["C"])
+    solid = ~liquid
+    eF = rel(gpu["F"][solid], ref["F"][solid]) if solid.any() else 0.0
+    eJ = rel(gpu["J"][liquid], ref["J"][liquid]) if liquid.any() else 0.0
+    say(f"  rel err x {ex:.2e} v {ev:.2e} C {eC:.2e} F {eF:.2e} J {eJ:.2e}")
+    assert ex <= tol_x
+    assert ev <= tol and eC <= tol and eF <= tol_x * 10 and eJ <= tol_x * 10
+
+
+def liquid_mask(sc):
+    kinds = np.array([m.kind for m in sc.materials])
+    return kinds[sc.mat] == scenes.LIQUID
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_one_step_all_materials(seed):
+    sc = scenes.tiny(n_particles=300, n_grid=24, steps=1, seed=seed)
+    say(f"tiny one step seed {seed}")
+    sim = sim_of(sc)
+    sim.step(1)
+    compare_states(sim.state_numpy(), oracle_state(sc, 1), liquid_mask(sc), tol_x=1e-6, tol=1e-4)
+
+
+def test_tiny_many_steps_with_contact():
+    sc = scenes.tiny(n_particles=600, n_grid=32, steps=60, seed=4, dt=1e-4)
+    say("tiny 60 steps")
+    sim = sim_of(sc)
+    sim.step(60)
+    compare_states(sim.state_numpy(), oracle_state(sc, 60), liquid_mask(sc), tol_x=1e-5, tol=2e-3)
+
+
+def test_config1_free_fall_100_steps():
+    sc = scenes.config1()
+    say("config 1, 100 steps")
+    sim = sim_of(sc)
+    sim.step(100)
+    g = sim.state_numpy()
+    x0 = sc.x
+    dy = -9.8 * sc.dt ** 2 * 100 * 101 / 2
+    assert np.abs(g["x"][:, 1] - x0[:, 1] - dy).max() < 2e-6
+    ref = oracle_state(sc, 100)
+    e = rel(g["x"], ref["x"])
+    say(f"  config 1 rel err {e:.2e}")
+    assert e <= 1e-4
+
+
+def test_config1b_affine_100_steps():
+    sc = scenes.config1(affine=True)
+    say("config 1b (affine velocity), 100 steps")
+    sim = sim_of(sc)
+    sim.step(100)
+    g = sim.state_numpy()
+    ref = oracle_state(sc, 100)
+    e = rel(g["x"], ref["x"])
+    eF = rel(g["F"], ref["F"])
+    say(f"  config 1b rel err x {e:.2e} F {eF:.2e}")
+    assert e <= 1e-4 and eF <= 1e-3
+
+
+def test_config2_full_size_first_steps():
+    """Config 2 at its full size (250k particles, 128^3) in the launch
+    configuration the benchmark times, 3 steps against the oracle."""
+    sc = scenes.config2()
+    say("config 2 full size, 3 steps")
+    sim = sim_of(sc)
+    sim.step(3)
+    g = sim.state_numpy()
+    ref = oracle_state(sc, 3)
+    compare_states(g, ref, liquid_mask(sc), tol_x=1e-6, tol=1e-3)
+
+
+def test_config2_full_horizon_invariants():
+    """200 steps of config 2: finite state inside the domain; the sand box,
+    which neither the cylinder nor the walls reach in 10 ms, keeps its
+    momentum balance: its mean displacement is the free-fall value
+    g dt^2 n(n+1)/2 (stresses carry no net force through APIC)."""
+    sc = scenes.config2()
+    say("config 2 full size, 200 steps")
+    sim = sim_of(sc)
+    sim.step(200)
+    g = sim.state_numpy()
+    assert np.isfinite(g["x"]).all() and np.isfinite(g["v"]).all()
+    assert (g["x"] > 0).all() and (g["x"] < 1).all()
+    sand = ~liquid_mask(sc)
+    dy = (g["x"][sand, 1] - sc.x[sand, 1]).mean()
+    ref = -9.8 * sc.dt ** 2 * 200 * 201 / 2
+    say(f"  sand mean dy {dy:.6e} free fall {ref:.6e}")
+    assert abs(dy - ref) <= 2e-3 * abs(ref)
+
+
+def test_domain_error_is_reported():
+    sc = scenes.tiny(n_particles=50, n_grid=16, steps=2)
+    sc.x[3] = [0.01, 0.5, 0.5]          # stencil leaves the grid
+    say("domain error")
+    sim = sim_of(sc)
+    with pytest.raises(_lib.MpmError) as e:
+        sim.step(1)
+    assert e.value.status == _lib.MPM_EDOMAIN and e.value.bits & 1
+
+
+def test_nonfinite_error_is_reported():
+    sc = scenes.tiny(n_particles=50, n_grid=16, steps=2)
+    sc.v[5] = [np.nan, 0.0, 0.0]
+    say("non-finite error")
+    sim = sim_of(sc)
+    with pytest.raises(_lib.MpmError) as e:
+        sim.step(2)
+    assert e.value.status == _lib.MPM_EDOMAIN
+
+
+# ---------------------------------------------------------------------------
+# gradients
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_tiny_vs_oracle(seed):
+    sc = scenes.tiny(n_particles=90, n_grid=16, steps=8, seed=seed)
+    say(f"gradient tiny seed {seed}")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=3)
+    sim.step(sc.horizon)
+    loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
+    ga = sim.backward(g[0:3], torch.zeros_like(g[0:3]))[:, 0].double().cpu().numpy()
+    L, gref = O.loss_and_action_grad(sc)
+    gref = gref.numpy()
+    e = rel(ga, gref)
+    say(f"  loss gpu {loss.item():.8f} ref {L.item():.8f}; grad rel err {e:.2e}")
+    assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
+    assert e <= 1e-4
+
+
+def test_gradient_state0_vs_oracle():
+    """dL/dx_0 and dL/dv_0 through the full adjoint (P2G/G2P weights,
+    stresses, contact) against oracle autograd."""
+    sc = scenes.tiny(n_particles=90, n_grid=16, steps=5, seed=2)
+    say("gradient wrt initial state")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=2)
+    sim.step(sc.horizon)
+    loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
+    ga, g0 = sim.backward(g[0:3], torch.zeros_like(g[0:3]), want_grad0=True)
+    p = O.params_from_scene(sc)
+    st0 = O.state_from_scene(sc, requires_grad=True)
+    st = O.rollout(sc, state=st0, params=p)
+    L = O.blob_loss(st["x"], p.kind == O.LIQUID, torch.tensor(sc.target_mu, dtype=torch.float64), sc.target_sigma)
+    L.backward()
+    gx = g0[0:3].T.double().cpu().numpy()
+    gv = g0[3:6].T.double().cpu().numpy()
+    ex = rel(gx, st0["x"].grad.numpy())
+    ev = rel(gv, st0["v"].grad.numpy())
+    say(f"  dL/dx0 rel {ex:.2e} dL/dv0 rel {ev:.2e}")
+    assert ex <= 1e-4 and ev <= 1e-4
