@@ -1,0 +1,166 @@
+#!/usr/bin/env python
+"""Benchmark of the MLS-MPM step on one MI355X.
+
+Workload: the two-material scene of 250k particles (125k weakly compressible
+viscous liquid, 125k Drucker-Prager sand) on a 128^3 grid, dt = 5e-5, with a
+kinematic cylinder driven by a smooth 6-DoF velocity trajectory.  One step is
+one MLS-MPM substep (P2G with stress, grid update with gravity, walls and
+soft contact, G2P with F/J update and plastic projection).
+
+Prints one JSON line: forward particle-steps/s as ``value``, the
+forward+backward rate (checkpointed adjoint, blob loss) in ``fwd_bwd``, the
+dominant kernel against the HBM roofline in ``roofline``, and the FP64 CPU
+oracle timed on a bounded sample in ``cpu_baseline``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MPM particle-steps/s fwd and fwd+bwd, 250k particles 128^3 grid; % HBM roofline"
+
+# Algorithmic bytes per unit, FP32 SoA state read once and written once.
+BYTES_SOLID = 193      # x v C F read + write (96 + 96) + 1 B material tag
+BYTES_LIQUID = 129     # x v C J read + write (64 + 64) + 1 B tag
+BYTES_NODE = 56        # active node: P2G write m,mv 16; grid read 16, write v 12; G2P read 12
+# per-kernel algorithmic bytes: (bytes per solid particle, per liquid particle, per active node)
+KERNEL_BYTES = {
+    "k_p2g_plain": (97, 65, 16),      # read x v C F|J + tag; write m, mv
+    "k_g2p2g": (193, 129, 28),        # read + write the particle state; write m,mv and read v per node
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def active_nodes(x, n):
+    import numpy as np
+    base = np.floor(x * n - 0.5).astype(np.int64)
+    offs = np.array([[i, j, k] for i in range(3) for j in range(3) for k in range(3)])
+    idx = base[:, None, :] + offs[None]
+    lin = (idx[..., 0] * n + idx[..., 1]) * n + idx[..., 2]
+    return int(np.unique(lin.reshape(-1)).size)
+
+
+def cpu_baseline(sc, steps):
+    import torch
+    from oracle import mpm_oracle as O
+    p = O.params_from_scene(sc)
+    st = O.state_from_scene(sc)
+    t0 = time.perf_counter()
+    O.rollout(sc, state=st, steps=steps, params=p)
+    dt = time.perf_counter() - t0
+    return {"value": sc.n * steps / dt, "unit": "particle-steps/s", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": f"config-2 scene (250k particles, 128^3), first {steps} steps, FP64 torch-CPU",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--bwd-steps", type=int, default=64)
+    ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--particles", type=int, default=250_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2303_02346_amd import scenes
+    from paper_2303_02346_amd.sim import Simulator
+
+    sc = scenes.config2(n_particles=args.particles, steps=max(args.steps, args.warmup, args.bwd_steps))
+    N = sc.n
+    kinds = np.array([m.kind for m in sc.materials])[sc.mat]
+    n_liq = int((kinds == scenes.LIQUID).sum())
+    n_sol = N - n_liq
+    n_act = active_nodes(sc.x, sc.n_grid)
+
+    log(f"[bench] forward: {N} particles, {args.warmup} warmup + {args.steps} timed steps")
+    sim = Simulator(sc, requires_grad=False, horizon=max(args.steps, args.warmup))
+    sim.reset()
+    sim.step(args.warmup)
+    sim.reset()
+    torch.cuda.synchronize()
+    sim.timing(True)
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    k_ms, k_launches, k_name = sim.timing_read()
+    sim.timing(False)
+    fwd_rate = N * args.steps / t_fwd
+    log(f"[bench] forward {t_fwd * 1e3 / args.steps:.3f} ms/step, {fwd_rate:.3e} particle-steps/s; "
+        f"{k_name} avg {k_ms / max(k_launches, 1) * 1e3:.1f} us over {k_launches} launches")
+
+    per = KERNEL_BYTES.get(k_name)
+    roof = None
+    if per is not None and k_launches > 0:
+        bytes_launch = per[0] * n_sol + per[1] * n_liq + per[2] * n_act
+        avg_s = k_ms / k_launches * 1e-3
+        ach = bytes_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": k_name,
+                "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_launch)}
+    step_bytes = BYTES_SOLID * n_sol + BYTES_LIQUID * n_liq + BYTES_NODE * n_act
+    step_frac = step_bytes / (t_fwd / args.steps) / 1e9 / HBM_PEAK_GBS
+
+    fwd_bwd = None
+    if not args.no_bwd:
+        T = args.bwd_steps
+        log(f"[bench] forward+backward: {T} steps, checkpoint every 16")
+        simg = Simulator(sc, requires_grad=True, ckpt_every=16, horizon=T)
+        for rep in range(2):
+            simg.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            simg.step(T)
+            loss, g = simg.loss_blob(sc.target_mu, sc.target_sigma)
+            ga = simg.backward(g[0:3], torch.zeros_like(g[0:3]))
+            torch.cuda.synchronize()
+            t_fb = time.perf_counter() - t0
+        fb_bytes = 680.0 * N * T
+        fwd_bwd = {"value": N * T / t_fb, "unit": "particle-steps/s", "steps": T, "ckpt_every": 16,
+                   "ms_per_step": t_fb * 1e3 / T, "loss": float(loss.item()),
+                   "grad_norm": float(ga.norm().item()),
+                   "hbm_frac_algorithmic": round(fb_bytes / t_fb / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] fwd+bwd {t_fb * 1e3 / T:.3f} ms/step, {N * T / t_fb:.3e} particle-steps/s")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle sample: {args.cpu_steps} steps")
+        cpu = cpu_baseline(sc, args.cpu_steps)
+        log(f"[bench] CPU oracle {cpu['value']:.3e} particle-steps/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": fwd_rate, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_fwd * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (FP64 SVD/polar)", "data": "synthetic",
+        "config": {"workload": "config 2: 250k particles (125k liquid + 125k Drucker-Prager sand) in two seeded boxes, "
+                               "128^3 grid, dt=5e-5, kinematic cylinder r=0.05 with seeded smooth 6-DoF trajectory",
+                   "n_particles": N, "n_grid": sc.n_grid, "dt": sc.dt, "active_nodes": n_act},
+        "step_hbm_frac_algorithmic": round(step_frac, 4),
+        "fwd_bwd": fwd_bwd,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,14 @@ int mpm_clock(const mpm_ctx* c, int32_t* t_out);
 /* Error bits (MPM_ERR_*) seen by the last call that returned MPM_EDOMAIN. */
 int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out);
 
+/* Measurement: when enabled, every launch of the step's dominant kernel
+ * (the particle kernel that carries the transfer traffic) is bracketed by
+ * HIP events on the context's stream; elapsed times are summed when a call
+ * synchronises.  mpm_timing_read returns the accumulated time, the number of
+ * timed launches and the kernel's name, and resets the counters. */
+int mpm_timing_enable(mpm_ctx* c, int32_t enable);
+int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name, int32_t name_len);
+
 /* Free the host context (not the borrowed device memory). */
 int mpm_destroy(mpm_ctx* c);
 

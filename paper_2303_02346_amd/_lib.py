@@ -32,8 +32,8 @@ class MpmDesc(ctypes.Structure):
 
 
 EXPORTS = ["mpm_workspace_bytes", "mpm_create", "mpm_set_state", "mpm_set_actions", "mpm_step",
-           "mpm_step_backward", "mpm_loss_blob", "mpm_clock", "mpm_last_error_bits", "mpm_destroy",
-           "mpm_strerror"]
+           "mpm_step_backward", "mpm_loss_blob", "mpm_clock", "mpm_last_error_bits", "mpm_timing_enable",
+           "mpm_timing_read", "mpm_destroy", "mpm_strerror"]
 
 _lib = None
 
@@ -64,6 +64,8 @@ def lib():
     L.mpm_loss_blob.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_float, vp, ctypes.POINTER(MpmState)]
     L.mpm_clock.argtypes = [vp, ctypes.POINTER(i32)]
     L.mpm_last_error_bits.argtypes = [vp, ctypes.POINTER(i32)]
+    L.mpm_timing_enable.argtypes = [vp, i32]
+    L.mpm_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p, i32]
     L.mpm_destroy.argtypes = [vp]
     L.mpm_strerror.argtypes = [ctypes.c_int]
     L.mpm_strerror.restype = ctypes.c_char_p

@@ -95,6 +95,7 @@ struct mpm_ctx {
   int last_err_bits;
   size_t state_bytes;
   FastPath fast;
+  KernelTimer timer;
 };
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_EHIP; }
@@ -134,6 +135,7 @@ static int finish(mpm_ctx* c) {
   if (hipMemcpyAsync(&host, err, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return MPM_EHIP;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return MPM_EHIP;
   if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+  c->timer.collect();
   if (host) {
     c->last_err_bits = host;
     if (hipMemsetAsync(err, 0, sizeof(int), c->stream) != hipSuccess) return MPM_EHIP;
@@ -166,6 +168,7 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   c->t = 0;
   c->last_err_bits = 0;
   c->state_bytes = align_up(STATE_FLOATS * (size_t)d->n_particles * sizeof(float));
+  c->timer.name = "k_p2g_plain";
   int S = d->n_scenes;
   c->mats.resize(256);
   memset(c->mats.data(), 0, 256 * sizeof(MatDev));
@@ -249,7 +252,9 @@ static const float* act_at(mpm_ctx* c, int t) {
 static void plain_step(mpm_ctx* c, const StepParams& P, const PState& in, const PState& out, int t) {
   size_t nodes = (size_t)c->d.n_grid * c->d.n_grid * c->d.n_grid * c->d.n_scenes;
   launch_zero(G(c, c->L.mmv), nodes * sizeof(float4), c->stream);
+  c->timer.begin(c->stream);
   launch_p2g_plain(in, P, G(c, c->L.mmv), c->stream);
+  c->timer.end(c->stream);
   launch_grid_plain(P, G(c, c->L.mmv), G(c, c->L.vgrid), pose_at(c, t), act_at(c, t), c->stream);
   launch_g2p_plain(in, out, P, G(c, c->L.vgrid), c->stream);
 }
@@ -276,7 +281,7 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
       plain_step(c, P, us, us, t);
     }
   } else {
-    int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream);
+    int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
     if (rc != MPM_OK) return rc;
   }
   c->t += n_steps;
@@ -366,8 +371,31 @@ int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out) {
   return MPM_OK;
 }
 
+int mpm_timing_enable(mpm_ctx* c, int32_t enable) {
+  if (!c) return MPM_EINVAL;
+  c->timer.on = enable != 0;
+  c->timer.total_ms = 0.0;
+  c->timer.launches = 0;
+  c->timer.used = 0;
+  return MPM_OK;
+}
+
+int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name, int32_t name_len) {
+  if (!c || !total_ms || !launches) return MPM_EINVAL;
+  *total_ms = c->timer.total_ms;
+  *launches = c->timer.launches;
+  if (name && name_len > 0) {
+    strncpy(name, c->timer.name, name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  c->timer.total_ms = 0.0;
+  c->timer.launches = 0;
+  return MPM_OK;
+}
+
 int mpm_destroy(mpm_ctx* c) {
   if (!c) return MPM_EINVAL;
+  c->timer.destroy();
   fast_destroy(c->fast);
   delete c;
   return MPM_OK;

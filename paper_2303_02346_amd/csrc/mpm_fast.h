@@ -18,7 +18,7 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
 void fast_bind_grid(FastPath& f, float4* mmv, float4* vgrid);
 void fast_invalidate(FastPath& f);
 int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n, const double* pose, const float* act,
-             hipStream_t s);
+             hipStream_t s, KernelTimer* timer);
 void fast_destroy(FastPath& f);
 
 }  // namespace mpm

@@ -15,11 +15,13 @@ void fast_invalidate(FastPath& f) { f.valid = false; }
 void fast_destroy(FastPath&) {}
 
 int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n, const double* pose, const float* act,
-             hipStream_t s) {
+             hipStream_t s, KernelTimer* timer) {
   size_t nodes = (size_t)f.n_grid * f.n_grid * f.n_grid * f.n_scenes;
   for (int t = t0; t < t0 + n; t++) {
     launch_zero(f.mmv, nodes * sizeof(float4), s);
+    timer->begin(s);
     launch_p2g_plain(user, P, f.mmv, s);
+    timer->end(s);
     launch_grid_plain(P, f.mmv, f.vgrid, pose + (size_t)t * f.n_scenes * POSE_DOUBLES, act + (size_t)t * f.n_scenes * 6, s);
     launch_g2p_plain(user, user, P, f.vgrid, s);
   }

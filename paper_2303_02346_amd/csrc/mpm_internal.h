@@ -59,6 +59,43 @@ constexpr int POSE_DOUBLES = 12;
 // u (3), w (3), c (3), axis a = R e_y (3).
 constexpr int ACC_DOUBLES = 12;
 
+// Optional per-launch timing of one kernel with HIP events on its stream.
+struct KernelTimer {
+  bool on = false;
+  const char* name = "";
+  hipEvent_t ev[2 * 4096];
+  int created = 0;
+  int used = 0;
+  double total_ms = 0.0;
+  long long launches = 0;
+  void begin(hipStream_t s) {
+    if (!on || used >= 4096) return;
+    if (used >= created) {
+      hipEventCreate(&ev[2 * used]);
+      hipEventCreate(&ev[2 * used + 1]);
+      created = used + 1;
+    }
+    hipEventRecord(ev[2 * used], s);
+  }
+  void end(hipStream_t s) {
+    if (!on || used >= 4096) return;
+    hipEventRecord(ev[2 * used + 1], s);
+    used++;
+  }
+  // after the stream has been synchronised
+  void collect() {
+    for (int i = 0; i < used; i++) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) { total_ms += ms; launches++; }
+    }
+    used = 0;
+  }
+  void destroy() {
+    for (int i = 0; i < created; i++) { hipEventDestroy(ev[2 * i]); hipEventDestroy(ev[2 * i + 1]); }
+    created = 0;
+  }
+};
+
 // ---- launch wrappers (mpm_kernels.hip) ----
 void launch_pose(int n_scenes, int t0, int n, float dt, const float* act, double* pose, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -185,6 +185,17 @@ class Simulator:
                                             ctypes.byref(gs) if gs is not None else None), "mpm_loss_blob", self.ctx)
         return (loss, g) if want_grad else loss
 
+    def timing(self, enable: bool):
+        _lib.check(_lib.lib().mpm_timing_enable(self.ctx, 1 if enable else 0), "mpm_timing_enable")
+
+    def timing_read(self):
+        """(total ms, launches, kernel name) of the timed kernel since the last read."""
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        name = ctypes.create_string_buffer(64)
+        _lib.check(_lib.lib().mpm_timing_read(self.ctx, ctypes.byref(ms), ctypes.byref(n), name, 64), "mpm_timing_read")
+        return ms.value, n.value, name.value.decode()
+
     def positions(self) -> np.ndarray:
         return self.x.T.double().cpu().numpy()
 
