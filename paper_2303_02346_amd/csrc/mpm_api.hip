@@ -270,6 +270,7 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
   const int N = c->d.n_particles;
   PState us = user_pstate(&c->user, N);
   launch_pose(c->d.n_scenes, c->t, n_steps, c->d.dt, (const float*)(c->ws + c->L.act), (double*)(c->ws + c->L.pose), c->stream);
+  c->timer.name = c->d.requires_grad ? "k_p2g_plain" : "k_g2p2g";
   if (c->d.requires_grad) {
     // plain path, recording checkpoints every k steps
     int k = c->d.ckpt_every;
