@@ -22,7 +22,6 @@ constexpr int TILE = 10;                     // P2G tile edge (nodes): block +-2
 constexpr int TILE_NODES = TILE * TILE * TILE;
 constexpr int VT = 8;                        // G2P velocity tile edge
 constexpr int VT_NODES = VT * VT * VT;
-constexpr int NSUB = 64;                     // active-block sub-lists (spread append atomics)
 
 // Particle buffer: packed state (25 rows of N floats) plus bookkeeping.
 struct PBuf {
@@ -40,15 +39,15 @@ struct FastPath {
   PBuf buf[2];
   uint32_t *key_tmp, *rank_tmp;
   uint32_t *counts, *offsets;
-  int4* list[2];
-  uint32_t* list_n;        // [2]
-  uint32_t* active[2];     // NSUB sub-lists of n_keys entries each
-  uint32_t* active_n;      // [2][NSUB]
-  uint32_t* active_stamp;
+  int4* list[3];           // occupied-block lists (rotating)
+  uint32_t* list_n;        // [3]
+  uint32_t* claim;         // per-block stamp: which step last updated the block
+  uint32_t* won;           // per list entry: mask of the neighbour blocks it claimed
   int2* tile_box;          // {packed lo/hi, stamp}
   float* tiles;            // n_keys x 4 x TILE_NODES
   float4* vgrid;           // n_keys x 64
-  uint32_t* gen;           // device step stamp
+  uint32_t* gen;           // device per-call epoch of the step stamps
+  unsigned long long calls;
   int grid_wgs, part_wgs;
   // plain dense grid (shared with the adjoint path), unused here
   float4* mmv;

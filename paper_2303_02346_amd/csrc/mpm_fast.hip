@@ -10,9 +10,11 @@
 //                       written to its slot in the other buffer, which is
 //                       sorted by the block key of the previous position, and
 //                       the key of its new position is counted.
-//   k_grid              one wavefront per active block: sum the overlapping
-//                       tiles of the 27 neighbouring blocks, then normalise,
-//                       gravity, soft cylinder contact, slip walls.
+//                       The blocks a tile touches are claimed (first entry
+//                       wins) and recorded per entry.
+//   k_grid              per occupied-block entry, its claimed blocks: sum
+//                       the overlapping tiles of the 27 neighbouring blocks,
+//                       then normalise, gravity, soft cylinder contact, walls.
 //   k_scan              exclusive scan of the key counts -> destination
 //                       offsets and the list of occupied blocks.
 // The particle order therefore lags the positions by one step: a particle's
@@ -57,6 +59,37 @@ __device__ inline void key_decode(const FastGeom& g, uint32_t key, int& s, int& 
   by = (int)compact3(m >> 1);
   bz = (int)compact3(m);
 }
+
+// Rank of each lane's key among equal keys of the wavefront, in two phases
+// so that the global atomic's latency overlaps other work: rank_issue groups
+// the lanes by key (ballots only) and lets one leader lane per distinct key
+// reserve the group's range; rank_finish broadcasts the leader's base.
+// Every lane of the wave must call both.
+struct WaveRank {
+  int leader;
+  uint32_t prefix;
+  uint32_t lbase;
+};
+__device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid) {
+  const int lane = __lane_id();
+  unsigned long long pending = __ballot(valid);
+  WaveRank R;
+  R.leader = lane;
+  R.prefix = 0;
+  R.lbase = 0;
+  uint32_t lcount = 0;
+  while (pending) {
+    int leader = __ffsll((long long)pending) - 1;
+    uint32_t k = __shfl(key, leader);
+    unsigned long long m = __ballot(valid && key == k) & pending;
+    if ((m >> lane) & 1ull) { R.leader = leader; R.prefix = (uint32_t)__popcll(m & ((1ull << lane) - 1ull)); }
+    if (lane == leader) lcount = (uint32_t)__popcll(m);
+    pending &= ~m;
+  }
+  if (lcount > 0) R.lbase = atomicAdd(&counts[key], lcount);
+  return R;
+}
+__device__ inline uint32_t rank_finish(const WaveRank& R) { return __shfl(R.lbase, R.leader) + R.prefix; }
 
 // Rank of each lane's key among equal keys, with one global atomic per
 // distinct key of the wavefront.  Every lane of the wave must call it.
@@ -108,29 +141,41 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
   if (has) { key_tmp[p] = key; rank_tmp[p] = r; }
 }
 
-// exclusive scan of counts -> offsets, compact list of occupied keys, zero
-// counts; resets the NSUB active-list counters the next step appends to and
-// advances the step stamp.  One workgroup; each thread owns a contiguous
-// range of keys read and written with 16-byte vector accesses.
-__global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
-                                               int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
-                                               uint32_t* __restrict__ active_n_reset, uint32_t* __restrict__ gen) {
-  __shared__ uint32_t s_sum[1024], s_nz[1024];
+// Exclusive scan of counts -> offsets, compact list of occupied keys, and
+// zero the counts.  Run by one workgroup of NT threads; each thread owns a
+// contiguous range of keys, loaded as independent 16-byte loads.
+template <int NT>
+__device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, int4* __restrict__ list,
+                          uint32_t* __restrict__ list_n, int n_keys) {
+  constexpr int NW = NT / 64;
+  __shared__ uint32_t s_sum[NW], s_nz[NW];
   const int t = threadIdx.x;
-  const int per = ((n_keys + 1023) / 1024 + 3) & ~3;       // multiple of 4
+  const int per = ((n_keys + NT - 1) / NT + 3) & ~3;       // multiple of 4
   const int k0 = t * per;
+  // batches of 32 keys as 8 independent 16-byte loads
+  auto load_batch = [&](int b, uint4* v) {
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int k = k0 + b + 4 * u;
+      if (b + 4 * u < per && k + 3 < n_keys) v[u] = *(const uint4*)(counts + k);
+      else {
+        v[u].x = (b + 4 * u < per && k < n_keys) ? counts[k] : 0u;
+        v[u].y = (b + 4 * u < per && k + 1 < n_keys) ? counts[k + 1] : 0u;
+        v[u].z = (b + 4 * u < per && k + 2 < n_keys) ? counts[k + 2] : 0u;
+        v[u].w = 0u;
+      }
+    }
+  };
+  uint4 v0[8];
+  load_batch(0, v0);
   uint32_t sum = 0, nz = 0;
   for (int b = 0; b < per; b += 32) {
     uint4 v[8];
+    if (b == 0) {
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-      int k = k0 + b + 4 * u;
-      v[u] = (b + 4 * u < per && k + 3 < n_keys) ? *(const uint4*)(counts + k) : make_uint4(0, 0, 0, 0);
-      if (b + 4 * u < per && k < n_keys && k + 3 >= n_keys) {
-        v[u].x = counts[k];
-        v[u].y = k + 1 < n_keys ? counts[k + 1] : 0;
-        v[u].z = k + 2 < n_keys ? counts[k + 2] : 0;
-      }
+      for (int u = 0; u < 8; u++) v[u] = v0[u];
+    } else {
+      load_batch(b, v);
     }
 #pragma unroll
     for (int u = 0; u < 8; u++) {
@@ -138,53 +183,65 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, ui
       nz += (v[u].x > 0) + (v[u].y > 0) + (v[u].z > 0) + (v[u].w > 0);
     }
   }
-  s_sum[t] = sum;
-  s_nz[t] = nz;
+  // inclusive scan within the wavefront, then across the wavefronts
+  const int lane = t & 63, wv = t >> 6;
+  uint32_t is = sum, inz = nz;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t o = __shfl_up(is, off), o2 = __shfl_up(inz, off);
+    if (lane >= off) { is += o; inz += o2; }
+  }
+  if (lane == 63) { s_sum[wv] = is; s_nz[wv] = inz; }
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t a = (t >= off) ? s_sum[t - off] : 0, b = (t >= off) ? s_nz[t - off] : 0;
-    __syncthreads();
-    s_sum[t] += a;
-    s_nz[t] += b;
-    __syncthreads();
+  uint32_t woff = 0, wnz = 0, totnz = 0;
+#pragma unroll
+  for (int q = 0; q < NW; q++) {
+    if (q < wv) { woff += s_sum[q]; wnz += s_nz[q]; }
+    totnz += s_nz[q];
   }
-  uint32_t run = s_sum[t] - sum, li = s_nz[t] - nz;
-  for (int b = 0; b < per; b += 4) {
-    int k = k0 + b;
-    if (k >= n_keys) break;
-    uint32_t c[4], o[4];
-    bool full = k + 3 < n_keys;
-    if (full) { uint4 v = *(const uint4*)(counts + k); c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w; }
-    else {
+  uint32_t run = woff + is - sum, li = wnz + inz - nz;
+  for (int b = 0; b < per; b += 32) {
+    uint4 v[8];
+    if (b == 0) {
 #pragma unroll
-      for (int u = 0; u < 4; u++) c[u] = (k + u < n_keys) ? counts[k + u] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      o[u] = run;
-      if (c[u] > 0) { list[li] = make_int4(k + u, (int)run, (int)c[u], 0); li++; }
-      run += c[u];
-    }
-    if (full) {
-      *(uint4*)(offsets + k) = make_uint4(o[0], o[1], o[2], o[3]);
-      *(uint4*)(counts + k) = make_uint4(0, 0, 0, 0);
+      for (int u = 0; u < 8; u++) v[u] = v0[u];
     } else {
+      load_batch(b, v);
+    }
 #pragma unroll
-      for (int u = 0; u < 4; u++)
-        if (k + u < n_keys) { offsets[k + u] = o[u]; counts[k + u] = 0; }
+    for (int u = 0; u < 8; u++) {
+      const int k = k0 + b + 4 * u;
+      if (b + 4 * u >= per || k >= n_keys) break;
+      const uint32_t c[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+      uint32_t o[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        o[q] = run;
+        if (c[q] > 0) { list[li] = make_int4(k + q, (int)run, (int)c[q], 0); li++; }
+        run += c[q];
+      }
+      if (k + 3 < n_keys) {
+        *(uint4*)(offsets + k) = make_uint4(o[0], o[1], o[2], o[3]);
+        *(uint4*)(counts + k) = make_uint4(0, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          if (k + q < n_keys) { offsets[k + q] = o[q]; counts[k + q] = 0; }
+      }
     }
   }
-  if (t < NSUB && active_n_reset) active_n_reset[t] = 0;
-  if (t == 1023) {
-    list_n[0] = s_nz[1023];
-    if (gen) gen[0] = gen[0] + 1;
-  }
+  if (t == NT - 1) list_n[0] = totnz;
 }
 
-__global__ void k_bookkeep(uint32_t* active_n_reset, uint32_t* gen) {
-  if (threadIdx.x < NSUB) active_n_reset[threadIdx.x] = 0;
-  if (threadIdx.x == 0) gen[0] = gen[0] + 1;
+// the import's scan; also advances the per-call epoch of the step stamps
+__global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
+                                               int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
+                                               uint32_t* __restrict__ epoch) {
+  scan_keys<1024>(counts, offsets, list, list_n, n_keys);
+  if (threadIdx.x == 0) epoch[0] = epoch[0] + 1;
 }
+
+
 
 // scatter the user-order particles to their sorted slots
 __global__ __launch_bounds__(256) void k_permute(PState u, const uint8_t* __restrict__ umat, PBuf X,
@@ -241,11 +298,11 @@ struct PartArgs {
   uint32_t* counts;            // histogram of the new keys
   float* tiles;
   int2* tile_box;
-  uint32_t* active_stamp;
-  uint32_t* active;            // active sub-lists appended this step: NSUB x n_keys
-  uint32_t* active_n;          // NSUB counters
   int n_keys;
-  const uint32_t* gen;
+  uint32_t* claim;             // per-block stamp of the step that claimed it
+  uint32_t* won;               // per entry: mask of the 27 neighbours it claimed
+  const uint32_t* gen;         // per-call epoch
+  uint32_t step_id;            // 1-based step within the call
   const float4* vgrid;
 };
 
@@ -260,7 +317,8 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
   const int tid = threadIdx.x;
   const int N = A.N;
   const uint32_t n_list = A.list_n[0];
-  const uint32_t stamp = A.gen[0];
+  // step stamp: per-call epoch (advanced by the import) and step within the call
+  const uint32_t stamp = (A.gen[0] << 16) | A.step_id;
   for (uint32_t e = blockIdx.x; e < n_list; e += gridDim.x) {
     const int4 ent = A.list[e];
     int sc, bx, by, bz;
@@ -461,6 +519,10 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
             counted = true;
           }
         }
+        // reserve this particle's rank under its new key now; the result is
+        // consumed after the scatter, so the atomic's latency is hidden
+        WaveRank WR = {0, 0, 0};
+        if (MODE == MODE_FUSED) WR = rank_issue(A.counts, nkey, counted && has);
         // chunk-wide bound sums and box (wave shuffles, then 4 waves in LDS)
         int clo[3], chi[3];
 #pragma unroll
@@ -541,7 +603,7 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
         }
         __syncthreads();
         if (MODE == MODE_FUSED) {
-          uint32_t r = wave_rank(A.counts, nkey, counted && has);
+          uint32_t r = rank_finish(WR);
           if (has && dst < (uint32_t)N) { A.out.key[dst] = nkey; A.out.rank[dst] = counted ? r : 0u; }
           // a particle that could not be counted keeps a valid (key 0) slot
           if (has && !counted && dst < (uint32_t)N) {
@@ -572,24 +634,23 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
           int packed = lo0 | (lo1 << 4) | (lo2 << 8) | (hi0 << 12) | (hi1 << 16) | (hi2 << 20);
           A.tile_box[bkey] = make_int2(packed, (int)stamp);
         }
-        if (tid < 27) {
-          int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
-          int nbx = bx + dx, nby = by + dy, nbz = bz + dz;
-          // node range of that block in tile coordinates: [4 nb - (4b - 2), +3]
-          int l0 = 4 * dx + 2, l1 = 4 * dy + 2, l2 = 4 * dz + 2;
-          bool hit = nbx >= 0 && nby >= 0 && nbz >= 0 && nbx < g.nb && nby < g.nb && nbz < g.nb &&
-                     l0 <= hi0 && l0 + 3 >= lo0 && l1 <= hi1 && l1 + 3 >= lo1 && l2 <= hi2 && l2 + 3 >= lo2;
-          if (hit) {
-            uint32_t nk = block_key(g, sc, nbx, nby, nbz);
-            uint32_t old = atomicExch(&A.active_stamp[nk], stamp);
-            if (old != stamp) {
-              // spread the appends over NSUB counters to avoid one hot address
-              const uint32_t sub = blockIdx.x & (NSUB - 1);
-              uint32_t i = atomicAdd(A.active_n + sub, 1u);
-              A.active[(size_t)sub * A.n_keys + i] = nk;
-            }
+        // claim the blocks this tile touches: the first entry to claim a block
+        // in this step updates it in the grid kernel
+        if (tid < 64) {
+          bool won = false;
+          if (tid < 27) {
+            const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+            const int nbx = bx + dx, nby = by + dy, nbz = bz + dz;
+            const int l0 = 4 * dx + 2, l1 = 4 * dy + 2, l2 = 4 * dz + 2;
+            const bool hit = nbx >= 0 && nby >= 0 && nbz >= 0 && nbx < g.nb && nby < g.nb && nbz < g.nb &&
+                             l0 <= hi0 && l0 + 3 >= lo0 && l1 <= hi1 && l1 + 3 >= lo1 && l2 <= hi2 && l2 + 3 >= lo2;
+            if (hit) won = atomicExch(&A.claim[block_key(g, sc, nbx, nby, nbz)], stamp) != stamp;
           }
+          const unsigned long long wm = __ballot(won);
+          if (tid == 0) A.won[e] = (uint32_t)wm;
         }
+      } else if (tid == 0) {
+        A.won[e] = 0u;
       }
       __syncthreads();
     }
@@ -597,62 +658,85 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
 }
 
 // ---------------------------------------------------------------------------
-// grid update over active blocks: gather tiles, then the node update
+// grid update: one workgroup (4 wavefronts) per entry of the occupied-block
+// list; the entry's claimed neighbour blocks (claimed by the particle kernel)
+// are shared among the wavefronts; for each block the 64 node lanes sum the
+// overlapping tiles of its 27 neighbours and apply the node update
+// (normalise, gravity, soft cylinder contact, slip walls).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_grid(StepParams P, FastGeom g, const uint32_t* __restrict__ active,
-                                             const uint32_t* __restrict__ active_n, const int2* __restrict__ tile_box,
-                                             const float* __restrict__ tiles, const uint32_t* __restrict__ gen,
-                                             float4* __restrict__ vgrid, const double* __restrict__ pose_t,
-                                             const float* __restrict__ act_t) {
-  __shared__ uint32_t s_pre[NSUB + 1];
-  const int lane = threadIdx.x;
-  // prefix over the sub-list counters (NSUB == 64 == one wavefront)
-  uint32_t cnt = active_n[lane];
-  uint32_t inc = cnt;
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t o = __shfl_up(inc, off);
-    if (lane >= off) inc += o;
+struct ScanArgs {
+  uint32_t* counts;
+  uint32_t* offsets;
+  int4* list;
+  uint32_t* list_n;
+  int n_keys;
+};
+
+// With do_scan, workgroup 0 scans the key counts of this step's particle
+// kernel (independent of the grid work) and the others do the grid update.
+__global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const int4* __restrict__ list,
+                                              const uint32_t* __restrict__ list_n, const uint32_t* __restrict__ won,
+                                              const int2* __restrict__ tile_box, const float* __restrict__ tiles,
+                                              const uint32_t* __restrict__ gen, uint32_t step_id,
+                                              float4* __restrict__ vgrid, const double* __restrict__ pose_t,
+                                              const float* __restrict__ act_t, int do_scan, ScanArgs SA) {
+  if (do_scan && blockIdx.x == 0) {
+    scan_keys<256>(SA.counts, SA.offsets, SA.list, SA.list_n, SA.n_keys);
+    return;
   }
-  s_pre[lane + 1] = inc;
-  if (lane == 0) s_pre[0] = 0;
-  __syncthreads();
-  const uint32_t n_act = s_pre[NSUB];
-  const uint32_t stamp = gen[0];
+  const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
+  const uint32_t n_list = list_n[0];
+  const uint32_t stamp = (gen[0] << 16) | step_id;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane >> 4, lj = (lane >> 2) & 3, lk = lane & 3;
-  for (uint32_t e = blockIdx.x; e < n_act; e += gridDim.x) {
-    int sub = 0;
-    while (sub < NSUB - 1 && s_pre[sub + 1] <= e) sub++;
-    const uint32_t key = active[(size_t)sub * g.n_keys + (e - s_pre[sub])];
+  for (uint32_t e = wg; e < n_list; e += n_wg) {
+    uint32_t mask = won[e];
+    if (!mask) continue;
     int sc, bx, by, bz;
-    key_decode(g, key, sc, bx, by, bz);
-    const int gx = 4 * bx + li, gy = 4 * by + lj, gz = 4 * bz + lk;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll 1
-    for (int d = 0; d < 27; d++) {
-      int sx = bx + d / 9 - 1, sy = by + (d / 3) % 3 - 1, sz = bz + d % 3 - 1;
-      if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nb || sy >= g.nb || sz >= g.nb) continue;
-      uint32_t sk = block_key(g, sc, sx, sy, sz);
-      int2 box = tile_box[sk];
-      if ((uint32_t)box.y != stamp) continue;
-      int qi = gx - (4 * sx - 2), qj = gy - (4 * sy - 2), qk = gz - (4 * sz - 2);
-      int lo0 = box.x & 15, lo1 = (box.x >> 4) & 15, lo2 = (box.x >> 8) & 15;
-      int hi0 = (box.x >> 12) & 15, hi1 = (box.x >> 16) & 15, hi2 = (box.x >> 20) & 15;
-      if (qi < lo0 || qi > hi0 || qj < lo1 || qj > hi1 || qk < lo2 || qk > hi2) continue;
-      int q = (qi * TILE + qj) * TILE + qk;
-      const float* T = tiles + (size_t)sk * 4 * TILE_NODES;
-      acc.w += T[q];
-      acc.x += T[TILE_NODES + q];
-      acc.y += T[2 * TILE_NODES + q];
-      acc.z += T[3 * TILE_NODES + q];
+    key_decode(g, (uint32_t)list[e].x, sc, bx, by, bz);
+    // the j-th claimed block goes to wavefront j % 4
+    for (int j = 0; mask; j++) {
+      const int d = __ffs(mask) - 1;
+      mask &= mask - 1u;
+      if ((j & 3) != wv) continue;
+      const int cx = bx + d / 9 - 1, cy = by + (d / 3) % 3 - 1, cz = bz + d % 3 - 1;
+      const uint32_t key = block_key(g, sc, cx, cy, cz);
+      int2 nbox = make_int2(0, 0);
+      if (lane < 27) {
+        const int sx = cx + lane / 9 - 1, sy = cy + (lane / 3) % 3 - 1, sz = cz + lane % 3 - 1;
+        if (sx >= 0 && sy >= 0 && sz >= 0 && sx < g.nb && sy < g.nb && sz < g.nb) {
+          nbox = tile_box[block_key(g, sc, sx, sy, sz)];
+          if ((uint32_t)nbox.y != stamp) nbox.y = 0;
+        }
+      }
+      const int gx = 4 * cx + li, gy = 4 * cy + lj, gz = 4 * cz + lk;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int dd = 0; dd < 27; dd++) {
+        const int bxv = __shfl(nbox.x, dd);
+        const int valid = __shfl(nbox.y, dd);
+        if (!valid) continue;
+        const int sx = cx + dd / 9 - 1, sy = cy + (dd / 3) % 3 - 1, sz = cz + dd % 3 - 1;
+        const int qi = gx - (4 * sx - 2), qj = gy - (4 * sy - 2), qk = gz - (4 * sz - 2);
+        const int lo0 = bxv & 15, lo1 = (bxv >> 4) & 15, lo2 = (bxv >> 8) & 15;
+        const int hi0 = (bxv >> 12) & 15, hi1 = (bxv >> 16) & 15, hi2 = (bxv >> 20) & 15;
+        if (qi < lo0 || qi > hi0 || qj < lo1 || qj > hi1 || qk < lo2 || qk > hi2) continue;
+        const int q = (qi * TILE + qj) * TILE + qk;
+        const float* T = tiles + (size_t)block_key(g, sc, sx, sy, sz) * 4 * TILE_NODES;
+        acc.w += T[q];
+        acc.x += T[TILE_NODES + q];
+        acc.y += T[2 * TILE_NODES + q];
+        acc.z += T[3 * TILE_NODES + q];
+      }
+      float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (acc.w > 0.f && gx < g.n && gy < g.n && gz < g.n) {
+        int idx[3] = {gx, gy, gz};
+        float vv[3];
+        grid_node_forward(P, sc, idx, acc, pose_t, act_t, vv, nullptr);
+        out = make_float4(vv[0], vv[1], vv[2], acc.w);
+      }
+      vgrid[(size_t)key * 64 + lane] = out;
     }
-    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (acc.w > 0.f && gx < g.n && gy < g.n && gz < g.n) {
-      int idx[3] = {gx, gy, gz};
-      float vv[3];
-      grid_node_forward(P, sc, idx, acc, pose_t, act_t, vv, nullptr);
-      out = make_float4(vv[0], vv[1], vv[2], acc.w);
-    }
-    vgrid[(size_t)key * 64 + lane] = out;
   }
 }
 
@@ -671,8 +755,8 @@ static FastGeom make_geom(int n_grid, int S) {
 }
 
 struct FastLayout {
-  size_t buf_f[2], buf_id[2], buf_key[2], buf_rank[2], buf_mat[2];
-  size_t key_tmp, rank_tmp, counts, offsets, list[2], list_n, active[2], active_n, active_stamp, tile_box, tiles, vgrid, gen;
+  size_t buf_f[2], buf_id[2], buf_key[2], buf_rank[2], buf_mat[2], list[3];
+  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, won, tile_box, tiles, vgrid, gen;
   size_t total;
 };
 
@@ -681,6 +765,7 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   FastLayout L;
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o += a256(b); return r; };
+  for (int b = 0; b < 3; b++) L.list[b] = take((size_t)g.n_keys * 16);
   for (int b = 0; b < 2; b++) {
     L.buf_f[b] = take((size_t)STATE_FLOATS * N * 4);
     L.buf_id[b] = take((size_t)N * 4);
@@ -692,13 +777,9 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   L.rank_tmp = take((size_t)N * 4);
   L.counts = take((size_t)g.n_keys * 4);
   L.offsets = take((size_t)g.n_keys * 4);
-  L.list[0] = take((size_t)g.n_keys * 16);
-  L.list[1] = take((size_t)g.n_keys * 16);
   L.list_n = take(16);
-  L.active[0] = take((size_t)g.n_keys * 4 * NSUB);
-  L.active[1] = take((size_t)g.n_keys * 4 * NSUB);
-  L.active_n = take(2 * NSUB * 4);
-  L.active_stamp = take((size_t)g.n_keys * 4);
+  L.claim = take((size_t)g.n_keys * 4);
+  L.won = take((size_t)g.n_keys * 4);
   L.tile_box = take((size_t)g.n_keys * 8);
   L.tiles = take((size_t)g.n_keys * 4 * TILE_NODES * 4);
   L.vgrid = take((size_t)g.n_keys * 64 * 16);
@@ -722,28 +803,27 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
     f.buf[b].key = (uint32_t*)(ws + L.buf_key[b]);
     f.buf[b].rank = (uint32_t*)(ws + L.buf_rank[b]);
     f.buf[b].mat = (uint8_t*)(ws + L.buf_mat[b]);
-    f.list[b] = (int4*)(ws + L.list[b]);
-    f.active[b] = (uint32_t*)(ws + L.active[b]);
   }
+  for (int b = 0; b < 3; b++) f.list[b] = (int4*)(ws + L.list[b]);
   f.key_tmp = (uint32_t*)(ws + L.key_tmp);
   f.rank_tmp = (uint32_t*)(ws + L.rank_tmp);
   f.counts = (uint32_t*)(ws + L.counts);
   f.offsets = (uint32_t*)(ws + L.offsets);
   f.list_n = (uint32_t*)(ws + L.list_n);
-  f.active_n = (uint32_t*)(ws + L.active_n);
-  f.active_stamp = (uint32_t*)(ws + L.active_stamp);
+  f.claim = (uint32_t*)(ws + L.claim);
+  f.won = (uint32_t*)(ws + L.won);
   f.tile_box = (int2*)(ws + L.tile_box);
   f.tiles = (float*)(ws + L.tiles);
   f.vgrid = (float4*)(ws + L.vgrid);
   f.gen = (uint32_t*)(ws + L.gen);
   f.part_wgs = 2048;
-  f.grid_wgs = 4096;
+  f.calls = 0;
+  f.grid_wgs = 2048;
   f.valid = false;
   // zero the bookkeeping (counts, stamps, counters, velocity grid)
   launch_zero(ws + L.counts, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.list_n, 256, s);
-  launch_zero(ws + L.active_n, a256(2 * NSUB * 4), s);
-  launch_zero(ws + L.active_stamp, a256((size_t)f.g.n_keys * 4), s);
+  launch_zero(ws + L.claim, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.tile_box, a256((size_t)f.g.n_keys * 8), s);
   launch_zero(ws + L.vgrid, a256((size_t)f.g.n_keys * 64 * 16), s);
   launch_zero(ws + L.gen, 256, s);
@@ -761,7 +841,13 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   const int S = g.S;
   // ---- import: sort the user-order state into buf[0] by block key
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.counts, f.key_tmp, f.rank_tmp);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.list[0], f.list_n + 0, g.n_keys, f.active_n, f.gen);
+  if (n >= 65535) return -1;
+  if ((++f.calls & 0xffff) == 0) {
+    // the 16-bit epoch wraps: clear the stamps so no stale entry can match
+    launch_zero(f.claim, (size_t)g.n_keys * 4, s);
+    launch_zero(f.tile_box, (size_t)g.n_keys * 8, s);
+  }
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.list[0], f.list_n + 0, g.n_keys, f.gen);
   k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, f.buf[0], f.key_tmp, f.rank_tmp, f.offsets);
   // The particle kernels read the material of the sorted buffer.
   StepParams Q = P;
@@ -771,23 +857,22 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   A.offsets = f.offsets;
   A.tiles = f.tiles;
   A.tile_box = f.tile_box;
-  A.active_stamp = f.active_stamp;
   A.gen = f.gen;
   A.vgrid = f.vgrid;
   A.n_keys = g.n_keys;
+  A.claim = f.claim;
+  A.won = f.won;
   // Bookkeeping: `rd` is the list describing buf[cur] (the buffer the next
   // particle kernel reads); `wr` is the list describing the order in which
   // the current offsets place particles (the buffer the next kernel writes).
   int cur = 0, rd = 0, wr = 0;
   for (int step = 0; step <= n; step++) {
     const int t = t0 + step;
-    const int ap = step & 1;   // active list of this step
     A.in = f.buf[cur];
     A.out = f.buf[cur ^ 1];
     A.list = f.list[rd];
     A.list_n = f.list_n + rd;
-    A.active = f.active[ap];
-    A.active_n = f.active_n + ap * NSUB;
+    A.step_id = (uint32_t)(step + 1);
     if (step == n) {
       k_particles<MODE_G2P><<<f.part_wgs, 256, 0, s>>>(A, Q, g);
       cur ^= 1;
@@ -800,18 +885,28 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
       k_particles<MODE_FUSED><<<f.part_wgs, 256, 0, s>>>(A, Q, g);
       if (timer) timer->end(s);
     }
-    k_grid<<<f.grid_wgs, 64, 0, s>>>(Q, g, f.active[ap], f.active_n + ap * NSUB, f.tile_box, f.tiles, f.gen, f.vgrid,
-                                      pose + (size_t)t * S * POSE_DOUBLES, act + (size_t)t * S * 6);
-    if (step == 0) {
-      // nothing counted: keep the import's offsets, advance the stamp and
-      // reset the next step's active list
-      k_bookkeep<<<1, 64, 0, s>>>(f.active_n + (ap ^ 1) * NSUB, f.gen);
-    } else {
+    // grid update of this step; from step 1 on, workgroup 0 also scans the
+    // keys the particle kernel counted (the step-0 kernel counts nothing and
+    // the import's offsets stay in force)
+    const int do_scan = step >= 1 ? 1 : 0;
+    // three lists rotate: rd is read by this launch's grid workgroups, wr
+    // describes the buffer just written (read next step), the scan fills the
+    // third one
+    const int nwr = (rd == wr) ? (rd + 1) % 3 : 3 - rd - wr;
+    const int nrd = do_scan ? wr : rd;
+    ScanArgs SA;
+    SA.counts = f.counts;
+    SA.offsets = f.offsets;
+    SA.list = f.list[nwr];
+    SA.list_n = f.list_n + nwr;
+    SA.n_keys = g.n_keys;
+    k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(Q, g, f.list[rd], f.list_n + rd, f.won, f.tile_box, f.tiles, f.gen,
+                                               (uint32_t)(step + 1), f.vgrid, pose + (size_t)t * S * POSE_DOUBLES,
+                                               act + (size_t)t * S * 6, do_scan, SA);
+    if (do_scan) {
       cur ^= 1;
-      rd = wr;
-      wr = 1 - rd;
-      k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.list[wr], f.list_n + wr, g.n_keys, f.active_n + (ap ^ 1) * NSUB,
-                                f.gen);
+      rd = nrd;
+      wr = nwr;
     }
   }
   k_export<<<nblk(N, 256), 256, 0, s>>>(f.buf[cur], user, P.mats);
