@@ -165,6 +165,25 @@ int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out);
 int mpm_timing_enable(mpm_ctx* c, int32_t enable);
 int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name, int32_t name_len);
 
+/* Launch-shape and mode options of the forward path (mpm_step without
+ * requires_grad).  Defaults: graph 0, particle workgroup 256 threads, 2048
+ * particle workgroups, 2048 grid workgroups. */
+enum {
+  MPM_OPT_GRAPH = 1,          /* 1: capture each call shape in a HIP graph and replay it */
+  MPM_OPT_PART_THREADS = 2,   /* 128 or 256 threads per particle workgroup */
+  MPM_OPT_PART_WGS = 3,       /* particle workgroups per launch (persistent, 64..65536) */
+  MPM_OPT_GRID_WGS = 4        /* grid-update workgroups per launch (64..65536) */
+};
+int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value);
+int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value);
+
+/* Autotuner: times n_steps of the forward path from the current state (the
+ * state and the clock are left unchanged; actions t..t+n_steps-1 must be
+ * set) for every launch shape in a fixed candidate set, keeps the fastest
+ * and returns it in best[4] = {part_threads, part_wgs, grid_wgs,
+ * microseconds per step}. */
+int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best);
+
 /* Free the host context (not the borrowed device memory). */
 int mpm_destroy(mpm_ctx* c);
 

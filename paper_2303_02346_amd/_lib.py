@@ -33,7 +33,9 @@ class MpmDesc(ctypes.Structure):
 
 EXPORTS = ["mpm_workspace_bytes", "mpm_create", "mpm_set_state", "mpm_set_actions", "mpm_step",
            "mpm_step_backward", "mpm_loss_blob", "mpm_clock", "mpm_last_error_bits", "mpm_timing_enable",
-           "mpm_timing_read", "mpm_destroy", "mpm_strerror"]
+           "mpm_timing_read", "mpm_set_option", "mpm_get_option", "mpm_autotune", "mpm_destroy", "mpm_strerror"]
+
+MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS = 1, 2, 3, 4
 
 _lib = None
 
@@ -66,6 +68,9 @@ def lib():
     L.mpm_last_error_bits.argtypes = [vp, ctypes.POINTER(i32)]
     L.mpm_timing_enable.argtypes = [vp, i32]
     L.mpm_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_char_p, i32]
+    L.mpm_set_option.argtypes = [vp, i32, i32]
+    L.mpm_get_option.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.mpm_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.mpm_destroy.argtypes = [vp]
     L.mpm_strerror.argtypes = [ctypes.c_int]
     L.mpm_strerror.restype = ctypes.c_char_p

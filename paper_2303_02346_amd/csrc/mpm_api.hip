@@ -216,6 +216,7 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
 
 int mpm_set_state(mpm_ctx* c, const mpm_state* st) {
   if (!c || !st || !st->x || !st->v || !st->C || !st->F || !st->J || !st->mat) return MPM_EINVAL;
+  if (c->has_state && (c->user.x != st->x || c->user.mat != st->mat)) fast_invalidate(c->fast);
   c->user = *st;
   c->has_state = true;
   c->t = 0;
@@ -227,7 +228,6 @@ int mpm_set_state(mpm_ctx* c, const mpm_state* st) {
   }
   if (hipMemcpyAsync(c->ws + c->L.pose, pose0.data(), pose0.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return MPM_EHIP;
-  fast_invalidate(c->fast);
   // pose0 is a host temporary: wait for the copy
   return hip_ok(hipStreamSynchronize(c->stream));
 }
@@ -370,6 +370,93 @@ int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out) {
   if (!c || !bits_out) return MPM_EINVAL;
   *bits_out = c->last_err_bits;
   return MPM_OK;
+}
+
+int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value) {
+  if (!c) return MPM_EINVAL;
+  switch (key) {
+    case MPM_OPT_GRAPH: c->fast.use_graph = value != 0; return MPM_OK;
+    case MPM_OPT_PART_THREADS:
+      if (value != 128 && value != 256) return MPM_EINVAL;
+      c->fast.part_threads = value;
+      return MPM_OK;
+    case MPM_OPT_PART_WGS:
+      if (value < 64 || value > 65536) return MPM_EINVAL;
+      c->fast.part_wgs = value;
+      return MPM_OK;
+    case MPM_OPT_GRID_WGS:
+      if (value < 64 || value > 65536) return MPM_EINVAL;
+      c->fast.grid_wgs = value;
+      return MPM_OK;
+    default: return MPM_EINVAL;
+  }
+}
+
+int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value) {
+  if (!c || !value) return MPM_EINVAL;
+  switch (key) {
+    case MPM_OPT_GRAPH: *value = c->fast.use_graph ? 1 : 0; return MPM_OK;
+    case MPM_OPT_PART_THREADS: *value = c->fast.part_threads; return MPM_OK;
+    case MPM_OPT_PART_WGS: *value = c->fast.part_wgs; return MPM_OK;
+    case MPM_OPT_GRID_WGS: *value = c->fast.grid_wgs; return MPM_OK;
+    default: return MPM_EINVAL;
+  }
+}
+
+int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best) {
+  if (!c || !best || n_steps < 1) return MPM_EINVAL;
+  if (!c->has_state) return MPM_ESTATE;
+  if (c->t + n_steps > c->d.horizon) return MPM_EINVAL;
+  for (int t = c->t; t < c->t + n_steps; t++)
+    if (!c->act_set[t]) return MPM_ESTATE;
+  StepParams P = make_params(c);
+  PState us = user_pstate(&c->user, c->d.n_particles);
+  hipStream_t s = c->stream;
+  launch_pose(c->d.n_scenes, c->t, n_steps, c->d.dt, (const float*)(c->ws + c->L.act), (double*)(c->ws + c->L.pose), s);
+  const int pts[2] = {128, 256};
+  const int pws[4] = {512, 1024, 2048, 4096};
+  const int gws[3] = {512, 1024, 2048};
+  const int save_pt = c->fast.part_threads, save_pw = c->fast.part_wgs, save_gw = c->fast.grid_wgs;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPM_EHIP;
+  float best_ms = 1e30f;
+  int bpt = save_pt, bpw = save_pw, bgw = save_gw;
+  c->fast.do_export = false;     // the trial runs leave the user state untouched
+  int rc = MPM_OK;
+  for (int a = 0; a < 2 && rc == MPM_OK; a++)
+    for (int b = 0; b < 4 && rc == MPM_OK; b++)
+      for (int d = 0; d < 3 && rc == MPM_OK; d++) {
+        c->fast.part_threads = pts[a];
+        c->fast.part_wgs = pws[b];
+        c->fast.grid_wgs = gws[d];
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3; rep++) {
+          hipEventRecord(e0, s);
+          if (fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), s, nullptr) != 0) { rc = MPM_EHIP; break; }
+          hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) { rc = MPM_EHIP; break; }
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0 && ms < ms_min) ms_min = ms;   // first run warms up (and captures)
+        }
+        if (rc == MPM_OK && ms_min < best_ms) { best_ms = ms_min; bpt = pts[a]; bpw = pws[b]; bgw = gws[d]; }
+      }
+  c->fast.do_export = true;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != MPM_OK) {
+    c->fast.part_threads = save_pt; c->fast.part_wgs = save_pw; c->fast.grid_wgs = save_gw;
+    return rc;
+  }
+  c->fast.part_threads = bpt;
+  c->fast.part_wgs = bpw;
+  c->fast.grid_wgs = bgw;
+  best[0] = bpt;
+  best[1] = bpw;
+  best[2] = bgw;
+  best[3] = (int32_t)(best_ms * 1000.f / n_steps);
+  int frc = finish(c);
+  return frc == MPM_OK ? MPM_OK : frc;
 }
 
 int mpm_timing_enable(mpm_ctx* c, int32_t enable) {

@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <vector>
 #include "mpm_internal.h"
 
 namespace mpm {
@@ -32,6 +33,17 @@ struct PBuf {
   uint8_t* mat;
 };
 
+// A captured call (graph mode).
+struct FastGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int n = 0, part_threads = 0, part_wgs = 0, grid_wgs = 0;
+  bool timed = false, do_export = true;
+  const float* x = nullptr;
+  const uint8_t* mat = nullptr;
+  std::vector<hipEvent_t> ev;   // fused-kernel event pairs recorded by the graph
+};
+
 struct FastPath {
   char* ws;
   FastGeom g;
@@ -47,7 +59,13 @@ struct FastPath {
   float* tiles;            // n_keys x 4 x TILE_NODES
   float4* vgrid;           // n_keys x 64
   uint32_t* gen;           // device per-call epoch of the step stamps
+  int* t0_dev;             // device clock at the start of the call
   unsigned long long calls;
+  // launch shape and mode (set by mpm_set_option / the autotuner)
+  int part_threads;        // 128 or 256 threads per particle workgroup
+  bool use_graph;          // capture each call shape once and replay it
+  bool do_export;          // write the result back to the user arrays
+  std::vector<FastGraph> graphs;
   int grid_wgs, part_wgs;
   // plain dense grid (shared with the adjoint path), unused here
   float4* mmv;

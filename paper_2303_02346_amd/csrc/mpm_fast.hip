@@ -23,6 +23,7 @@
 // MPM_ERR_TILE, the CFL > 1 condition).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <vector>
 #include "mpm_fast.h"
 #include "mpm_math.h"
 #include "mpm_phys.h"
@@ -306,8 +307,9 @@ struct PartArgs {
   const float4* vgrid;
 };
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, FastGeom g) {
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, FastGeom g) {
+  constexpr int NW = NT / 64;
   __shared__ float s_tile[4 * TILE_NODES];
   __shared__ int s_itile[4 * TILE_NODES];
   __shared__ float4 s_v[VT_NODES];
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
     const int ox = 4 * bx, oy = 4 * by, oz = 4 * bz;
     // ---- stage grid velocities of nodes [4b-1, 4b+7) for G2P
     if (MODE != MODE_P2G) {
-      for (int q = tid; q < VT_NODES; q += 256) {
+      for (int q = tid; q < VT_NODES; q += NT) {
         int qi = q / (VT * VT), qj = (q / VT) % VT, qk = q % VT;
         int gx = ox - 1 + qi, gy = oy - 1 + qj, gz = oz - 1 + qk;
         float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -338,12 +340,12 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
       }
     }
     if (MODE != MODE_G2P) {
-      for (int q = tid; q < 4 * TILE_NODES; q += 256) { s_tile[q] = 0.f; s_itile[q] = 0; }
+      for (int q = tid; q < 4 * TILE_NODES; q += NT) { s_tile[q] = 0.f; s_itile[q] = 0; }
       if (tid < 3) { s_lo[tid] = 1 << 20; s_hi[tid] = -(1 << 20); }
     }
     __syncthreads();
     const int start = ent.y, count = ent.z;
-    for (int c0 = 0; c0 < count; c0 += 256) {
+    for (int c0 = 0; c0 < count; c0 += NT) {
       const int j = start + c0 + tid;
       const bool has = (c0 + tid) < count && j < N;
       float x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, C[9], F[9], J = 1.f;
@@ -353,6 +355,9 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
       if (has) {
         load_state(A.in, N, j, x, v, C, F, J);
         m = A.in.mat[j];
+        // destination slot in the output buffer; loaded now so that the
+        // dependent key -> offset lookup overlaps the G2P arithmetic
+        if (MODE != MODE_P2G) dst = A.offsets[A.in.key[j]] + A.in.rank[j];
       }
       const MatDev& M = P.mats[m];
       const bool liquid = M.kind == KIND_LIQUID;
@@ -374,24 +379,33 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
         if (!in_grid) { atomicOr(P.err, ERR_OUTSIDE); ok = false; }
         else if (!in_tile) { atomicOr(P.err, ERR_TILE); ok = false; }
         if (ok) {
-          float vn[3] = {0, 0, 0}, B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          // sum_i w v_i and sum_i w v_i idx^T (idx = the node offset in
+          // {0,1,2}^3); then B = sum w v (x_i - x_p)^T = dx (Bi - vn f^T)
+          float vn[3] = {0, 0, 0}, Bi[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
           for (int i = 0; i < 3; i++)
 #pragma unroll
-            for (int jj = 0; jj < 3; jj++)
+            for (int jj = 0; jj < 3; jj++) {
+              const float wxy = S.w[0][i] * S.w[1][jj];
 #pragma unroll
               for (int k = 0; k < 3; k++) {
-                float w = S.w[0][i] * S.w[1][jj] * S.w[2][k];
-                float d[3] = {(i - S.f[0]) * P.dx, (jj - S.f[1]) * P.dx, (k - S.f[2]) * P.dx};
-                float4 gv4 = s_v[((lb[0] + i) * VT + lb[1] + jj) * VT + lb[2] + k];
-                float gv[3] = {w * gv4.x, w * gv4.y, w * gv4.z};
+                const float w = wxy * S.w[2][k];
+                const float4 gv4 = s_v[((lb[0] + i) * VT + lb[1] + jj) * VT + lb[2] + k];
+                const float wv[3] = {w * gv4.x, w * gv4.y, w * gv4.z};
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
-                  vn[a] += gv[a];
-#pragma unroll
-                  for (int b = 0; b < 3; b++) B[a * 3 + b] += gv[a] * d[b];
+                  vn[a] += wv[a];
+                  if (i) Bi[a * 3 + 0] += (float)i * wv[a];
+                  if (jj) Bi[a * 3 + 1] += (float)jj * wv[a];
+                  if (k) Bi[a * 3 + 2] += (float)k * wv[a];
                 }
               }
+            }
+          float B[9];
+#pragma unroll
+          for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) B[a * 3 + b] = P.dx * (Bi[a * 3 + b] - vn[a] * S.f[b]);
           // particle update (+ stress of the new state for the fused mode)
           const float d4 = 4.f * P.inv_dx * P.inv_dx;
           float Md[9];
@@ -459,7 +473,6 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
           if (!fin) { atomicOr(P.err, ERR_NONFINITE); ok = false; }
         }
         // write the particle to its slot in the output buffer
-        dst = A.offsets[A.in.key[j]] + A.in.rank[j];
         if (dst < (uint32_t)N) {
           PBuf& O = A.out;
 #pragma unroll
@@ -479,7 +492,7 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
       }
       // ---------------- P2G of this step ----------------
       // LDS float atomics are slow on gfx950 (about 1/30 of the integer
-      // rate), so each 256-particle chunk accumulates in exact 32-bit fixed
+      // rate), so each chunk of NT particles accumulates in exact 32-bit fixed
       // point: a power-of-two scale per quantity, chosen from a bound on the
       // chunk's contributions so that no node sum can overflow, then the
       // integer tile is flushed into the float tile by its owner threads.
@@ -545,7 +558,10 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
         if (tid == 0) {
 #pragma unroll
           for (int q = 0; q < 4; q++) {
-            float T = 0.421875f * (s_red[q] + s_red[4 + q] + s_red[8 + q] + s_red[12 + q]);
+            float T = 0.f;
+#pragma unroll
+            for (int w = 0; w < NW; w++) T += s_red[w * 4 + q];
+            T *= 0.421875f;
             if (!isfinite(T)) { atomicOr(P.err, ERR_NONFINITE); T = 1.f; }
             int e = 0;
             frexpf(T > 0.f ? T : 1.f, &e);
@@ -555,8 +571,9 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
           }
 #pragma unroll
           for (int a = 0; a < 3; a++) {
-            int lo = min(min(s_ired[a], s_ired[6 + a]), min(s_ired[12 + a], s_ired[18 + a]));
-            int hi = max(max(s_ired[3 + a], s_ired[9 + a]), max(s_ired[15 + a], s_ired[21 + a]));
+            int lo = s_ired[a], hi = s_ired[3 + a];
+#pragma unroll
+            for (int w = 1; w < NW; w++) { lo = min(lo, s_ired[w * 6 + a]); hi = max(hi, s_ired[w * 6 + 3 + a]); }
             s_ired[24 + a] = lo;
             s_ired[27 + a] = hi;
             if (lo <= hi) { s_lo[a] = min(s_lo[a], lo); s_hi[a] = max(s_hi[a], hi); }
@@ -564,21 +581,40 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
         }
         __syncthreads();
         if (ok) {
-          const float sm = s_scale[0], sx = s_scale[1], sy = s_scale[2], sz = s_scale[3];
+          // mom_a(node) = mvp_a + sum_b A_ab (idx_b - f_b) dx = c0_a + sum_b Ad_ab idx_b,
+          // with the quantity's power-of-two scale folded into c0 and Ad
+          const float sm = M.mass * s_scale[0];
+          float c0[3], Ad[9];
 #pragma unroll
-          for (int i = 0; i < 3; i++)
+          for (int a = 0; a < 3; a++) {
+            const float sa = s_scale[1 + a];
 #pragma unroll
-            for (int jj = 0; jj < 3; jj++)
+            for (int b = 0; b < 3; b++) Ad[a * 3 + b] = sa * P.dx * Am[a * 3 + b];
+            c0[a] = sa * mvp[a] - (Ad[a * 3] * S.f[0] + Ad[a * 3 + 1] * S.f[1] + Ad[a * 3 + 2] * S.f[2]);
+          }
+          int* T = s_itile + (lb[0] * TILE + lb[1]) * TILE + lb[2];
+#pragma unroll
+          for (int i = 0; i < 3; i++) {
+            float m1[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) m1[a] = c0[a] + (float)i * Ad[a * 3];
+#pragma unroll
+            for (int jj = 0; jj < 3; jj++) {
+              const float wxy = S.w[0][i] * S.w[1][jj];
+              float m2[3];
+#pragma unroll
+              for (int a = 0; a < 3; a++) m2[a] = m1[a] + (float)jj * Ad[a * 3 + 1];
 #pragma unroll
               for (int k = 0; k < 3; k++) {
-                float w = S.w[0][i] * S.w[1][jj] * S.w[2][k];
-                float d0 = (i - S.f[0]) * P.dx, d1 = (jj - S.f[1]) * P.dx, d2 = (k - S.f[2]) * P.dx;
-                int q = ((lb[0] + i) * TILE + lb[1] + jj) * TILE + lb[2] + k;
-                atomicAdd(&s_itile[q], __float2int_rn(w * M.mass * sm));
-                atomicAdd(&s_itile[TILE_NODES + q], __float2int_rn(w * (mvp[0] + Am[0] * d0 + Am[1] * d1 + Am[2] * d2) * sx));
-                atomicAdd(&s_itile[2 * TILE_NODES + q], __float2int_rn(w * (mvp[1] + Am[3] * d0 + Am[4] * d1 + Am[5] * d2) * sy));
-                atomicAdd(&s_itile[3 * TILE_NODES + q], __float2int_rn(w * (mvp[2] + Am[6] * d0 + Am[7] * d1 + Am[8] * d2) * sz));
+                const float w = wxy * S.w[2][k];
+                const int q = (i * TILE + jj) * TILE + k;
+                atomicAdd(&T[q], __float2int_rn(w * sm));
+                atomicAdd(&T[TILE_NODES + q], __float2int_rn(w * (m2[0] + (float)k * Ad[2])));
+                atomicAdd(&T[2 * TILE_NODES + q], __float2int_rn(w * (m2[1] + (float)k * Ad[5])));
+                atomicAdd(&T[3 * TILE_NODES + q], __float2int_rn(w * (m2[2] + (float)k * Ad[8])));
               }
+            }
+          }
         }
         __syncthreads();
         {
@@ -588,7 +624,7 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
           if (lo0 <= hi0) {
             const int ex = hi0 - lo0 + 3, ey = hi1 - lo1 + 3, ez = hi2 - lo2 + 3;
             const int cnt = ex * ey * ez;
-            for (int r = tid; r < cnt; r += 256) {
+            for (int r = tid; r < cnt; r += NT) {
               int qq = ((lo0 + r / (ey * ez)) * TILE + lo1 + (r / ez) % ey) * TILE + lo2 + r % ez;
 #pragma unroll
               for (int c = 0; c < 4; c++) {
@@ -624,7 +660,7 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs A, StepParams P, Fas
         const int ex = hi0 - lo0 + 1, ey = hi1 - lo1 + 1, ez = hi2 - lo2 + 1;
         const int cnt = ex * ey * ez;
         float* T = A.tiles + (size_t)bkey * 4 * TILE_NODES;
-        for (int r = tid; r < cnt; r += 256) {
+        for (int r = tid; r < cnt; r += NT) {
           int qi = lo0 + r / (ey * ez), qj = lo1 + (r / ez) % ey, qk = lo2 + r % ez;
           int q = (qi * TILE + qj) * TILE + qk;
 #pragma unroll
@@ -678,13 +714,19 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const in
                                               const uint32_t* __restrict__ list_n, const uint32_t* __restrict__ won,
                                               const int2* __restrict__ tile_box, const float* __restrict__ tiles,
                                               const uint32_t* __restrict__ gen, uint32_t step_id,
-                                              float4* __restrict__ vgrid, const double* __restrict__ pose_t,
-                                              const float* __restrict__ act_t, int do_scan, ScanArgs SA) {
+                                              float4* __restrict__ vgrid, const double* __restrict__ pose_base,
+                                              const float* __restrict__ act_base, const int* __restrict__ t0_dev,
+                                              int do_scan, ScanArgs SA) {
   if (do_scan && blockIdx.x == 0) {
     scan_keys<256>(SA.counts, SA.offsets, SA.list, SA.list_n, SA.n_keys);
     return;
   }
   const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
+  // the clock lives in device memory so that a captured call can be replayed
+  // at any start time: this launch is step (step_id - 1) of the call
+  const size_t t = (size_t)t0_dev[0] + step_id - 1;
+  const double* pose_t = pose_base + t * g.S * POSE_DOUBLES;
+  const float* act_t = act_base + t * g.S * 6;
   const uint32_t n_list = list_n[0];
   const uint32_t stamp = (gen[0] << 16) | step_id;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -756,7 +798,7 @@ static FastGeom make_geom(int n_grid, int S) {
 
 struct FastLayout {
   size_t buf_f[2], buf_id[2], buf_key[2], buf_rank[2], buf_mat[2], list[3];
-  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, won, tile_box, tiles, vgrid, gen;
+  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, won, tile_box, tiles, vgrid, gen, t0;
   size_t total;
 };
 
@@ -784,6 +826,7 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   L.tiles = take((size_t)g.n_keys * 4 * TILE_NODES * 4);
   L.vgrid = take((size_t)g.n_keys * 64 * 16);
   L.gen = take(16);
+  L.t0 = take(16);
   L.total = o;
   return L;
 }
@@ -816,6 +859,10 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.tiles = (float*)(ws + L.tiles);
   f.vgrid = (float4*)(ws + L.vgrid);
   f.gen = (uint32_t*)(ws + L.gen);
+  f.t0_dev = (int*)(ws + L.t0);
+  f.part_threads = 256;
+  f.use_graph = false;
+  f.do_export = true;
   f.part_wgs = 2048;
   f.calls = 0;
   f.grid_wgs = 2048;
@@ -831,26 +878,19 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
 }
 
 void fast_bind_grid(FastPath& f, float4* mmv, float4* vgrid) { f.mmv = mmv; f.vdense = vgrid; }
-void fast_invalidate(FastPath& f) { f.valid = false; }
-void fast_destroy(FastPath&) {}
 
-int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n, const double* pose, const float* act,
-             hipStream_t s, KernelTimer* timer) {
+__global__ void k_set_word(int* w, int v) { w[0] = v; }
+
+// Enqueue one call of n steps: import (sort by block), n steps, export.  With
+// `ev` the fused kernel's launches are bracketed by the given event pairs.
+template <int NT>
+static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, int n, const double* pose,
+                         const float* act, hipStream_t s, std::vector<hipEvent_t>* ev) {
   const FastGeom g = f.g;
   const int N = f.N;
-  const int S = g.S;
-  // ---- import: sort the user-order state into buf[0] by block key
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.counts, f.key_tmp, f.rank_tmp);
-  if (n >= 65535) return -1;
-  if ((++f.calls & 0xffff) == 0) {
-    // the 16-bit epoch wraps: clear the stamps so no stale entry can match
-    launch_zero(f.claim, (size_t)g.n_keys * 4, s);
-    launch_zero(f.tile_box, (size_t)g.n_keys * 8, s);
-  }
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.list[0], f.list_n + 0, g.n_keys, f.gen);
   k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, f.buf[0], f.key_tmp, f.rank_tmp, f.offsets);
-  // The particle kernels read the material of the sorted buffer.
-  StepParams Q = P;
   PartArgs A;
   A.N = N;
   A.counts = f.counts;
@@ -865,25 +905,24 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   // Bookkeeping: `rd` is the list describing buf[cur] (the buffer the next
   // particle kernel reads); `wr` is the list describing the order in which
   // the current offsets place particles (the buffer the next kernel writes).
-  int cur = 0, rd = 0, wr = 0;
+  int cur = 0, rd = 0, wr = 0, ei = 0;
   for (int step = 0; step <= n; step++) {
-    const int t = t0 + step;
     A.in = f.buf[cur];
     A.out = f.buf[cur ^ 1];
     A.list = f.list[rd];
     A.list_n = f.list_n + rd;
     A.step_id = (uint32_t)(step + 1);
     if (step == n) {
-      k_particles<MODE_G2P><<<f.part_wgs, 256, 0, s>>>(A, Q, g);
+      k_particles<MODE_G2P, NT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
       cur ^= 1;
       break;
     }
     if (step == 0) {
-      k_particles<MODE_P2G><<<f.part_wgs, 256, 0, s>>>(A, Q, g);
+      k_particles<MODE_P2G, NT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
     } else {
-      if (timer) timer->begin(s);
-      k_particles<MODE_FUSED><<<f.part_wgs, 256, 0, s>>>(A, Q, g);
-      if (timer) timer->end(s);
+      if (ev) hipEventRecord((*ev)[2 * ei], s);
+      k_particles<MODE_FUSED, NT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
+      if (ev) { hipEventRecord((*ev)[2 * ei + 1], s); ei++; }
     }
     // grid update of this step; from step 1 on, workgroup 0 also scans the
     // keys the particle kernel counted (the step-0 kernel counts nothing and
@@ -900,17 +939,87 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
     SA.list = f.list[nwr];
     SA.list_n = f.list_n + nwr;
     SA.n_keys = g.n_keys;
-    k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(Q, g, f.list[rd], f.list_n + rd, f.won, f.tile_box, f.tiles, f.gen,
-                                               (uint32_t)(step + 1), f.vgrid, pose + (size_t)t * S * POSE_DOUBLES,
-                                               act + (size_t)t * S * 6, do_scan, SA);
+    k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.list[rd], f.list_n + rd, f.won, f.tile_box, f.tiles, f.gen,
+                                               (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA);
     if (do_scan) {
       cur ^= 1;
       rd = nrd;
       wr = nwr;
     }
   }
-  k_export<<<nblk(N, 256), 256, 0, s>>>(f.buf[cur], user, P.mats);
+  if (f.do_export) k_export<<<nblk(N, 256), 256, 0, s>>>(f.buf[cur], user, P.mats);
+}
+
+static void enqueue(FastPath& f, const StepParams& P, const PState& user, int n, const double* pose, const float* act,
+                    hipStream_t s, std::vector<hipEvent_t>* ev) {
+  if (f.part_threads == 128) enqueue_call<128>(f, P, user, n, pose, act, s, ev);
+  else enqueue_call<256>(f, P, user, n, pose, act, s, ev);
+}
+
+static void destroy_graph(FastGraph& G) {
+  if (G.exec) hipGraphExecDestroy(G.exec);
+  if (G.graph) hipGraphDestroy(G.graph);
+  for (hipEvent_t e : G.ev) hipEventDestroy(e);
+  G = FastGraph();
+}
+
+int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n, const double* pose, const float* act,
+             hipStream_t s, KernelTimer* timer) {
+  const FastGeom g = f.g;
+  if (n < 1 || n >= 65535) return -1;
+  if ((++f.calls & 0xffff) == 0) {
+    // the 16-bit epoch wraps: clear the stamps so no stale entry can match
+    launch_zero(f.claim, (size_t)g.n_keys * 4, s);
+    launch_zero(f.tile_box, (size_t)g.n_keys * 8, s);
+  }
+  k_set_word<<<1, 1, 0, s>>>(f.t0_dev, t0);
+  const bool timed = timer && timer->on;
+  if (!f.use_graph) {
+    std::vector<hipEvent_t> ev;
+    if (timed) {
+      ev.resize(2 * (size_t)(n - 1));
+      for (auto& e : ev) hipEventCreate(&e);
+    }
+    enqueue(f, P, user, n, pose, act, s, timed ? &ev : nullptr);
+    if (timed) timer->adopt(ev, n - 1, true);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  }
+  // graph mode: one captured call per (n, state pointers, launch shape),
+  // replayed with the clock taken from device memory
+  FastGraph* G = nullptr;
+  for (auto& c : f.graphs)
+    if (c.exec && c.n == n && c.x == user.x && c.mat == P.mat && c.part_threads == f.part_threads &&
+        c.part_wgs == f.part_wgs && c.grid_wgs == f.grid_wgs && c.timed == timed && c.do_export == f.do_export)
+      G = &c;
+  if (!G) {
+    FastGraph c;
+    c.n = n; c.x = user.x; c.mat = P.mat; c.part_threads = f.part_threads; c.part_wgs = f.part_wgs;
+    c.grid_wgs = f.grid_wgs; c.timed = timed; c.do_export = f.do_export;
+    if (timed) {
+      c.ev.resize(2 * (size_t)(n - 1));
+      for (auto& e : c.ev) hipEventCreate(&e);
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -3;
+    enqueue(f, P, user, n, pose, act, s, timed ? &c.ev : nullptr);
+    if (hipStreamEndCapture(s, &c.graph) != hipSuccess) { destroy_graph(c); return -3; }
+    if (hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) != hipSuccess) { destroy_graph(c); return -3; }
+    if (f.graphs.size() >= 8) { destroy_graph(f.graphs.front()); f.graphs.erase(f.graphs.begin()); }
+    f.graphs.push_back(c);
+    G = &f.graphs.back();
+  }
+  if (hipGraphLaunch(G->exec, s) != hipSuccess) return -3;
+  if (timed) timer->adopt(G->ev, n - 1);
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+void fast_destroy(FastPath& f) {
+  for (auto& c : f.graphs) destroy_graph(c);
+  f.graphs.clear();
+}
+
+void fast_invalidate(FastPath& f) {
+  for (auto& c : f.graphs) destroy_graph(c);
+  f.graphs.clear();
 }
 
 }  // namespace mpm

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <vector>
 
 namespace mpm {
 
@@ -82,6 +83,17 @@ struct KernelTimer {
     hipEventRecord(ev[2 * used + 1], s);
     used++;
   }
+  // event pairs owned elsewhere (a captured graph, or a call's temporaries
+  // with owned = true), read at the next collect()
+  std::vector<hipEvent_t> ext;
+  std::vector<char> ext_owned;
+  void adopt(const std::vector<hipEvent_t>& pairs, int n_pairs, bool owned = false) {
+    for (int i = 0; i < n_pairs && 2 * i + 1 < (int)pairs.size(); i++) {
+      ext.push_back(pairs[2 * i]);
+      ext.push_back(pairs[2 * i + 1]);
+      ext_owned.push_back(owned ? 1 : 0);
+    }
+  }
   // after the stream has been synchronised
   void collect() {
     for (int i = 0; i < used; i++) {
@@ -89,6 +101,13 @@ struct KernelTimer {
       if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) { total_ms += ms; launches++; }
     }
     used = 0;
+    for (size_t i = 0; 2 * i + 1 < ext.size(); i++) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ext[2 * i], ext[2 * i + 1]) == hipSuccess) { total_ms += ms; launches++; }
+      if (ext_owned[i]) { hipEventDestroy(ext[2 * i]); hipEventDestroy(ext[2 * i + 1]); }
+    }
+    ext.clear();
+    ext_owned.clear();
   }
   void destroy() {
     for (int i = 0; i < created; i++) { hipEventDestroy(ev[2 * i]); hipEventDestroy(ev[2 * i + 1]); }

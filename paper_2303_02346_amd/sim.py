@@ -33,7 +33,7 @@ class Simulator:
     """
 
     def __init__(self, scenes: Union[Scene, Sequence[Scene]], requires_grad: bool = False, ckpt_every: int = 16,
-                 horizon: Optional[int] = None, device: str = "cuda"):
+                 horizon: Optional[int] = None, device: str = "cuda", graph: bool = False):
         if isinstance(scenes, Scene):
             scenes = [scenes]
         self.scenes = list(scenes)
@@ -83,7 +83,9 @@ class Simulator:
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        self.stream = torch.cuda.current_stream(self.device)
+        # the library works on a stream of its own (default priority); every
+        # call first waits for torch's current stream and returns synchronised
+        self.stream = torch.cuda.Stream(self.device)
         ctx = ctypes.c_void_p()
         _lib.check(L.mpm_create(ctypes.byref(d), ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(self.ws_bytes),
                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)), "mpm_create")
@@ -97,6 +99,47 @@ class Simulator:
             acts[: sc.horizon, s] = sc.actions[: self.horizon]
         self.actions.copy_(torch.from_numpy(acts))
         self.reset()
+        if graph:
+            self.set_option(_lib.MPM_OPT_GRAPH, 1)
+
+    def _sync_in(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def set_option(self, key: int, value: int):
+        _lib.check(_lib.lib().mpm_set_option(self.ctx, int(key), int(value)), "mpm_set_option")
+
+    def get_option(self, key: int) -> int:
+        v = ctypes.c_int32(0)
+        _lib.check(_lib.lib().mpm_get_option(self.ctx, int(key), ctypes.byref(v)), "mpm_get_option")
+        return v.value
+
+    def autotune(self, n_steps: int = 20, cache: Optional[str] = None):
+        """Pick the fastest launch shape (native autotuner, mpm_autotune) for
+        this workload; with `cache`, results are stored in / read from a JSON
+        file keyed by the workload's shape and the device."""
+        import json, os
+        key = f"{torch.cuda.get_device_name(self.device)}|N={self.N}|S={self.S}|n={self.desc.n_grid}|steps={n_steps}"
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            best = table[key]
+            self.set_option(_lib.MPM_OPT_PART_THREADS, best["part_threads"])
+            self.set_option(_lib.MPM_OPT_PART_WGS, best["part_wgs"])
+            self.set_option(_lib.MPM_OPT_GRID_WGS, best["grid_wgs"])
+            return best
+        self._sync_in()
+        out = (ctypes.c_int32 * 4)()
+        _lib.check(_lib.lib().mpm_autotune(self.ctx, int(n_steps), out), "mpm_autotune", self.ctx)
+        best = {"part_threads": out[0], "part_wgs": out[1], "grid_wgs": out[2], "us_per_step": out[3]}
+        if cache:
+            table[key] = best
+            d = os.path.dirname(os.path.abspath(cache))
+            os.makedirs(d, exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return best
 
     # ---- views -------------------------------------------------------------
     @property
@@ -144,15 +187,18 @@ class Simulator:
         self.set_actions(self.actions)
 
     def set_state(self):
+        self._sync_in()
         self._state = self.state_struct()
         _lib.check(_lib.lib().mpm_set_state(self.ctx, ctypes.byref(self._state)), "mpm_set_state", self.ctx)
 
     def set_actions(self, actions: torch.Tensor, t0: int = 0):
         a = actions.to(self.device, torch.float32).reshape(-1, self.S, 6).contiguous()
+        self._sync_in()
         self._act_keep = a
         _lib.check(_lib.lib().mpm_set_actions(self.ctx, t0, a.shape[0], ctypes.c_void_p(a.data_ptr())), "mpm_set_actions", self.ctx)
 
     def step(self, n: int):
+        self._sync_in()
         _lib.check(_lib.lib().mpm_step(self.ctx, int(n)), "mpm_step", self.ctx)
 
     def clock(self) -> int:
@@ -171,6 +217,7 @@ class Simulator:
         ga = torch.zeros(T, self.S, 6, dtype=torch.float32, device=self.device)
         g0 = torch.zeros_like(gT) if want_grad0 else None
         g0s = self.state_struct(g0, with_mat=False) if want_grad0 else None
+        self._sync_in()
         _lib.check(_lib.lib().mpm_step_backward(self.ctx, ctypes.byref(gs), ctypes.c_void_p(ga.data_ptr()),
                                                 ctypes.byref(g0s) if g0s is not None else None),
                    "mpm_step_backward", self.ctx)
@@ -181,6 +228,7 @@ class Simulator:
         mu_c = (ctypes.c_float * 3)(*[float(m) for m in mu])
         g = torch.zeros(STATE_ROWS, self.N, dtype=torch.float32, device=self.device) if want_grad else None
         gs = self.state_struct(g, with_mat=False) if want_grad else None
+        self._sync_in()
         _lib.check(_lib.lib().mpm_loss_blob(self.ctx, mu_c, ctypes.c_float(sigma), ctypes.c_void_p(loss.data_ptr()),
                                             ctypes.byref(gs) if gs is not None else None), "mpm_loss_blob", self.ctx)
         return (loss, g) if want_grad else loss
