@@ -63,6 +63,100 @@ def cpu_baseline(sc, steps):
             "seconds": dt}
 
 
+def bench_batched(torch, steps=100):
+    """Config 4: 64 independent 64^3 scenes of log-uniform size in one
+    launch (graph-captured, autotuned) against the same scenes run one
+    after another, each in its own launch."""
+    from paper_2303_02346_amd import scenes
+    from paper_2303_02346_amd.sim import Simulator
+    scs = scenes.config4(steps=steps)
+    n_tot = sum(sc.n for sc in scs)
+    log(f"[bench] batched: {len(scs)} scenes, {n_tot} particles")
+    sim = Simulator(scs, graph=True)
+    tune = sim.autotune(n_steps=10)
+    sim.reset()
+    sim.step(steps)
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    sim.close()
+    singles = [Simulator(sc, graph=True) for sc in scs]
+    for s1 in singles:
+        s1.step(steps)
+        s1.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s1 in singles:
+        s1.step(steps)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    for s1 in singles:
+        s1.close()
+    out = {"scenes": len(scs), "particles": n_tot, "steps": steps, "launch": tune,
+           "batched_rate": n_tot * steps / t_b, "sequential_rate": n_tot * steps / t_s,
+           "speedup": t_s / t_b, "unit": "particle-steps/s"}
+    log(f"[bench] batched {out['batched_rate']:.3e} vs sequential {out['sequential_rate']:.3e} particle-steps/s "
+        f"(x{out['speedup']:.2f})")
+    return out
+
+
+def bench_closure(torch, steps=100, n_samples=10_000_000, epochs=4):
+    """Config 5: 1M sand particles on 256^3 with the learned cone return
+    against the exact return (step time, fallback rate, accuracy)."""
+    import numpy as np
+    from paper_2303_02346_amd import scenes
+    from paper_2303_02346_amd.closure import MLP, generate_samples
+    from paper_2303_02346_amd.sim import Simulator
+    t0 = time.perf_counter()
+    samples = generate_samples(n_samples)
+    t_gen = time.perf_counter() - t0
+    perm = torch.randperm(samples.shape[0], device=samples.device)
+    samples = samples[perm].contiguous()
+    n_tr = int(0.95 * samples.shape[0])
+    train, held = samples[:n_tr].contiguous(), samples[n_tr:].contiguous()
+    net = MLP()
+    net.init(train, seed=0)
+    t0 = time.perf_counter()
+    hist = net.train(train, epochs=epochs, batch=8192, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    y = net.predict(held)
+    err = (y - held[:, 6:9]).abs().max(1).values
+    sc = scenes.config5(steps=steps)
+    times = {}
+    pos = {}
+    stats = None
+    for mode in ("exact", "learned"):
+        sim = Simulator(sc, horizon=steps, graph=True)
+        if mode == "learned":
+            sim.set_closure(net, tol=1e-3)
+        sim.step(steps)
+        sim.reset()
+        if mode == "learned":
+            sim.closure_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        times[mode] = time.perf_counter() - t0
+        pos[mode] = sim.positions()
+        if mode == "learned":
+            stats = sim.closure_stats()
+        sim.close()
+    dx = float(np.linalg.norm(pos["learned"] - pos["exact"]) / np.linalg.norm(pos["exact"]))
+    out = {"particles": sc.n, "steps": steps, "samples": int(samples.shape[0]), "sample_seconds": t_gen,
+           "train_seconds": t_train, "train_loss": hist, "heldout_err_inf_median": float(err.median()),
+           "heldout_err_inf_p99": float(err.quantile(0.99)) if err.numel() < 16_000_000 else None,
+           "exact_ms_per_step": times["exact"] * 1e3 / steps, "learned_ms_per_step": times["learned"] * 1e3 / steps,
+           "speedup": times["exact"] / times["learned"], "accepted": stats[0], "fallback": stats[1],
+           "position_rel_diff": dx}
+    log(f"[bench] closure: exact {out['exact_ms_per_step']:.3f} ms/step, learned {out['learned_ms_per_step']:.3f} "
+        f"ms/step (x{out['speedup']:.2f}); accepted {stats[0]}, fallback {stats[1]}; position diff {dx:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,9 +164,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--bwd-steps", type=int, default=64)
     ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--adjoint", choices=["tiled", "plain"], default="tiled")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--particles", type=int, default=250_000)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--closure", action="store_true", help="also train and time the learned closure (config 5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
@@ -92,9 +191,16 @@ def main():
     n_act = active_nodes(sc.x, sc.n_grid)
 
     log(f"[bench] forward: {N} particles, {args.warmup} warmup + {args.steps} timed steps")
-    sim = Simulator(sc, requires_grad=False, horizon=max(args.steps, args.warmup))
+    sim = Simulator(sc, requires_grad=False, horizon=max(args.steps, args.warmup), graph=not args.no_graph)
+    tune = None
+    if not args.no_tune:
+        tune = sim.autotune(n_steps=min(20, args.steps))
+        log(f"[bench] autotuned launch shape: {tune}")
+    # untimed: W warm-up steps, then one call of the timed shape (captures its graph)
     sim.reset()
     sim.step(args.warmup)
+    sim.reset()
+    sim.step(args.steps)
     sim.reset()
     torch.cuda.synchronize()
     sim.timing(True)
@@ -123,8 +229,9 @@ def main():
     fwd_bwd = None
     if not args.no_bwd:
         T = args.bwd_steps
-        log(f"[bench] forward+backward: {T} steps, checkpoint every 16")
-        simg = Simulator(sc, requires_grad=True, ckpt_every=16, horizon=T)
+        log(f"[bench] forward+backward: {T} steps, checkpoint every 16, {args.adjoint} adjoint")
+        simg = Simulator(sc, requires_grad=True, ckpt_every=16, horizon=T, graph=not args.no_graph,
+                         adjoint=args.adjoint)
         for rep in range(2):
             simg.reset()
             torch.cuda.synchronize()
@@ -136,10 +243,17 @@ def main():
             t_fb = time.perf_counter() - t0
         fb_bytes = 680.0 * N * T
         fwd_bwd = {"value": N * T / t_fb, "unit": "particle-steps/s", "steps": T, "ckpt_every": 16,
+                   "adjoint": args.adjoint,
                    "ms_per_step": t_fb * 1e3 / T, "loss": float(loss.item()),
                    "grad_norm": float(ga.norm().item()),
                    "hbm_frac_algorithmic": round(fb_bytes / t_fb / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"[bench] fwd+bwd {t_fb * 1e3 / T:.3f} ms/step, {N * T / t_fb:.3e} particle-steps/s")
+
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(torch)
+
+    closure = bench_closure(torch) if args.closure else None
 
     cpu = None
     if not args.no_cpu:
@@ -155,7 +269,10 @@ def main():
                                "128^3 grid, dt=5e-5, kinematic cylinder r=0.05 with seeded smooth 6-DoF trajectory",
                    "n_particles": N, "n_grid": sc.n_grid, "dt": sc.dt, "active_nodes": n_act},
         "step_hbm_frac_algorithmic": round(step_frac, 4),
+        "launch": tune,
         "fwd_bwd": fwd_bwd,
+        "batched": batched,
+        "closure": closure,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

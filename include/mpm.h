@@ -165,14 +165,19 @@ int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out);
 int mpm_timing_enable(mpm_ctx* c, int32_t enable);
 int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name, int32_t name_len);
 
-/* Launch-shape and mode options of the forward path (mpm_step without
- * requires_grad).  Defaults: graph 0, particle workgroup 256 threads, 2048
- * particle workgroups, 2048 grid workgroups. */
+/* Launch-shape and mode options.  Defaults: graph 0, particle workgroup 256
+ * threads, 2048 particle workgroups, 2048 grid workgroups, tiled adjoint.
+ * MPM_OPT_ADJOINT selects how requires_grad contexts step and differentiate:
+ * 0 = the tiled path (forward on the tiled path, checkpoint segments
+ * recomputed on block-sorted states, tiled adjoint kernels); 1 = the plain
+ * path (one particle per thread with global atomics on a dense grid, for
+ * both the forward and the adjoint).  Both record the same checkpoints. */
 enum {
   MPM_OPT_GRAPH = 1,          /* 1: capture each call shape in a HIP graph and replay it */
   MPM_OPT_PART_THREADS = 2,   /* 128 or 256 threads per particle workgroup */
   MPM_OPT_PART_WGS = 3,       /* particle workgroups per launch (persistent, 64..65536) */
-  MPM_OPT_GRID_WGS = 4        /* grid-update workgroups per launch (64..65536) */
+  MPM_OPT_GRID_WGS = 4,       /* grid-update workgroups per launch (64..65536) */
+  MPM_OPT_ADJOINT = 5         /* 0: tiled (default), 1: plain */
 };
 int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value);
 int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value);
@@ -183,6 +188,55 @@ int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value);
  * and returns it in best[4] = {part_threads, part_wgs, grid_wgs,
  * microseconds per step}. */
 int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best);
+
+/* ---- learned closure of the Drucker-Prager cone return (sand) ----------
+ * A 6 -> 64 -> 64 -> 3 MLP (ReLU; BF16 weights, FP32 accumulation on the
+ * matrix cores) maps (log singular values of the trial F sorted descending,
+ * alpha, c, kappa) to the projected log singular values.  It is trained on
+ * samples logged from the simulator's own exact projections.  The state
+ * buffer (device, caller-owned, mpm_mlp_state_bytes()) holds the FP32 master
+ * weights, the Adam moments and the inference copy. */
+
+/* Log every exact cone-case projection of sand particles during mpm_step:
+ * records of 9 floats (log sigma_tr[3], alpha, c, kappa, projected[3]) are
+ * appended to buf_dev (capacity records) and *count_dev (device uint64) is
+ * advanced (it may exceed the capacity; records beyond it are dropped).
+ * buf_dev == NULL stops logging.  Not combined with an active closure. */
+int mpm_log_samples(mpm_ctx* c, float* buf_dev, uint64_t capacity, uint64_t* count_dev);
+
+/* Use the trained MLP (mlp_state_dev; NULL disables) for the cone case of
+ * the sand projection in mpm_step.  A prediction whose yield residual
+ * |f(eps)| + |tr eps - tr eps_tr| exceeds residual_tol falls back to the
+ * exact return.  Forward only: a requires_grad context returns MPM_ESTATE
+ * (its adjoint differentiates the exact return). */
+int mpm_set_closure(mpm_ctx* c, const void* mlp_state_dev, float residual_tol);
+
+/* Counts of closure predictions accepted and fallen back since the last read
+ * (reads reset them). */
+int mpm_closure_stats(mpm_ctx* c, uint64_t* accepted, uint64_t* fallback);
+
+size_t mpm_mlp_state_bytes(void);
+/* Scratch (device) for mpm_mlp_train / mpm_mlp_grad with this batch size. */
+size_t mpm_mlp_scratch_bytes(int32_t batch);
+/* Initialise: normalisation statistics from the n logged records in
+ * samples_dev, weights from init_params (host, MLP parameter vector of 4803
+ * floats W1 b1 W2 b2 W3 b3, row-major [out][in]) or, if NULL, a seeded
+ * He-uniform draw; zero Adam moments. */
+int mpm_mlp_init(void* state_dev, const float* samples_dev, int64_t n, const float* init_params, uint64_t seed,
+                 void* stream);
+/* Train with Adam (lr; beta 0.9/0.999) on the n records, `epochs` passes of
+ * batches of `batch` records starting at a seeded offset; loss_hist_host
+ * (may be NULL) receives the mean batch loss of each epoch. */
+int mpm_mlp_train(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, int32_t epochs, float lr,
+                  uint64_t seed, void* scratch_dev, double* loss_hist_host, void* stream);
+/* Loss (host) and parameter gradient (device, 4803 floats) on the first
+ * min(n, batch) records, without updating the weights. */
+int mpm_mlp_grad(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, void* scratch_dev,
+                 float* grad_out_dev, double* loss_out_host, void* stream);
+/* Outputs (n x 3) for n records of 9 floats (only the 6 inputs are read). */
+int mpm_mlp_predict(const void* state_dev, const float* records_dev, int64_t n, float* y_dev, void* stream);
+/* Copy the FP32 parameter vector and/or the inference blob to the host. */
+int mpm_mlp_params(const void* state_dev, float* params_host, void* blob_host, void* stream);
 
 /* Free the host context (not the borrowed device memory). */
 int mpm_destroy(mpm_ctx* c);

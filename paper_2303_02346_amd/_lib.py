@@ -33,9 +33,11 @@ class MpmDesc(ctypes.Structure):
 
 EXPORTS = ["mpm_workspace_bytes", "mpm_create", "mpm_set_state", "mpm_set_actions", "mpm_step",
            "mpm_step_backward", "mpm_loss_blob", "mpm_clock", "mpm_last_error_bits", "mpm_timing_enable",
-           "mpm_timing_read", "mpm_set_option", "mpm_get_option", "mpm_autotune", "mpm_destroy", "mpm_strerror"]
+           "mpm_timing_read", "mpm_set_option", "mpm_get_option", "mpm_autotune", "mpm_log_samples", "mpm_set_closure",
+           "mpm_closure_stats", "mpm_mlp_state_bytes", "mpm_mlp_scratch_bytes", "mpm_mlp_init", "mpm_mlp_train",
+           "mpm_mlp_grad", "mpm_mlp_predict", "mpm_mlp_params", "mpm_destroy", "mpm_strerror"]
 
-MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS = 1, 2, 3, 4
+MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS, MPM_OPT_ADJOINT = 1, 2, 3, 4, 5
 
 _lib = None
 
@@ -71,11 +73,24 @@ def lib():
     L.mpm_set_option.argtypes = [vp, i32, i32]
     L.mpm_get_option.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.mpm_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    u64, i64 = ctypes.c_uint64, ctypes.c_int64
+    L.mpm_log_samples.argtypes = [vp, vp, u64, vp]
+    L.mpm_set_closure.argtypes = [vp, vp, ctypes.c_float]
+    L.mpm_closure_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    L.mpm_mlp_state_bytes.argtypes = []
+    L.mpm_mlp_state_bytes.restype = ctypes.c_size_t
+    L.mpm_mlp_scratch_bytes.argtypes = [i32]
+    L.mpm_mlp_scratch_bytes.restype = ctypes.c_size_t
+    L.mpm_mlp_init.argtypes = [vp, vp, i64, vp, u64, vp]
+    L.mpm_mlp_train.argtypes = [vp, vp, i64, i32, i32, ctypes.c_float, u64, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.mpm_mlp_grad.argtypes = [vp, vp, i64, i32, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.mpm_mlp_predict.argtypes = [vp, vp, i64, vp, vp]
+    L.mpm_mlp_params.argtypes = [vp, vp, vp, vp]
     L.mpm_destroy.argtypes = [vp]
     L.mpm_strerror.argtypes = [ctypes.c_int]
     L.mpm_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("mpm_workspace_bytes", "mpm_strerror"):
+        if name not in ("mpm_workspace_bytes", "mpm_strerror", "mpm_mlp_state_bytes", "mpm_mlp_scratch_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

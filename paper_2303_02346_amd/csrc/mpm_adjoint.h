@@ -1,0 +1,34 @@
+// Tiled adjoint of one MLS-MPM step on a block-sorted state (mpm_adjoint.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "mpm_fast.h"
+#include "mpm_internal.h"
+
+namespace mpm {
+
+struct AdjArgs {
+  PBuf st;                   // s_t sorted by its own block key
+  const int4* list;          // its occupied blocks
+  const uint32_t* list_n;
+  int N;
+  const float* abar_next;    // adjoint of s_{t+1}, packed 25 x N
+  const uint32_t* map;       // row of particle j (s_t's order) in abar_next
+  float* abar;               // adjoint of s_t in s_t's order, packed 25 x N
+  const float4* vgrid;       // updated node velocities of step t (block layout)
+  float* tiles;              // per-block tile slots (velocity-adjoint tiles)
+  int2* tile_box;
+  const uint32_t* gen;       // stamp epoch
+  uint32_t sid;              // stamp step id of the velocity-adjoint tiles
+  const uint32_t* won;       // per list entry: neighbour blocks claimed by the recompute
+  const float4* mmv;         // node momenta and masses of step t (block layout)
+  float4* mmvb;              // their adjoints (block layout)
+};
+
+void launch_g2p_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, hipStream_t s);
+void launch_grid_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, const double* pose_t,
+                           const float* act_t, double* acc_t, hipStream_t s);
+void launch_p2g_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, hipStream_t s);
+void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, bool to_user, hipStream_t s);
+
+}  // namespace mpm

@@ -8,6 +8,7 @@
 
 #include "../../include/mpm.h"
 #include "mpm_internal.h"
+#include "mpm_adjoint.h"
 #include "mpm_fast.h"
 
 using namespace mpm;
@@ -17,9 +18,33 @@ namespace {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
+// Per-step record of a block-sorted segment state of the tiled adjoint
+// (offsets relative to the record's start).
+struct SortedRec {
+  size_t f, id, key, rank, mat, map, list, list_n, bytes;
+};
+
+SortedRec sorted_rec(size_t N, size_t n_keys) {
+  SortedRec r;
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t q = o; o += align_up(b); return q; };
+  r.f = take(STATE_FLOATS * N * sizeof(float));
+  r.id = take(N * 4);
+  r.key = take(N * 4);
+  r.rank = take(N * 4);
+  r.mat = take(N);
+  r.map = take(N * 4);
+  r.list = take(n_keys * 16);
+  r.list_n = take(16);
+  r.bytes = o;
+  return r;
+}
+
 struct Layout {
   size_t mats, offs, pscene, cyl_radius, err, mmv, vgrid, vbar, mmvb, pose, act, acc, ckpt, seg, adj0, adj1, scratch;
-  size_t fast;
+  size_t fast, cstats;
+  size_t tmp, mmv_blk, mmvb_blk;   // tiled adjoint: G2P output, node (mv, m) and their adjoints
+  SortedRec rec;
   size_t total;
   int n_ckpt;
 };
@@ -32,7 +57,8 @@ bool desc_ok(const mpm_desc* d) {
   if (d->n_scenes > 1 && !d->scene_offsets) return false;
   if (!d->cyl_radius || !d->cyl_pos0 || !d->cyl_rot0) return false;
   if (!(d->dt > 0.f) || d->horizon < 1 || d->bound < 0) return false;
-  if (d->requires_grad && d->ckpt_every < 1) return false;
+  // (the tiled adjoint hands out 2 k + 1 step stamps per 16-bit epoch)
+  if (d->requires_grad && (d->ckpt_every < 1 || d->ckpt_every > 16384)) return false;
   if (d->scene_offsets) {
     if (d->scene_offsets[0] != 0 || d->scene_offsets[d->n_scenes] != d->n_particles) return false;
     for (int s = 0; s < d->n_scenes; s++)
@@ -60,6 +86,7 @@ Layout plan(const mpm_desc* d) {
   L.pose = take((T + 1) * S * POSE_DOUBLES * sizeof(double));
   L.act = take(T * S * 6 * sizeof(float));
   L.scratch = take(64);
+  L.cstats = take(64);
   L.fast = take(fast_workspace_bytes(d->n_grid, (int)S, (int)N));
   if (d->requires_grad) {
     int k = d->ckpt_every;
@@ -68,12 +95,22 @@ Layout plan(const mpm_desc* d) {
     L.mmvb = take(nodes * sizeof(float4));
     L.acc = take(T * S * ACC_DOUBLES * sizeof(double));
     L.ckpt = take(st * L.n_ckpt);
-    L.seg = take(st * (size_t)(k + 1));
+    // the plain adjoint's k + 1 segment states and the tiled adjoint's k
+    // sorted records share one region
+    size_t n_keys = (size_t)fast_n_keys(d->n_grid, (int)S);
+    L.rec = sorted_rec(N, n_keys);
+    size_t plain_seg = st * (size_t)(k + 1), tiled_seg = L.rec.bytes * (size_t)k;
+    L.seg = take(plain_seg > tiled_seg ? plain_seg : tiled_seg);
+    L.tmp = take(L.rec.bytes);
+    L.mmv_blk = take(n_keys * 64 * sizeof(float4));
+    L.mmvb_blk = take(n_keys * 64 * sizeof(float4));
     L.adj0 = take(st);
     L.adj1 = take(st);
   } else {
     L.n_ckpt = 0;
     L.vbar = L.mmvb = L.acc = L.ckpt = L.seg = L.adj0 = L.adj1 = 0;
+    L.tmp = L.mmv_blk = L.mmvb_blk = 0;
+    L.rec = SortedRec{};
   }
   L.total = o;
   return L;
@@ -96,6 +133,7 @@ struct mpm_ctx {
   size_t state_bytes;
   FastPath fast;
   KernelTimer timer;
+  bool plain_adjoint;
 };
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_EHIP; }
@@ -169,6 +207,7 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   c->last_err_bits = 0;
   c->state_bytes = align_up(STATE_FLOATS * (size_t)d->n_particles * sizeof(float));
   c->timer.name = "k_p2g_plain";
+  c->plain_adjoint = false;
   int S = d->n_scenes;
   c->mats.resize(256);
   memset(c->mats.data(), 0, 256 * sizeof(MatDev));
@@ -207,6 +246,8 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
     launch_zero(c->ws + L.vgrid, (size_t)d->n_grid * d->n_grid * d->n_grid * S * sizeof(float4), c->stream);
     rc = fast_init(c->fast, c->ws + L.fast, d->n_grid, S, d->n_particles, c->stream);
     fast_bind_grid(c->fast, G(c, L.mmv), G(c, L.vgrid));
+    c->fast.closure_stats = (unsigned long long*)(c->ws + L.cstats);
+    if (hipMemsetAsync(c->ws + L.cstats, 0, 64, c->stream) != hipSuccess) rc = MPM_EHIP;
   }
   if (rc == MPM_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = MPM_EHIP;
   if (rc != MPM_OK) { delete c; return rc; }
@@ -270,8 +311,8 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
   const int N = c->d.n_particles;
   PState us = user_pstate(&c->user, N);
   launch_pose(c->d.n_scenes, c->t, n_steps, c->d.dt, (const float*)(c->ws + c->L.act), (double*)(c->ws + c->L.pose), c->stream);
-  c->timer.name = c->d.requires_grad ? "k_p2g_plain" : "k_g2p2g";
-  if (c->d.requires_grad) {
+  c->timer.name = (c->d.requires_grad && c->plain_adjoint) ? "k_p2g_plain" : "k_g2p2g";
+  if (c->d.requires_grad && c->plain_adjoint) {
     // plain path, recording checkpoints every k steps
     int k = c->d.ckpt_every;
     for (int t = c->t; t < c->t + n_steps; t++) {
@@ -281,6 +322,20 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
       }
       plain_step(c, P, us, us, t);
     }
+  } else if (c->d.requires_grad) {
+    // tiled path in runs that end on checkpoint boundaries
+    int k = c->d.ckpt_every;
+    for (int t = c->t; t < c->t + n_steps;) {
+      if (t % k == 0) {
+        PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)(t / k) * c->state_bytes), N);
+        launch_copy_state(us, ck, c->stream);
+      }
+      int run = k - t % k;
+      if (run > c->t + n_steps - t) run = c->t + n_steps - t;
+      int rc = fast_run(c->fast, P, us, t, run, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
+      if (rc != MPM_OK) return MPM_EHIP;
+      t += run;
+    }
   } else {
     int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
     if (rc != MPM_OK) return rc;
@@ -288,6 +343,86 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
   c->t += n_steps;
   if (hipGetLastError() != hipSuccess) return MPM_EHIP;
   return finish(c);
+}
+
+// The k block-sorted records of a segment, and the G2P output record.
+static SortedState sorted_state(mpm_ctx* c, size_t base) {
+  const SortedRec& r = c->L.rec;
+  char* b = c->ws + base;
+  SortedState S;
+  S.b.f = (float*)(b + r.f);
+  S.b.id = (uint32_t*)(b + r.id);
+  S.b.key = (uint32_t*)(b + r.key);
+  S.b.rank = (uint32_t*)(b + r.rank);
+  S.b.mat = (uint8_t*)(b + r.mat);
+  S.list = (int4*)(b + r.list);
+  S.list_n = (uint32_t*)(b + r.list_n);
+  return S;
+}
+static uint32_t* sorted_map(mpm_ctx* c, size_t base) { return (uint32_t*)(c->ws + base + c->L.rec.map); }
+
+// Tiled adjoint over all segments, last first.  On entry a_cur holds the
+// adjoint of the final state in user order; on return it holds the adjoint
+// of the initial state in user order (a_cur / a_nxt swapped as needed).
+static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState& a_nxt, double* acc) {
+  FastPath& f = c->fast;
+  const int N = c->d.n_particles, T = c->t, k = c->d.ckpt_every;
+  hipStream_t s = c->stream;
+  const size_t rb = c->L.rec.bytes;
+  SortedState tmp = sorted_state(c, c->L.tmp);
+  float4* mmv_blk = G(c, c->L.mmv_blk);
+  float4* mmvb_blk = G(c, c->L.mmvb_blk);
+  const int n_seg = (T + k - 1) / k;
+  for (int seg = n_seg - 1; seg >= 0; seg--) {
+    const int ts = seg * k, te = ts + k < T ? ts + k : T;
+    // recompute: sorted s_ts .. s_{te-1}
+    PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)seg * c->state_bytes), N);
+    SortedState S0 = sorted_state(c, c->L.seg);
+    fast_sort_user(f, P, ck, S0, s);
+    for (int t = ts; t < te - 1; t++) {
+      const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
+      SortedState Si = sorted_state(c, bi), Sn = sorted_state(c, bi + rb);
+      const uint32_t sid = fast_next_sid(f);
+      fast_p2g(f, P, Si, sid, s);
+      fast_grid(f, P, Si, sid, t, pose_at(c, 0), act_at(c, 0), nullptr, s);
+      fast_g2p(f, P, Si, tmp.b, s);
+      fast_sort_next(f, P, Si, tmp.b, Sn, sorted_map(c, bi), s);
+    }
+    // adjoint, step te-1 down to ts; the adjoint of s_te is in user order,
+    // read through s_{te-1}'s ids, the later ones through the recorded maps
+    for (int t = te - 1; t >= ts; t--) {
+      const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
+      SortedState Si = sorted_state(c, bi);
+      const uint32_t sid_f = fast_next_sid(f);
+      fast_p2g(f, P, Si, sid_f, s);
+      fast_grid(f, P, Si, sid_f, t, pose_at(c, 0), act_at(c, 0), mmv_blk, s);
+      AdjArgs A;
+      A.st = Si.b;
+      A.list = Si.list;
+      A.list_n = Si.list_n;
+      A.N = N;
+      A.abar_next = a_cur.x;
+      A.map = (t == te - 1) ? Si.b.id : sorted_map(c, bi);
+      A.abar = a_nxt.x;
+      A.vgrid = f.vgrid;
+      A.tiles = f.tiles;
+      A.tile_box = f.tile_box;
+      A.gen = f.gen;
+      A.sid = fast_next_sid(f);
+      A.won = f.won;
+      A.mmv = mmv_blk;
+      A.mmvb = mmvb_blk;
+      launch_g2p_adj_tiled(A, P, f.g, f.part_wgs, s);
+      launch_grid_adj_tiled(A, P, f.g, f.grid_wgs, pose_at(c, t), act_at(c, t),
+                            acc + (size_t)t * c->d.n_scenes * ACC_DOUBLES, s);
+      launch_p2g_adj_tiled(A, P, f.g, f.part_wgs, s);
+      PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
+    }
+    // back to user order for the previous segment
+    launch_adj_reorder(a_cur.x, a_nxt.x, S0.b.id, N, true, s);
+    PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
+  }
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
 }
 
 int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_dev, mpm_state* grad_0) {
@@ -313,6 +448,11 @@ int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_d
   double* acc = (double*)(c->ws + c->L.acc);
   launch_zero(acc, align_up((size_t)T * S * ACC_DOUBLES * sizeof(double)), s);
   int n_seg = (T + k - 1) / k;
+  if (!c->plain_adjoint) {
+    int rc = backward_tiled(c, P, a_cur, a_nxt, acc);
+    if (rc != MPM_OK) return rc;
+    n_seg = 0;
+  }
   for (int seg = n_seg - 1; seg >= 0; seg--) {
     int ts = seg * k, te = ts + k < T ? ts + k : T;
     PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)seg * c->state_bytes), N);
@@ -388,6 +528,10 @@ int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value) {
       if (value < 64 || value > 65536) return MPM_EINVAL;
       c->fast.grid_wgs = value;
       return MPM_OK;
+    case MPM_OPT_ADJOINT:
+      if (value != 0 && value != 1) return MPM_EINVAL;
+      c->plain_adjoint = value == 1;
+      return MPM_OK;
     default: return MPM_EINVAL;
   }
 }
@@ -399,6 +543,7 @@ int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value) {
     case MPM_OPT_PART_THREADS: *value = c->fast.part_threads; return MPM_OK;
     case MPM_OPT_PART_WGS: *value = c->fast.part_wgs; return MPM_OK;
     case MPM_OPT_GRID_WGS: *value = c->fast.grid_wgs; return MPM_OK;
+    case MPM_OPT_ADJOINT: *value = c->plain_adjoint ? 1 : 0; return MPM_OK;
     default: return MPM_EINVAL;
   }
 }
@@ -457,6 +602,37 @@ int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best) {
   best[3] = (int32_t)(best_ms * 1000.f / n_steps);
   int frc = finish(c);
   return frc == MPM_OK ? MPM_OK : frc;
+}
+
+size_t mpm_mlp_blob_offset(void);
+
+int mpm_log_samples(mpm_ctx* c, float* buf_dev, uint64_t capacity, uint64_t* count_dev) {
+  if (!c) return MPM_EINVAL;
+  if (buf_dev && (!count_dev || capacity == 0)) return MPM_EINVAL;
+  if (buf_dev && c->fast.mlp_blob) return MPM_ESTATE;
+  c->fast.log_buf = buf_dev;
+  c->fast.log_count = (unsigned long long*)count_dev;
+  c->fast.log_cap = buf_dev ? capacity : 0;
+  return MPM_OK;
+}
+
+int mpm_set_closure(mpm_ctx* c, const void* mlp_state_dev, float residual_tol) {
+  if (!c || (mlp_state_dev && !(residual_tol >= 0.f))) return MPM_EINVAL;
+  if (mlp_state_dev && (c->fast.log_buf || c->d.requires_grad)) return MPM_ESTATE;
+  c->fast.mlp_blob = mlp_state_dev ? (const void*)((const char*)mlp_state_dev + mpm_mlp_blob_offset()) : nullptr;
+  c->fast.closure_tol = residual_tol;
+  return MPM_OK;
+}
+
+int mpm_closure_stats(mpm_ctx* c, uint64_t* accepted, uint64_t* fallback) {
+  if (!c || !accepted || !fallback) return MPM_EINVAL;
+  unsigned long long h[2] = {0, 0};
+  if (hipMemcpyAsync(h, c->fast.closure_stats, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return MPM_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return MPM_EHIP;
+  *accepted = h[0];
+  *fallback = h[1];
+  if (hipMemsetAsync(c->fast.closure_stats, 0, sizeof(h), c->stream) != hipSuccess) return MPM_EHIP;
+  return hip_ok(hipStreamSynchronize(c->stream));
 }
 
 int mpm_timing_enable(mpm_ctx* c, int32_t enable) {

@@ -1,0 +1,95 @@
+// Block keys of the tiled path (4^3-node grid blocks keyed by scene and the
+// Morton code of the block coordinates) and the wavefront-level rank
+// reservation used by the counting sort of the particles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "mpm_fast.h"
+
+namespace mpm {
+
+__host__ __device__ inline uint32_t spread3(uint32_t v) {
+  v &= 0x3ff;
+  v = (v | (v << 16)) & 0x030000FF;
+  v = (v | (v << 8)) & 0x0300F00F;
+  v = (v | (v << 4)) & 0x030C30C3;
+  v = (v | (v << 2)) & 0x09249249;
+  return v;
+}
+__host__ __device__ inline uint32_t compact3(uint32_t v) {
+  v &= 0x09249249;
+  v = (v | (v >> 2)) & 0x030C30C3;
+  v = (v | (v >> 4)) & 0x0300F00F;
+  v = (v | (v >> 8)) & 0x030000FF;
+  v = (v | (v >> 16)) & 0x000003FF;
+  return v;
+}
+__device__ inline uint32_t block_key(const FastGeom& g, int s, int bx, int by, int bz) {
+  return ((uint32_t)s << (3 * g.kb)) | (spread3(bx) << 2) | (spread3(by) << 1) | spread3(bz);
+}
+__device__ inline void key_decode(const FastGeom& g, uint32_t key, int& s, int& bx, int& by, int& bz) {
+  s = (int)(key >> (3 * g.kb));
+  uint32_t m = key & ((1u << (3 * g.kb)) - 1u);
+  bx = (int)compact3(m >> 2);
+  by = (int)compact3(m >> 1);
+  bz = (int)compact3(m);
+}
+
+// Rank of each lane's key among equal keys of the wavefront, in two phases
+// so that the global atomic's latency overlaps other work: rank_issue groups
+// the lanes by key (ballots only) and lets one leader lane per distinct key
+// reserve the group's range; rank_finish broadcasts the leader's base.
+// Every lane of the wave must call both.
+struct WaveRank {
+  int leader;
+  uint32_t prefix;
+  uint32_t lbase;
+};
+__device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid) {
+  const int lane = __lane_id();
+  unsigned long long pending = __ballot(valid);
+  WaveRank R;
+  R.leader = lane;
+  R.prefix = 0;
+  R.lbase = 0;
+  uint32_t lcount = 0;
+  while (pending) {
+    int leader = __ffsll((long long)pending) - 1;
+    uint32_t k = __shfl(key, leader);
+    unsigned long long m = __ballot(valid && key == k) & pending;
+    if ((m >> lane) & 1ull) { R.leader = leader; R.prefix = (uint32_t)__popcll(m & ((1ull << lane) - 1ull)); }
+    if (lane == leader) lcount = (uint32_t)__popcll(m);
+    pending &= ~m;
+  }
+  if (lcount > 0) R.lbase = atomicAdd(&counts[key], lcount);
+  return R;
+}
+__device__ inline uint32_t rank_finish(const WaveRank& R) { return __shfl(R.lbase, R.leader) + R.prefix; }
+
+// Rank of each lane's key among equal keys, with one global atomic per
+// distinct key of the wavefront.  Every lane of the wave must call it.
+__device__ inline uint32_t wave_rank(uint32_t* counts, uint32_t key, bool valid) {
+  const int lane = __lane_id();
+  unsigned long long pending = __ballot(valid);
+  uint32_t myrank = 0;
+  while (pending) {
+    int leader = __ffsll((long long)pending) - 1;
+    uint32_t k = __shfl(key, leader);
+    unsigned long long m = __ballot(valid && key == k) & pending;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if ((m >> lane) & 1ull) myrank = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    pending &= ~m;
+  }
+  return myrank;
+}
+
+__device__ inline void load_state(const PBuf& b, int N, int j, float* x, float* v, float* C, float* F, float& J) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) { x[a] = b.f[a * (size_t)N + j]; v[a] = b.f[(3 + a) * (size_t)N + j]; }
+#pragma unroll
+  for (int k = 0; k < 9; k++) C[k] = b.f[(6 + k) * (size_t)N + j];
+}
+
+}  // namespace mpm

@@ -41,6 +41,9 @@ struct FastGraph {
   bool timed = false, do_export = true;
   const float* x = nullptr;
   const uint8_t* mat = nullptr;
+  const void* mlp = nullptr;
+  const float* log = nullptr;
+  float tol = 0.f;
   std::vector<hipEvent_t> ev;   // fused-kernel event pairs recorded by the graph
 };
 
@@ -66,19 +69,54 @@ struct FastPath {
   bool use_graph;          // capture each call shape once and replay it
   bool do_export;          // write the result back to the user arrays
   std::vector<FastGraph> graphs;
+  // learned closure (device MLP blob, residual tolerance, counters) and
+  // cone-case sample logging
+  const void* mlp_blob;
+  float closure_tol;
+  unsigned long long* closure_stats;
+  float* log_buf;
+  unsigned long long* log_count;
+  unsigned long long log_cap;
   int grid_wgs, part_wgs;
   // plain dense grid (shared with the adjoint path), unused here
   float4* mmv;
   float4* vdense;
   bool valid;
+  uint32_t sid;            // last step id handed out under the current epoch
+};
+
+// A state sorted by the block key of its own positions (the tiled adjoint
+// keeps one per step of a checkpoint segment).
+struct SortedState {
+  PBuf b;                  // f (25 x N), id (user index), key, rank, mat
+  int4* list;              // occupied blocks {key, offset, count, 0}
+  uint32_t* list_n;
 };
 
 size_t fast_workspace_bytes(int n_grid, int n_scenes, int N);
+int fast_n_keys(int n_grid, int n_scenes);
 int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_t s);
 void fast_bind_grid(FastPath& f, float4* mmv, float4* vgrid);
 void fast_invalidate(FastPath& f);
 int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n, const double* pose, const float* act,
              hipStream_t s, KernelTimer* timer);
 void fast_destroy(FastPath& f);
+
+// Building blocks of the tiled adjoint.  fast_sort_user sorts a user-order
+// state (and starts a new stamp epoch); fast_sort_next sorts the state that
+// fast_g2p produced from `prev` (same row order as prev) and records in
+// map[j] the new row of prev's row j.  fast_p2g / fast_grid / fast_g2p run
+// one forward step's parts on a sorted state: P2G tiles and block claims
+// under step id `sid` (from fast_next_sid), the grid update of step t (and,
+// with mmv_out, the node momenta and masses in block layout), and G2P into
+// `out` in the same row order.
+uint32_t fast_next_sid(FastPath& f);
+void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s);
+void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, const PBuf& next, SortedState& out,
+                    uint32_t* map, hipStream_t s);
+void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, hipStream_t s);
+void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
+               const float* act_base, float4* mmv_out, hipStream_t s);
+void fast_g2p(FastPath& f, const StepParams& P, const SortedState& st, const PBuf& out, hipStream_t s);
 
 }  // namespace mpm

@@ -25,7 +25,9 @@
 #include <math.h>
 #include <vector>
 #include "mpm_fast.h"
+#include "mpm_blocks.h"
 #include "mpm_math.h"
+#include "mpm_mlp.h"
 #include "mpm_phys.h"
 
 namespace mpm {
@@ -33,90 +35,6 @@ namespace mpm {
 namespace {
 
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-__host__ __device__ inline uint32_t spread3(uint32_t v) {
-  v &= 0x3ff;
-  v = (v | (v << 16)) & 0x030000FF;
-  v = (v | (v << 8)) & 0x0300F00F;
-  v = (v | (v << 4)) & 0x030C30C3;
-  v = (v | (v << 2)) & 0x09249249;
-  return v;
-}
-__host__ __device__ inline uint32_t compact3(uint32_t v) {
-  v &= 0x09249249;
-  v = (v | (v >> 2)) & 0x030C30C3;
-  v = (v | (v >> 4)) & 0x0300F00F;
-  v = (v | (v >> 8)) & 0x030000FF;
-  v = (v | (v >> 16)) & 0x000003FF;
-  return v;
-}
-__device__ inline uint32_t block_key(const FastGeom& g, int s, int bx, int by, int bz) {
-  return ((uint32_t)s << (3 * g.kb)) | (spread3(bx) << 2) | (spread3(by) << 1) | spread3(bz);
-}
-__device__ inline void key_decode(const FastGeom& g, uint32_t key, int& s, int& bx, int& by, int& bz) {
-  s = (int)(key >> (3 * g.kb));
-  uint32_t m = key & ((1u << (3 * g.kb)) - 1u);
-  bx = (int)compact3(m >> 2);
-  by = (int)compact3(m >> 1);
-  bz = (int)compact3(m);
-}
-
-// Rank of each lane's key among equal keys of the wavefront, in two phases
-// so that the global atomic's latency overlaps other work: rank_issue groups
-// the lanes by key (ballots only) and lets one leader lane per distinct key
-// reserve the group's range; rank_finish broadcasts the leader's base.
-// Every lane of the wave must call both.
-struct WaveRank {
-  int leader;
-  uint32_t prefix;
-  uint32_t lbase;
-};
-__device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid) {
-  const int lane = __lane_id();
-  unsigned long long pending = __ballot(valid);
-  WaveRank R;
-  R.leader = lane;
-  R.prefix = 0;
-  R.lbase = 0;
-  uint32_t lcount = 0;
-  while (pending) {
-    int leader = __ffsll((long long)pending) - 1;
-    uint32_t k = __shfl(key, leader);
-    unsigned long long m = __ballot(valid && key == k) & pending;
-    if ((m >> lane) & 1ull) { R.leader = leader; R.prefix = (uint32_t)__popcll(m & ((1ull << lane) - 1ull)); }
-    if (lane == leader) lcount = (uint32_t)__popcll(m);
-    pending &= ~m;
-  }
-  if (lcount > 0) R.lbase = atomicAdd(&counts[key], lcount);
-  return R;
-}
-__device__ inline uint32_t rank_finish(const WaveRank& R) { return __shfl(R.lbase, R.leader) + R.prefix; }
-
-// Rank of each lane's key among equal keys, with one global atomic per
-// distinct key of the wavefront.  Every lane of the wave must call it.
-__device__ inline uint32_t wave_rank(uint32_t* counts, uint32_t key, bool valid) {
-  const int lane = __lane_id();
-  unsigned long long pending = __ballot(valid);
-  uint32_t myrank = 0;
-  while (pending) {
-    int leader = __ffsll((long long)pending) - 1;
-    uint32_t k = __shfl(key, leader);
-    unsigned long long m = __ballot(valid && key == k) & pending;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if ((m >> lane) & 1ull) myrank = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    pending &= ~m;
-  }
-  return myrank;
-}
-
-__device__ inline void load_state(const PBuf& b, int N, int j, float* x, float* v, float* C, float* F, float& J) {
-#pragma unroll
-  for (int a = 0; a < 3; a++) { x[a] = b.f[a * (size_t)N + j]; v[a] = b.f[(3 + a) * (size_t)N + j]; }
-#pragma unroll
-  for (int k = 0; k < 9; k++) C[k] = b.f[(6 + k) * (size_t)N + j];
-}
 
 }  // namespace
 
@@ -265,6 +183,43 @@ __global__ __launch_bounds__(256) void k_permute(PState u, const uint8_t* __rest
   X.mat[d] = umat[p];
 }
 
+// block key and rank of the state produced from a sorted state (same rows);
+// the scene comes from the previous key
+__global__ __launch_bounds__(256) void k_keys_next(const float* __restrict__ xf, const uint32_t* __restrict__ key_prev,
+                                                   int N, StepParams P, FastGeom g, uint32_t* __restrict__ counts,
+                                                   uint32_t* __restrict__ key_tmp, uint32_t* __restrict__ rank_tmp) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  bool has = p < N;
+  uint32_t key = 0;
+  if (has) {
+    float x[3] = {xf[p], xf[(size_t)N + p], xf[2 * (size_t)N + p]};
+    const uint32_t sc = key_prev[p] >> (3 * g.kb);
+    Stencil S;
+    if (!stencil_setup(x, P, S) || sc >= (uint32_t)g.S) atomicOr(P.err, ERR_OUTSIDE);
+    else key = block_key(g, (int)sc, S.base[0] >> 2, S.base[1] >> 2, S.base[2] >> 2);
+  }
+  uint32_t r = wave_rank(counts, key, has);
+  if (has) { key_tmp[p] = key; rank_tmp[p] = r; }
+}
+
+// move the rows of `in` to their sorted slots in `out`; map[p] = new row of p
+__global__ __launch_bounds__(256) void k_sort_permute(PBuf in, PBuf out, int N, const uint32_t* __restrict__ key_tmp,
+                                                      const uint32_t* __restrict__ rank_tmp,
+                                                      const uint32_t* __restrict__ offsets, uint32_t* __restrict__ map) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  uint32_t key = key_tmp[p], r = rank_tmp[p];
+  uint32_t d = offsets[key] + r;
+  if (d >= (uint32_t)N) return;
+#pragma unroll
+  for (int k = 0; k < STATE_FLOATS; k++) out.f[k * (size_t)N + d] = in.f[k * (size_t)N + p];
+  out.id[d] = in.id[p];
+  out.mat[d] = in.mat[p];
+  out.key[d] = key;
+  out.rank[d] = r;
+  map[p] = d;
+}
+
 // scatter the sorted buffer back to the user arrays; liquids keep the user's
 // F and solids the user's J (those rows are not carried by the kernels)
 __global__ __launch_bounds__(256) void k_export(PBuf X, PState u, const MatDev* __restrict__ mats) {
@@ -305,11 +260,28 @@ struct PartArgs {
   const uint32_t* gen;         // per-call epoch
   uint32_t step_id;            // 1-based step within the call
   const float4* vgrid;
+  // learned closure and sample logging (sand, cone case)
+  const MlpBlob* mlp;
+  float closure_tol;
+  unsigned long long* closure_stats;   // [0] accepted, [1] fell back to the exact return
+  float* log_buf;                      // samples of 9 floats: log sigma_tr (desc), alpha, c, kappa, eps'
+  unsigned long long* log_count;
+  unsigned long long log_cap;
 };
 
-template <int MODE, int NT>
+enum { FEAT_NONE = 0, FEAT_LOG = 1, FEAT_CLOSURE = 2 };
+
+template <int MODE, int NT, int FEAT>
 __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, FastGeom g) {
   constexpr int NW = NT / 64;
+  __shared__ MlpBlob s_mlp;
+  __shared__ MlpScratch s_mscr[NW];
+  if (FEAT == FEAT_CLOSURE) {
+    const uint32_t* src = (const uint32_t*)A.mlp;
+    uint32_t* dstw = (uint32_t*)&s_mlp;
+    for (int q = threadIdx.x; q < (int)(sizeof(MlpBlob) / 4); q += NT) dstw[q] = src[q];
+    __syncthreads();
+  }
   __shared__ float s_tile[4 * TILE_NODES];
   __shared__ int s_itile[4 * TILE_NODES];
   __shared__ float4 s_v[VT_NODES];
@@ -370,6 +342,10 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
       }
       float tau[9];
       bool have_tau = false;
+      // cone-case sample of this particle (closure input and exact answer)
+      bool cone = false;
+      float xin[MLP_IN] = {0, 0, 0, 0, 0, 0}, eex[MLP_OUT] = {0, 0, 0};
+      double Uk[9], Vk[9];
       // ---------------- G2P of the previous step ----------------
       if (MODE != MODE_P2G && has) {
         Stencil S;
@@ -437,6 +413,18 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
               double e[3] = {log(s[0]), log(s[1]), log(s[2])}, ep[3];
               DPInfo I;
               dp_project(e, M, ep, I);
+              if (FEAT != FEAT_NONE && I.cse == 2) {
+                cone = true;
+#pragma unroll
+                for (int a = 0; a < 3; a++) { xin[a] = (float)e[a]; eex[a] = (float)ep[a]; }
+                xin[3] = M.alpha;
+                xin[4] = M.coh;
+                xin[5] = M.kappa;
+                if (FEAT == FEAT_CLOSURE) {
+#pragma unroll
+                  for (int k = 0; k < 9; k++) { Uk[k] = Uu[k]; Vk[k] = V[k]; }
+                }
+              }
               double gg[3], Fo[9];
               if (I.cse == 0) {
 #pragma unroll
@@ -488,6 +476,75 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
           O.mat[dst] = (uint8_t)m;
         } else {
           ok = false;
+        }
+      }
+      if (FEAT == FEAT_LOG) {
+        // append the exact cone-case samples, one counter atomic per wavefront
+        const unsigned long long m = __ballot(cone);
+        if (m) {
+          const int lane = __lane_id();
+          const int leader = __ffsll((long long)m) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(A.log_count, (unsigned long long)__popcll(m));
+          base = __shfl(base, leader);
+          if (cone) {
+            const unsigned long long idx = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+            if (idx < A.log_cap) {
+              float* o = A.log_buf + idx * 9;
+#pragma unroll
+              for (int q = 0; q < MLP_IN; q++) o[q] = xin[q];
+#pragma unroll
+              for (int q = 0; q < MLP_OUT; q++) o[MLP_IN + q] = eex[q];
+            }
+          }
+        }
+      }
+      if (FEAT == FEAT_CLOSURE) {
+        // learned cone return on the matrix cores for the wave's cone-case
+        // lanes; a prediction whose yield residual exceeds the tolerance
+        // falls back to the exact return already in F and tau
+        const unsigned long long m = __ballot(cone);
+        if (m) {
+          float yp[MLP_OUT];
+          mlp_wave_forward(s_mlp, xin, yp, s_mscr[tid >> 6]);
+          bool accepted = false;
+          if (cone) {
+            const double c = (double)xin[4], ka = (double)xin[5] * (double)xin[3];
+            double es[3] = {yp[0] - c, yp[1] - c, yp[2] - c};
+            const double tr = es[0] + es[1] + es[2];
+            const double d0 = es[0] - tr / 3.0, d1 = es[1] - tr / 3.0, d2 = es[2] - tr / 3.0;
+            const double f = sqrt(d0 * d0 + d1 * d1 + d2 * d2) + ka * tr;
+            const double r = fabs(f) + fabs(((double)yp[0] + yp[1] + yp[2]) - ((double)xin[0] + xin[1] + xin[2]));
+            accepted = r <= (double)A.closure_tol && isfinite(r);
+            if (accepted) {
+              double gg[3] = {exp((double)yp[0]), exp((double)yp[1]), exp((double)yp[2])}, Fo[9];
+              usv(Uk, gg, Vk, Fo);
+#pragma unroll
+              for (int k = 0; k < 9; k++) F[k] = (float)Fo[k];
+              if (MODE == MODE_FUSED) {
+                const double trp = (double)yp[0] + yp[1] + yp[2];
+                double h[3];
+#pragma unroll
+                for (int a = 0; a < 3; a++) h[a] = 2.0 * (double)M.mu * yp[a] + (double)M.lam * trp;
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+#pragma unroll
+                  for (int jj = 0; jj < 3; jj++)
+                    tau[i * 3 + jj] = (float)(Uk[i * 3] * h[0] * Uk[jj * 3] + Uk[i * 3 + 1] * h[1] * Uk[jj * 3 + 1] +
+                                              Uk[i * 3 + 2] * h[2] * Uk[jj * 3 + 2]);
+              }
+              // the corrected F goes to the output slot written above
+              if (dst < (uint32_t)N) {
+#pragma unroll
+                for (int k = 0; k < 9; k++) A.out.f[(15 + k) * (size_t)N + dst] = F[k];
+              }
+            }
+          }
+          const unsigned long long acc = __ballot(accepted);
+          if (__lane_id() == 0) {
+            atomicAdd(A.closure_stats, (unsigned long long)__popcll(acc));
+            atomicAdd(A.closure_stats + 1, (unsigned long long)(__popcll(m) - __popcll(acc)));
+          }
         }
       }
       // ---------------- P2G of this step ----------------
@@ -716,7 +773,7 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const in
                                               const uint32_t* __restrict__ gen, uint32_t step_id,
                                               float4* __restrict__ vgrid, const double* __restrict__ pose_base,
                                               const float* __restrict__ act_base, const int* __restrict__ t0_dev,
-                                              int do_scan, ScanArgs SA) {
+                                              int do_scan, ScanArgs SA, int t_fixed, float4* __restrict__ mmv_out) {
   if (do_scan && blockIdx.x == 0) {
     scan_keys<256>(SA.counts, SA.offsets, SA.list, SA.list_n, SA.n_keys);
     return;
@@ -724,7 +781,8 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const in
   const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
   // the clock lives in device memory so that a captured call can be replayed
   // at any start time: this launch is step (step_id - 1) of the call
-  const size_t t = (size_t)t0_dev[0] + step_id - 1;
+  // (the adjoint's recompute passes its step explicitly in t_fixed)
+  const size_t t = t_fixed >= 0 ? (size_t)t_fixed : (size_t)t0_dev[0] + step_id - 1;
   const double* pose_t = pose_base + t * g.S * POSE_DOUBLES;
   const float* act_t = act_base + t * g.S * 6;
   const uint32_t n_list = list_n[0];
@@ -778,6 +836,7 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const in
         out = make_float4(vv[0], vv[1], vv[2], acc.w);
       }
       vgrid[(size_t)key * 64 + lane] = out;
+      if (mmv_out) mmv_out[(size_t)key * 64 + lane] = (out.w > 0.f) ? acc : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
 }
@@ -832,6 +891,7 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
 }
 
 size_t fast_workspace_bytes(int n_grid, int n_scenes, int N) { return fast_plan(n_grid, n_scenes, N).total; }
+int fast_n_keys(int n_grid, int n_scenes) { return make_geom(n_grid, n_scenes).n_keys; }
 
 static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
@@ -863,10 +923,17 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.part_threads = 256;
   f.use_graph = false;
   f.do_export = true;
+  f.mlp_blob = nullptr;
+  f.closure_tol = 1e-3f;
+  f.closure_stats = nullptr;
+  f.log_buf = nullptr;
+  f.log_count = nullptr;
+  f.log_cap = 0;
   f.part_wgs = 2048;
   f.calls = 0;
   f.grid_wgs = 2048;
   f.valid = false;
+  f.sid = 0;
   // zero the bookkeeping (counts, stamps, counters, velocity grid)
   launch_zero(ws + L.counts, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.list_n, 256, s);
@@ -881,9 +948,19 @@ void fast_bind_grid(FastPath& f, float4* mmv, float4* vgrid) { f.mmv = mmv; f.vd
 
 __global__ void k_set_word(int* w, int v) { w[0] = v; }
 
+// Every import scan advances the device epoch of the step stamps by one; the
+// host counts them so that the 16-bit epoch's wrap clears the stamps first.
+static void new_epoch(FastPath& f, hipStream_t s) {
+  if ((++f.calls & 0xffff) == 0) {
+    launch_zero(f.claim, (size_t)f.g.n_keys * 4, s);
+    launch_zero(f.tile_box, (size_t)f.g.n_keys * 8, s);
+  }
+  f.sid = 0;
+}
+
 // Enqueue one call of n steps: import (sort by block), n steps, export.  With
 // `ev` the fused kernel's launches are bracketed by the given event pairs.
-template <int NT>
+template <int NT, int FEAT>
 static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, int n, const double* pose,
                          const float* act, hipStream_t s, std::vector<hipEvent_t>* ev) {
   const FastGeom g = f.g;
@@ -902,6 +979,12 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   A.n_keys = g.n_keys;
   A.claim = f.claim;
   A.won = f.won;
+  A.mlp = (const MlpBlob*)f.mlp_blob;
+  A.closure_tol = f.closure_tol;
+  A.closure_stats = f.closure_stats;
+  A.log_buf = f.log_buf;
+  A.log_count = f.log_count;
+  A.log_cap = f.log_cap;
   // Bookkeeping: `rd` is the list describing buf[cur] (the buffer the next
   // particle kernel reads); `wr` is the list describing the order in which
   // the current offsets place particles (the buffer the next kernel writes).
@@ -913,15 +996,15 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     A.list_n = f.list_n + rd;
     A.step_id = (uint32_t)(step + 1);
     if (step == n) {
-      k_particles<MODE_G2P, NT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
+      k_particles<MODE_G2P, NT, FEAT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
       cur ^= 1;
       break;
     }
     if (step == 0) {
-      k_particles<MODE_P2G, NT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
+      k_particles<MODE_P2G, NT, FEAT_NONE><<<f.part_wgs, NT, 0, s>>>(A, P, g);
     } else {
       if (ev) hipEventRecord((*ev)[2 * ei], s);
-      k_particles<MODE_FUSED, NT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
+      k_particles<MODE_FUSED, NT, FEAT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
       if (ev) { hipEventRecord((*ev)[2 * ei + 1], s); ei++; }
     }
     // grid update of this step; from step 1 on, workgroup 0 also scans the
@@ -940,7 +1023,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     SA.list_n = f.list_n + nwr;
     SA.n_keys = g.n_keys;
     k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.list[rd], f.list_n + rd, f.won, f.tile_box, f.tiles, f.gen,
-                                               (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA);
+                                               (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA, -1, nullptr);
     if (do_scan) {
       cur ^= 1;
       rd = nrd;
@@ -952,8 +1035,10 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
 
 static void enqueue(FastPath& f, const StepParams& P, const PState& user, int n, const double* pose, const float* act,
                     hipStream_t s, std::vector<hipEvent_t>* ev) {
-  if (f.part_threads == 128) enqueue_call<128>(f, P, user, n, pose, act, s, ev);
-  else enqueue_call<256>(f, P, user, n, pose, act, s, ev);
+  if (f.mlp_blob) enqueue_call<256, FEAT_CLOSURE>(f, P, user, n, pose, act, s, ev);
+  else if (f.log_buf) enqueue_call<256, FEAT_LOG>(f, P, user, n, pose, act, s, ev);
+  else if (f.part_threads == 128) enqueue_call<128, FEAT_NONE>(f, P, user, n, pose, act, s, ev);
+  else enqueue_call<256, FEAT_NONE>(f, P, user, n, pose, act, s, ev);
 }
 
 static void destroy_graph(FastGraph& G) {
@@ -967,11 +1052,7 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
              hipStream_t s, KernelTimer* timer) {
   const FastGeom g = f.g;
   if (n < 1 || n >= 65535) return -1;
-  if ((++f.calls & 0xffff) == 0) {
-    // the 16-bit epoch wraps: clear the stamps so no stale entry can match
-    launch_zero(f.claim, (size_t)g.n_keys * 4, s);
-    launch_zero(f.tile_box, (size_t)g.n_keys * 8, s);
-  }
+  new_epoch(f, s);
   k_set_word<<<1, 1, 0, s>>>(f.t0_dev, t0);
   const bool timed = timer && timer->on;
   if (!f.use_graph) {
@@ -989,12 +1070,14 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   FastGraph* G = nullptr;
   for (auto& c : f.graphs)
     if (c.exec && c.n == n && c.x == user.x && c.mat == P.mat && c.part_threads == f.part_threads &&
-        c.part_wgs == f.part_wgs && c.grid_wgs == f.grid_wgs && c.timed == timed && c.do_export == f.do_export)
+        c.part_wgs == f.part_wgs && c.grid_wgs == f.grid_wgs && c.timed == timed && c.do_export == f.do_export &&
+        c.mlp == f.mlp_blob && c.log == f.log_buf && c.tol == f.closure_tol)
       G = &c;
   if (!G) {
     FastGraph c;
     c.n = n; c.x = user.x; c.mat = P.mat; c.part_threads = f.part_threads; c.part_wgs = f.part_wgs;
     c.grid_wgs = f.grid_wgs; c.timed = timed; c.do_export = f.do_export;
+    c.mlp = f.mlp_blob; c.log = f.log_buf; c.tol = f.closure_tol;
     if (timed) {
       c.ev.resize(2 * (size_t)(n - 1));
       for (auto& e : c.ev) hipEventCreate(&e);
@@ -1010,6 +1093,65 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   if (hipGraphLaunch(G->exec, s) != hipSuccess) return -3;
   if (timed) timer->adopt(G->ev, n - 1);
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+uint32_t fast_next_sid(FastPath& f) { return ++f.sid; }
+
+void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s) {
+  const int N = f.N;
+  new_epoch(f, s);
+  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.counts, f.key_tmp, f.rank_tmp);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen);
+  k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, out.b, f.key_tmp, f.rank_tmp, f.offsets);
+}
+
+void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, const PBuf& next, SortedState& out,
+                    uint32_t* map, hipStream_t s) {
+  const int N = f.N;
+  new_epoch(f, s);
+  k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen);
+  k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
+}
+
+static PartArgs sorted_args(FastPath& f, const SortedState& st, uint32_t sid) {
+  PartArgs A = {};
+  A.in = st.b;
+  A.out = st.b;
+  A.N = f.N;
+  A.list = st.list;
+  A.list_n = st.list_n;
+  A.offsets = f.offsets;
+  A.counts = f.counts;
+  A.tiles = f.tiles;
+  A.tile_box = f.tile_box;
+  A.n_keys = f.g.n_keys;
+  A.claim = f.claim;
+  A.won = f.won;
+  A.gen = f.gen;
+  A.step_id = sid;
+  A.vgrid = f.vgrid;
+  return A;
+}
+
+void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, hipStream_t s) {
+  PartArgs A = sorted_args(f, st, sid);
+  k_particles<MODE_P2G, 256, FEAT_NONE><<<f.part_wgs, 256, 0, s>>>(A, P, f.g);
+}
+
+void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
+               const float* act_base, float4* mmv_out, hipStream_t s) {
+  ScanArgs SA = {};
+  k_grid<<<f.grid_wgs, 256, 0, s>>>(P, f.g, st.list, st.list_n, f.won, f.tile_box, f.tiles, f.gen, sid, f.vgrid,
+                                    pose_base, act_base, f.t0_dev, 0, SA, t, mmv_out);
+}
+
+// the G2P kernel writes row j to offsets[key[j]] + rank[j], which is j itself
+// while the offsets are those of st's own sort (the latest one)
+void fast_g2p(FastPath& f, const StepParams& P, const SortedState& st, const PBuf& out, hipStream_t s) {
+  PartArgs A = sorted_args(f, st, 0);
+  A.out = out;
+  k_particles<MODE_G2P, 256, FEAT_NONE><<<f.part_wgs, 256, 0, s>>>(A, P, f.g);
 }
 
 void fast_destroy(FastPath& f) {

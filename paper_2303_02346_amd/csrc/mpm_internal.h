@@ -31,7 +31,7 @@ struct PState {
 // Floats per particle in a packed state buffer (x, v, C, F, J).
 constexpr int STATE_FLOATS = 25;
 
-inline PState packed_state(float* base, int N) {
+__host__ __device__ inline PState packed_state(float* base, int N) {
   PState s;
   s.x = base;
   s.v = base + 3 * (size_t)N;

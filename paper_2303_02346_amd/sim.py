@@ -33,7 +33,7 @@ class Simulator:
     """
 
     def __init__(self, scenes: Union[Scene, Sequence[Scene]], requires_grad: bool = False, ckpt_every: int = 16,
-                 horizon: Optional[int] = None, device: str = "cuda", graph: bool = False):
+                 horizon: Optional[int] = None, device: str = "cuda", graph: bool = False, adjoint: str = "tiled"):
         if isinstance(scenes, Scene):
             scenes = [scenes]
         self.scenes = list(scenes)
@@ -101,6 +101,9 @@ class Simulator:
         self.reset()
         if graph:
             self.set_option(_lib.MPM_OPT_GRAPH, 1)
+        if adjoint not in ("tiled", "plain"):
+            raise ValueError("adjoint must be 'tiled' or 'plain'")
+        self.set_option(_lib.MPM_OPT_ADJOINT, 1 if adjoint == "plain" else 0)
 
     def _sync_in(self):
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
@@ -232,6 +235,26 @@ class Simulator:
         _lib.check(_lib.lib().mpm_loss_blob(self.ctx, mu_c, ctypes.c_float(sigma), ctypes.c_void_p(loss.data_ptr()),
                                             ctypes.byref(gs) if gs is not None else None), "mpm_loss_blob", self.ctx)
         return (loss, g) if want_grad else loss
+
+    def log_samples(self, buf: Optional[torch.Tensor], count: Optional[torch.Tensor] = None):
+        """Log exact cone-case projections into buf (float32, (cap, 9));
+        count is a device uint64 tensor of one element.  None stops."""
+        L = _lib.lib()
+        if buf is None:
+            _lib.check(L.mpm_log_samples(self.ctx, None, 0, None), "mpm_log_samples")
+            return
+        _lib.check(L.mpm_log_samples(self.ctx, ctypes.c_void_p(buf.data_ptr()), ctypes.c_uint64(buf.shape[0]),
+                                     ctypes.c_void_p(count.data_ptr())), "mpm_log_samples")
+
+    def set_closure(self, mlp=None, tol: float = 1e-3):
+        """Use a trained closure.MLP for the sand cone return (None: exact)."""
+        ptr = ctypes.c_void_p(mlp.state.data_ptr()) if mlp is not None else None
+        _lib.check(_lib.lib().mpm_set_closure(self.ctx, ptr, ctypes.c_float(tol)), "mpm_set_closure")
+
+    def closure_stats(self):
+        a, f = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _lib.check(_lib.lib().mpm_closure_stats(self.ctx, ctypes.byref(a), ctypes.byref(f)), "mpm_closure_stats")
+        return a.value, f.value
 
     def timing(self, enable: bool):
         _lib.check(_lib.lib().mpm_timing_enable(self.ctx, 1 if enable else 0), "mpm_timing_enable")

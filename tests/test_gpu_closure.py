@@ -1,0 +1,132 @@
+"""GPU tests of the learned Drucker-Prager closure: the matrix-core MLP
+forward and the FP32 backward against the FP64 oracle network, the sample
+logger against the oracle's exact return, training, and the closure inside
+the simulator with its exact fallback."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as MO
+from oracle import mpm_oracle as O
+from paper_2303_02346_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def synthetic_records(n, seed=0):
+    """Cone-case records drawn directly (for network-only tests)."""
+    rng = np.random.default_rng(seed)
+    rec = np.zeros((n, 9), np.float32)
+    e = np.sort(rng.normal(0, 0.03, (n, 3)), axis=1)[:, ::-1]
+    rec[:, 0:3] = e
+    rec[:, 3] = [O.dp_alpha(p) for p in rng.uniform(20, 40, n)]
+    rec[:, 4] = rng.uniform(0, 0.01, n)
+    rec[:, 5] = rng.uniform(2, 4.5, n)
+    ep, _ = MO.exact_return(rec)
+    rec[:, 6:9] = ep
+    return rec
+
+
+def test_mfma_forward_matches_oracle():
+    from paper_2303_02346_amd.closure import MLP
+    rec = torch.from_numpy(synthetic_records(5000)).cuda()
+    net = MLP()
+    net.init(rec, seed=3)
+    y = net.predict(rec).double().cpu().numpy()
+    p, norm, pb = net.params()
+    yref, _ = MO.forward(pb, norm, rec[:, :6].double().cpu().numpy())
+    yref = yref.numpy()
+    e = rel(y - norm["out_mean"], yref - norm["out_mean"])
+    say(f"  MFMA forward vs FP64 oracle (BF16 weights): rel err {e:.2e}")
+    assert e < 2e-2
+
+
+def test_mlp_gradient_vs_oracle():
+    from paper_2303_02346_amd.closure import MLP
+    rec = torch.from_numpy(synthetic_records(2048, seed=1)).cuda()
+    net = MLP()
+    net.init(rec, seed=4)
+    loss, g = net.grad(rec, batch=2048)
+    p, norm, pb = net.params()
+    Lref, gref = MO.loss_and_grad(pb, norm, rec.double().cpu().numpy())
+    e = rel(g.double().cpu().numpy(), gref)
+    say(f"  loss gpu {loss:.6f} oracle {Lref:.6f}; gradient rel err {e:.2e}")
+    assert abs(loss - Lref) <= 2e-2 * Lref
+    assert e < 5e-2
+
+
+def test_logged_samples_are_exact_returns():
+    from paper_2303_02346_amd.closure import sand_scene
+    from paper_2303_02346_amd.sim import Simulator
+    sc = sand_scene(0, n_particles=20000, n_grid=48, steps=30)
+    sim = Simulator(sc)
+    buf = torch.zeros(500000, 9, dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sim.log_samples(buf, cnt)
+    sim.step(30)
+    n = int(cnt.item())
+    say(f"  logged {n} cone-case samples from 20k particles x 30 steps")
+    assert n > 1000
+    rec = buf[: min(n, buf.shape[0])].double().cpu().numpy()
+    ep, case = MO.exact_return(rec)
+    assert (case == 2).mean() > 0.99
+    e = np.abs(ep - rec[:, 6:9]).max()
+    say(f"  max |logged - oracle exact return| {e:.2e}")
+    assert e < 1e-6
+
+
+def test_training_and_closure_in_the_simulator():
+    """Train on logged samples, then run the closure inside the simulator
+    against the exact return.  The trained network must take over a larger
+    share of the cone-case returns than an untrained one (which the residual
+    check rejects), and the rollout must stay within the stated accuracy
+    (positions within 1e-3 relative of the exact-return rollout)."""
+    from paper_2303_02346_amd.closure import MLP, generate_samples, sand_scene
+    from paper_2303_02346_amd.sim import Simulator
+    t0 = time.time()
+    samples = generate_samples(400_000, max_scenes=4, steps=60)
+    say(f"  generated {samples.shape[0]} samples in {time.time() - t0:.1f} s")
+    assert samples.shape[0] > 10000
+    perm = torch.randperm(samples.shape[0], device="cuda")
+    samples = samples[perm].contiguous()
+    n_tr = int(0.9 * samples.shape[0])
+    train, held = samples[:n_tr].contiguous(), samples[n_tr:].contiguous()
+    net = MLP()
+    net.init(train, seed=0)
+    raw = MLP()
+    raw.init(train, seed=0)
+    hist = net.train(train, epochs=6, batch=4096, lr=2e-3)
+    say(f"  training loss by epoch {['%.3e' % h for h in hist]}")
+    assert hist[-1] < 0.2 * hist[0]
+    y = net.predict(held).double().cpu().numpy()
+    h = held.double().cpu().numpy()
+    err = np.abs(y - h[:, 6:9]).max(1)
+    r = MO.yield_residual(y, h)
+    say(f"  held-out |eps_pred - eps_exact|_inf: median {np.median(err):.2e}, p99 {np.quantile(err, 0.99):.2e}; "
+        f"residual <= 1e-3 for {(r <= 1e-3).mean() * 100:.1f}%")
+    # closure inside the simulator against the exact projection
+    sc = sand_scene(99, n_particles=60000, n_grid=64, steps=40)
+    exact = Simulator(sc)
+    exact.step(40)
+    shares = {}
+    for name, m in (("trained", net), ("untrained", raw)):
+        learned = Simulator(sc)
+        learned.set_closure(m, tol=1e-3)
+        learned.step(40)
+        acc, fb = learned.closure_stats()
+        ex = rel(learned.positions(), exact.positions())
+        shares[name] = acc / max(acc + fb, 1)
+        say(f"  {name} closure: {acc} predictions accepted, {fb} fell back; position rel diff vs exact {ex:.2e}")
+        assert acc + fb > 0
+        assert ex < 1e-3
+    assert shares["trained"] > shares["untrained"]

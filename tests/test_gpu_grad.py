@@ -32,12 +32,13 @@ def sim_of(sc, **kw):
     return Simulator(sc, **kw)
 
 
-def test_config3_gradient_vs_oracle():
+@pytest.mark.parametrize("adjoint", ["tiled", "plain"])
+def test_config3_gradient_vs_oracle(adjoint):
     with open(GOLDEN) as f:
         gold = json.load(f)
     sc = scenes.config3()
-    say("config 3 gradient (100k particles, 64 steps, checkpoint 16)")
-    sim = sim_of(sc, requires_grad=True, ckpt_every=16)
+    say(f"config 3 gradient (100k particles, 64 steps, checkpoint 16), {adjoint} adjoint")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=16, adjoint=adjoint)
     sim.step(64)
     loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
     ga = sim.backward(g[0:3], torch.zeros_like(g[0:3]))[:, 0].double().cpu().numpy()
@@ -74,6 +75,26 @@ def test_autograd_function_matches_direct_backward():
     e2 = rel(acts2.grad[:, 0].double().cpu().numpy(), gref.numpy())
     say(f"  torch-side loss grad rel err vs oracle {e2:.2e}")
     assert e2 <= 1e-4
+
+
+def test_tiled_adjoint_matches_plain_multi_segment():
+    """Both adjoints on a scene with every material, contact and ragged
+    checkpoint segments (13 steps, k = 5): action and initial-state
+    gradients agree to FP32 summation-order differences."""
+    sc = scenes.tiny(n_particles=2000, n_grid=32, steps=13, seed=7)
+    out = {}
+    for mode in ("tiled", "plain"):
+        sim = sim_of(sc, requires_grad=True, ckpt_every=5, adjoint=mode)
+        sim.step(13)
+        loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
+        ga, g0 = sim.backward(g[0:3], torch.zeros_like(g[0:3]), want_grad0=True)
+        out[mode] = (loss.item(), ga.double().cpu().numpy(), g0.double().cpu().numpy())
+    ea = rel(out["tiled"][1], out["plain"][1])
+    ex = rel(out["tiled"][2][0:3], out["plain"][2][0:3])
+    ev = rel(out["tiled"][2][3:6], out["plain"][2][3:6])
+    say(f"  tiled vs plain: actions {ea:.2e}, dL/dx0 {ex:.2e}, dL/dv0 {ev:.2e}")
+    assert abs(out["tiled"][0] - out["plain"][0]) <= 1e-5 * abs(out["plain"][0])
+    assert ea <= 1e-4 and ex <= 1e-4 and ev <= 1e-4
 
 
 def test_gradient_finite_difference_fp32():

@@ -153,11 +153,12 @@ def test_nonfinite_error_is_reported():
 # ---------------------------------------------------------------------------
 # gradients
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("adjoint", ["tiled", "plain"])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_gradient_tiny_vs_oracle(seed):
+def test_gradient_tiny_vs_oracle(seed, adjoint):
     sc = scenes.tiny(n_particles=90, n_grid=16, steps=8, seed=seed)
-    say(f"gradient tiny seed {seed}")
-    sim = sim_of(sc, requires_grad=True, ckpt_every=3)
+    say(f"gradient tiny seed {seed}, {adjoint} adjoint")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=3, adjoint=adjoint)
     sim.step(sc.horizon)
     loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
     ga = sim.backward(g[0:3], torch.zeros_like(g[0:3]))[:, 0].double().cpu().numpy()
@@ -169,12 +170,13 @@ def test_gradient_tiny_vs_oracle(seed):
     assert e <= 1e-4
 
 
-def test_gradient_state0_vs_oracle():
+@pytest.mark.parametrize("adjoint", ["tiled", "plain"])
+def test_gradient_state0_vs_oracle(adjoint):
     """dL/dx_0 and dL/dv_0 through the full adjoint (P2G/G2P weights,
     stresses, contact) against oracle autograd."""
     sc = scenes.tiny(n_particles=90, n_grid=16, steps=5, seed=2)
-    say("gradient wrt initial state")
-    sim = sim_of(sc, requires_grad=True, ckpt_every=2)
+    say(f"gradient wrt initial state, {adjoint} adjoint")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=2, adjoint=adjoint)
     sim.step(sc.horizon)
     loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
     ga, g0 = sim.backward(g[0:3], torch.zeros_like(g[0:3]), want_grad0=True)
