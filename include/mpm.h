@@ -161,7 +161,9 @@ int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out);
  * (the particle kernel that carries the transfer traffic) is bracketed by
  * HIP events on the context's stream; elapsed times are summed when a call
  * synchronises.  mpm_timing_read returns the accumulated time, the number of
- * timed launches and the kernel's name, and resets the counters. */
+ * timed launches and the kernel's name, and resets the counters.  While
+ * timing is enabled, calls run without graph capture (MPM_OPT_GRAPH is
+ * ignored) so that the events bracket the launches themselves. */
 int mpm_timing_enable(mpm_ctx* c, int32_t enable);
 int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name, int32_t name_len);
 

@@ -1054,8 +1054,10 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   if (n < 1 || n >= 65535) return -1;
   new_epoch(f, s);
   k_set_word<<<1, 1, 0, s>>>(f.t0_dev, t0);
+  // a timed call runs eagerly: its per-launch events bracket real launches
+  // (events recorded inside a captured graph do not give elapsed times here)
   const bool timed = timer && timer->on;
-  if (!f.use_graph) {
+  if (!f.use_graph || timed) {
     std::vector<hipEvent_t> ev;
     if (timed) {
       ev.resize(2 * (size_t)(n - 1));
@@ -1078,12 +1080,8 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
     c.n = n; c.x = user.x; c.mat = P.mat; c.part_threads = f.part_threads; c.part_wgs = f.part_wgs;
     c.grid_wgs = f.grid_wgs; c.timed = timed; c.do_export = f.do_export;
     c.mlp = f.mlp_blob; c.log = f.log_buf; c.tol = f.closure_tol;
-    if (timed) {
-      c.ev.resize(2 * (size_t)(n - 1));
-      for (auto& e : c.ev) hipEventCreate(&e);
-    }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -3;
-    enqueue(f, P, user, n, pose, act, s, timed ? &c.ev : nullptr);
+    enqueue(f, P, user, n, pose, act, s, nullptr);
     if (hipStreamEndCapture(s, &c.graph) != hipSuccess) { destroy_graph(c); return -3; }
     if (hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) != hipSuccess) { destroy_graph(c); return -3; }
     if (f.graphs.size() >= 8) { destroy_graph(f.graphs.front()); f.graphs.erase(f.graphs.begin()); }
@@ -1091,7 +1089,6 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
     G = &f.graphs.back();
   }
   if (hipGraphLaunch(G->exec, s) != hipSuccess) return -3;
-  if (timed) timer->adopt(G->ev, n - 1);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

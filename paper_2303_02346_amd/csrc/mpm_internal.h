@@ -94,16 +94,19 @@ struct KernelTimer {
       ext_owned.push_back(owned ? 1 : 0);
     }
   }
-  // after the stream has been synchronised
+  // after the stream has been synchronised; a failed query is skipped and
+  // its error cleared so that it does not surface at an unrelated call
   void collect() {
     for (int i = 0; i < used; i++) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) { total_ms += ms; launches++; }
+      else (void)hipGetLastError();
     }
     used = 0;
     for (size_t i = 0; 2 * i + 1 < ext.size(); i++) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ext[2 * i], ext[2 * i + 1]) == hipSuccess) { total_ms += ms; launches++; }
+      else (void)hipGetLastError();
       if (ext_owned[i]) { hipEventDestroy(ext[2 * i]); hipEventDestroy(ext[2 * i + 1]); }
     }
     ext.clear();
