@@ -47,8 +47,10 @@ __device__ inline float4 stage_node(const float4* __restrict__ src, const FastGe
 // adjoint.  Writes the direct part of the state adjoint of s_t (x, F, J; the
 // v and C adjoints of s_t come only through P2G and are added later).
 // ---------------------------------------------------------------------------
+// (two workgroups per CU: a few spilled registers cost less than the
+// latency that one wavefront per SIMD leaves exposed)
 template <int NT>
-__global__ __launch_bounds__(NT) void k_g2p_adj_tiled(AdjArgs A, StepParams P, FastGeom g) {
+__global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P, FastGeom g) {
   constexpr int NW = NT / 64;
   constexpr int NQ = 3;   // velocity adjoint components
   __shared__ float4 s_v[VT_NODES];
@@ -409,17 +411,20 @@ __global__ __launch_bounds__(NT) void k_p2g_adj_tiled(AdjArgs A, StepParams P, F
       if (lv[0] < 0 || lv[1] < 0 || lv[2] < 0 || lv[0] > VT - 3 || lv[1] > VT - 3 || lv[2] > VT - 3) continue;
       const MatDev& M = P.mats[A.st.mat[j]];
       float v[3] = {st.v[j], st.v[(size_t)N + j], st.v[2 * (size_t)N + j]};
-      float C[9], F[9];
+      float C[9];
 #pragma unroll
       for (int k = 0; k < 9; k++) C[k] = st.C[k * (size_t)N + j];
       float tau[9];
       const float Jv = st.J[j];
+      // one FP64 SVD serves the stress and its adjoint
+      double Fd[9], U[9], sv[3], V[9];
       if (M.kind == KIND_LIQUID) {
         stress_liquid(Jv, C, M, tau);
       } else {
 #pragma unroll
-        for (int k = 0; k < 9; k++) F[k] = st.F[k * (size_t)N + j];
-        stress_solid(F, M, tau);
+        for (int k = 0; k < 9; k++) Fd[k] = (double)st.F[k * (size_t)N + j];
+        svd3(Fd, U, sv, V);
+        stress_solid_usv(Fd, U, sv, V, M, tau);
       }
       float Am[9];
       const float scl = -P.dt * M.vol * 4.f * P.inv_dx * P.inv_dx;
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(NT) void k_p2g_adj_tiled(AdjArgs A, StepParams P, F
       for (int k = 0; k < 9; k++) { taub[k] = scl * Ab[k]; Cb[k] = M.mass * Ab[k]; }
       float Jb = 0.f;
       if (M.kind == KIND_LIQUID) stress_liquid_adjoint(Jv, C, M, taub, Jb, Cb);
-      else stress_solid_adjoint(F, M, taub, Fb);
+      else stress_solid_adjoint_usv(Fd, U, sv, V, M, taub, Fb);
       float* ab = A.abar;
 #pragma unroll
       for (int a = 0; a < 3; a++) { ab[a * (size_t)N + j] += xb[a]; ab[(3 + a) * (size_t)N + j] += vb[a]; }

@@ -21,13 +21,19 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 // Per-step record of a block-sorted segment state of the tiled adjoint
 // (offsets relative to the record's start).
 struct SortedRec {
-  size_t f, id, key, rank, mat, map, list, list_n, bytes;
+  size_t f, id, key, rank, mat, map, list, list_n, vgrid, mmv, won, bytes;
+  bool has_grid;
 };
 
-SortedRec sorted_rec(size_t N, size_t n_keys) {
+// with_grid: the record also keeps its step's grid for the adjoint
+SortedRec sorted_rec(size_t N, size_t n_keys, bool with_grid) {
   SortedRec r;
+  r.has_grid = with_grid;
   size_t o = 0;
   auto take = [&](size_t b) { size_t q = o; o += align_up(b); return q; };
+  r.vgrid = with_grid ? take(n_keys * 64 * sizeof(float4)) : 0;
+  r.mmv = with_grid ? take(n_keys * 64 * sizeof(float4)) : 0;
+  r.won = with_grid ? take(n_keys * 4) : 0;
   r.f = take(STATE_FLOATS * N * sizeof(float));
   r.id = take(N * 4);
   r.key = take(N * 4);
@@ -43,8 +49,8 @@ SortedRec sorted_rec(size_t N, size_t n_keys) {
 struct Layout {
   size_t mats, offs, pscene, cyl_radius, err, mmv, vgrid, vbar, mmvb, pose, act, acc, ckpt, seg, adj0, adj1, scratch;
   size_t fast, cstats;
-  size_t tmp, mmv_blk, mmvb_blk;   // tiled adjoint: G2P output, node (mv, m) and their adjoints
-  SortedRec rec;
+  size_t tmp, mmvb_blk;   // tiled adjoint: G2P output, node adjoints of (mv, m)
+  SortedRec rec, tmp_rec;
   size_t total;
   int n_ckpt;
 };
@@ -98,19 +104,19 @@ Layout plan(const mpm_desc* d) {
     // the plain adjoint's k + 1 segment states and the tiled adjoint's k
     // sorted records share one region
     size_t n_keys = (size_t)fast_n_keys(d->n_grid, (int)S);
-    L.rec = sorted_rec(N, n_keys);
+    L.rec = sorted_rec(N, n_keys, true);
+    L.tmp_rec = sorted_rec(N, n_keys, false);
     size_t plain_seg = st * (size_t)(k + 1), tiled_seg = L.rec.bytes * (size_t)k;
     L.seg = take(plain_seg > tiled_seg ? plain_seg : tiled_seg);
-    L.tmp = take(L.rec.bytes);
-    L.mmv_blk = take(n_keys * 64 * sizeof(float4));
+    L.tmp = take(L.tmp_rec.bytes);
     L.mmvb_blk = take(n_keys * 64 * sizeof(float4));
     L.adj0 = take(st);
     L.adj1 = take(st);
   } else {
     L.n_ckpt = 0;
     L.vbar = L.mmvb = L.acc = L.ckpt = L.seg = L.adj0 = L.adj1 = 0;
-    L.tmp = L.mmv_blk = L.mmvb_blk = 0;
-    L.rec = SortedRec{};
+    L.tmp = L.mmvb_blk = 0;
+    L.rec = L.tmp_rec = SortedRec{};
   }
   L.total = o;
   return L;
@@ -346,10 +352,13 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
 }
 
 // The k block-sorted records of a segment, and the G2P output record.
-static SortedState sorted_state(mpm_ctx* c, size_t base) {
-  const SortedRec& r = c->L.rec;
+static SortedState sorted_state(mpm_ctx* c, size_t base, bool tmp = false) {
+  const SortedRec& r = tmp ? c->L.tmp_rec : c->L.rec;
   char* b = c->ws + base;
   SortedState S;
+  S.vgrid = r.has_grid ? (float4*)(b + r.vgrid) : nullptr;
+  S.mmv = r.has_grid ? (float4*)(b + r.mmv) : nullptr;
+  S.won = r.has_grid ? (uint32_t*)(b + r.won) : nullptr;
   S.b.f = (float*)(b + r.f);
   S.b.id = (uint32_t*)(b + r.id);
   S.b.key = (uint32_t*)(b + r.key);
@@ -369,33 +378,32 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
   const int N = c->d.n_particles, T = c->t, k = c->d.ckpt_every;
   hipStream_t s = c->stream;
   const size_t rb = c->L.rec.bytes;
-  SortedState tmp = sorted_state(c, c->L.tmp);
-  float4* mmv_blk = G(c, c->L.mmv_blk);
+  SortedState tmp = sorted_state(c, c->L.tmp, true);
   float4* mmvb_blk = G(c, c->L.mmvb_blk);
   const int n_seg = (T + k - 1) / k;
   for (int seg = n_seg - 1; seg >= 0; seg--) {
     const int ts = seg * k, te = ts + k < T ? ts + k : T;
-    // recompute: sorted s_ts .. s_{te-1}
+    // recompute: sorted s_ts .. s_{te-1}, each with its step's grid
     PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)seg * c->state_bytes), N);
     SortedState S0 = sorted_state(c, c->L.seg);
     fast_sort_user(f, P, ck, S0, s);
-    for (int t = ts; t < te - 1; t++) {
+    for (int t = ts; t < te; t++) {
       const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
-      SortedState Si = sorted_state(c, bi), Sn = sorted_state(c, bi + rb);
+      SortedState Si = sorted_state(c, bi);
       const uint32_t sid = fast_next_sid(f);
       fast_p2g(f, P, Si, sid, s);
-      fast_grid(f, P, Si, sid, t, pose_at(c, 0), act_at(c, 0), nullptr, s);
-      fast_g2p(f, P, Si, tmp.b, s);
-      fast_sort_next(f, P, Si, tmp.b, Sn, sorted_map(c, bi), s);
+      fast_grid(f, P, Si, sid, t, pose_at(c, 0), act_at(c, 0), s);
+      if (t + 1 < te) {
+        SortedState Sn = sorted_state(c, bi + rb);
+        fast_g2p(f, P, Si, tmp.b, s);
+        fast_sort_next(f, P, Si, tmp.b, Sn, sorted_map(c, bi), s);
+      }
     }
     // adjoint, step te-1 down to ts; the adjoint of s_te is in user order,
     // read through s_{te-1}'s ids, the later ones through the recorded maps
     for (int t = te - 1; t >= ts; t--) {
       const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
       SortedState Si = sorted_state(c, bi);
-      const uint32_t sid_f = fast_next_sid(f);
-      fast_p2g(f, P, Si, sid_f, s);
-      fast_grid(f, P, Si, sid_f, t, pose_at(c, 0), act_at(c, 0), mmv_blk, s);
       AdjArgs A;
       A.st = Si.b;
       A.list = Si.list;
@@ -404,13 +412,13 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
       A.abar_next = a_cur.x;
       A.map = (t == te - 1) ? Si.b.id : sorted_map(c, bi);
       A.abar = a_nxt.x;
-      A.vgrid = f.vgrid;
+      A.vgrid = Si.vgrid;
       A.tiles = f.tiles;
       A.tile_box = f.tile_box;
       A.gen = f.gen;
       A.sid = fast_next_sid(f);
-      A.won = f.won;
-      A.mmv = mmv_blk;
+      A.won = Si.won;
+      A.mmv = Si.mmv;
       A.mmvb = mmvb_blk;
       launch_g2p_adj_tiled(A, P, f.g, f.part_wgs, s);
       launch_grid_adj_tiled(A, P, f.g, f.grid_wgs, pose_at(c, t), act_at(c, t),

@@ -66,23 +66,11 @@ __device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid
 }
 __device__ inline uint32_t rank_finish(const WaveRank& R) { return __shfl(R.lbase, R.leader) + R.prefix; }
 
-// Rank of each lane's key among equal keys, with one global atomic per
-// distinct key of the wavefront.  Every lane of the wave must call it.
+// Rank of each lane's key among equal keys of the wavefront, with one global
+// atomic per distinct key, all issued together (one round trip however many
+// distinct keys the wavefront holds).  Every lane of the wave must call it.
 __device__ inline uint32_t wave_rank(uint32_t* counts, uint32_t key, bool valid) {
-  const int lane = __lane_id();
-  unsigned long long pending = __ballot(valid);
-  uint32_t myrank = 0;
-  while (pending) {
-    int leader = __ffsll((long long)pending) - 1;
-    uint32_t k = __shfl(key, leader);
-    unsigned long long m = __ballot(valid && key == k) & pending;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if ((m >> lane) & 1ull) myrank = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    pending &= ~m;
-  }
-  return myrank;
+  return rank_finish(rank_issue(counts, key, valid));
 }
 
 __device__ inline void load_state(const PBuf& b, int N, int j, float* x, float* v, float* C, float* F, float& J) {

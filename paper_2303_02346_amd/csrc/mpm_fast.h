@@ -91,6 +91,12 @@ struct SortedState {
   PBuf b;                  // f (25 x N), id (user index), key, rank, mat
   int4* list;              // occupied blocks {key, offset, count, 0}
   uint32_t* list_n;
+  // the step's grid, kept for the adjoint (block layout; NULL = the path's
+  // shared arrays): updated velocities and masses, node momenta and masses,
+  // and the per-entry masks of the blocks claimed by its P2G
+  float4* vgrid;
+  float4* mmv;
+  uint32_t* won;
 };
 
 size_t fast_workspace_bytes(int n_grid, int n_scenes, int N);
@@ -107,16 +113,16 @@ void fast_destroy(FastPath& f);
 // fast_g2p produced from `prev` (same row order as prev) and records in
 // map[j] the new row of prev's row j.  fast_p2g / fast_grid / fast_g2p run
 // one forward step's parts on a sorted state: P2G tiles and block claims
-// under step id `sid` (from fast_next_sid), the grid update of step t (and,
-// with mmv_out, the node momenta and masses in block layout), and G2P into
-// `out` in the same row order.
+// under step id `sid` (from fast_next_sid), the grid update of step t (with
+// st.mmv, also the node momenta and masses), and G2P into `out` in the same
+// row order.
 uint32_t fast_next_sid(FastPath& f);
 void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s);
 void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, const PBuf& next, SortedState& out,
                     uint32_t* map, hipStream_t s);
 void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, hipStream_t s);
 void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
-               const float* act_base, float4* mmv_out, hipStream_t s);
+               const float* act_base, hipStream_t s);
 void fast_g2p(FastPath& f, const StepParams& P, const SortedState& st, const PBuf& out, hipStream_t s);
 
 }  // namespace mpm

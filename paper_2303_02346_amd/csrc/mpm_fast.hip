@@ -1124,10 +1124,10 @@ static PartArgs sorted_args(FastPath& f, const SortedState& st, uint32_t sid) {
   A.tile_box = f.tile_box;
   A.n_keys = f.g.n_keys;
   A.claim = f.claim;
-  A.won = f.won;
+  A.won = st.won ? st.won : f.won;
   A.gen = f.gen;
   A.step_id = sid;
-  A.vgrid = f.vgrid;
+  A.vgrid = st.vgrid ? st.vgrid : f.vgrid;
   return A;
 }
 
@@ -1137,10 +1137,10 @@ void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t 
 }
 
 void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
-               const float* act_base, float4* mmv_out, hipStream_t s) {
+               const float* act_base, hipStream_t s) {
   ScanArgs SA = {};
-  k_grid<<<f.grid_wgs, 256, 0, s>>>(P, f.g, st.list, st.list_n, f.won, f.tile_box, f.tiles, f.gen, sid, f.vgrid,
-                                    pose_base, act_base, f.t0_dev, 0, SA, t, mmv_out);
+  k_grid<<<f.grid_wgs, 256, 0, s>>>(P, f.g, st.list, st.list_n, st.won ? st.won : f.won, f.tile_box, f.tiles, f.gen,
+                                    sid, st.vgrid ? st.vgrid : f.vgrid, pose_base, act_base, f.t0_dev, 0, SA, t, st.mmv);
 }
 
 // the G2P kernel writes row j to offsets[key[j]] + rank[j], which is j itself

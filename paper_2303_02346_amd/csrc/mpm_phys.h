@@ -79,11 +79,9 @@ MPM_DI void stress_liquid_adjoint(float J, const float* C, const MatDev& M, cons
 // Solids, FP64 inside: fixed corotated tau = 2 mu (F - R) F^T + lam J (J-1) I
 // with R = U V^T; Hencky tau = U diag(2 mu eps + lam tr eps) U^T, eps = log s.
 // Returns false when a sand singular value is not positive.
-MPM_DI bool stress_solid(const float* Ff, const MatDev& M, float* tau) {
-  double F[9], U[9], s[3], V[9];
-#pragma unroll
-  for (int k = 0; k < 9; k++) F[k] = (double)Ff[k];
-  svd3(F, U, s, V);
+// The stress from a given signed SVD F = U diag(s) V^T of the FP64 copy F.
+MPM_DI bool stress_solid_usv(const double* F, const double* U, const double* s, const double* V, const MatDev& M,
+                             float* tau) {
   if (M.kind == KIND_ELASTIC) {
     double R[9], D[9], T[9];
     matmul_nt(U, V, R);
@@ -113,11 +111,20 @@ MPM_DI bool stress_solid(const float* Ff, const MatDev& M, float* tau) {
   return ok;
 }
 
-MPM_DI void stress_solid_adjoint(const float* Ff, const MatDev& M, const float* taubf, float* Fbf) {
-  double F[9], U[9], s[3], V[9], tb[9];
+MPM_DI bool stress_solid(const float* Ff, const MatDev& M, float* tau) {
+  double F[9], U[9], s[3], V[9];
 #pragma unroll
-  for (int k = 0; k < 9; k++) { F[k] = (double)Ff[k]; tb[k] = (double)taubf[k]; }
+  for (int k = 0; k < 9; k++) F[k] = (double)Ff[k];
   svd3(F, U, s, V);
+  return stress_solid_usv(F, U, s, V, M, tau);
+}
+
+// Adjoint of the solid stress, from a given signed SVD of the FP64 copy F.
+MPM_DI void stress_solid_adjoint_usv(const double* F, const double* U, const double* s, const double* V,
+                                     const MatDev& M, const float* taubf, float* Fbf) {
+  double tb[9];
+#pragma unroll
+  for (int k = 0; k < 9; k++) tb[k] = (double)taubf[k];
   double Fb[9];
   if (M.kind == KIND_ELASTIC) {
     double R[9], D[9], T1[9], T2[9], Rb[9];
@@ -172,6 +179,14 @@ MPM_DI void stress_solid_adjoint(const float* Ff, const MatDev& M, const float* 
   }
 #pragma unroll
   for (int k = 0; k < 9; k++) Fbf[k] = (float)Fb[k];
+}
+
+MPM_DI void stress_solid_adjoint(const float* Ff, const MatDev& M, const float* taubf, float* Fbf) {
+  double F[9], U[9], s[3], V[9];
+#pragma unroll
+  for (int k = 0; k < 9; k++) F[k] = (double)Ff[k];
+  svd3(F, U, s, V);
+  stress_solid_adjoint_usv(F, U, s, V, M, taubf, Fbf);
 }
 
 // ---------------------------------------------------------------------------
