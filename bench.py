@@ -103,7 +103,7 @@ def bench_batched(torch, steps=100):
     return out
 
 
-def bench_closure(torch, steps=100, n_samples=10_000_000, epochs=4):
+def bench_closure(torch, steps=100, n_samples=10_000_000, epochs=16):
     """Config 5: 1M sand particles on 256^3 with the learned cone return
     against the exact return (step time, fallback rate, accuracy)."""
     import numpy as np
@@ -157,6 +157,45 @@ def bench_closure(torch, steps=100, n_samples=10_000_000, epochs=4):
     return out
 
 
+def bench_paper_point(torch, steps=200):
+    """The paper's operating point: ~1e5 particles on 64^3, substeps of
+    1e-4 s; reported as substeps/s and as frames/s at 10 substeps per frame
+    (the paper's real-time statement is 60 frames/s on an RTX 3090)."""
+    from paper_2303_02346_amd import scenes
+    from paper_2303_02346_amd.sim import Simulator
+    sc = scenes.paper_point(steps=steps)
+    sim = Simulator(sc, graph=True)
+    tune = sim.autotune(n_steps=20)
+    sim.reset()
+    sim.step(steps)
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    sim.close()
+    out = {"particles": sc.n, "n_grid": sc.n_grid, "dt": sc.dt, "steps": steps, "launch": tune,
+           "ms_per_substep": t * 1e3 / steps, "particle_steps_per_s": sc.n * steps / t,
+           "frames_per_s_at_10_substeps": steps / t / 10.0}
+    log(f"[bench] paper operating point: {out['ms_per_substep']:.4f} ms/substep, "
+        f"{out['frames_per_s_at_10_substeps']:.0f} frames/s at 10 substeps per frame")
+    return out
+
+
+def copy_calibration(torch, mb):
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    n = int(mb) * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {n * 4} bytes")
+    return n * 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +210,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-paper-point", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0, help="first run a device copy of this size (counter scaling)")
     ap.add_argument("--closure", action="store_true", help="also train and time the learned closure (config 5)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -183,6 +224,7 @@ def main():
     from paper_2303_02346_amd import scenes
     from paper_2303_02346_amd.sim import Simulator
 
+    copy_bytes = copy_calibration(torch, args.copy_mb) if args.copy_mb > 0 else None
     sc = scenes.config2(n_particles=args.particles, steps=max(args.steps, args.warmup, args.bwd_steps))
     N = sc.n
     kinds = np.array([m.kind for m in sc.materials])[sc.mat]
@@ -268,6 +310,8 @@ def main():
     if not args.no_batched:
         batched = bench_batched(torch)
 
+    paper = None if args.no_paper_point else bench_paper_point(torch)
+
     closure = bench_closure(torch) if args.closure else None
 
     cpu = None
@@ -288,6 +332,7 @@ def main():
         "graph_replay": graph,
         "fwd_bwd": fwd_bwd,
         "batched": batched,
+        "paper_point": paper,
         "closure": closure,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -4,10 +4,12 @@ TEST INFRASTRUCTURE ONLY (imported by tests, never by the product path).
 
 The network is the plain definition: with normalised input
 xn = (x - in_mean) / in_std,
-  h1 = relu(W1 xn + b1), h2 = relu(W2 h1 + b2), yn = W3 h2 + b3,
-  y = yn * out_std + out_mean,
-and the training loss is the mean squared error of the normalised outputs,
-L = mean over samples and outputs of (yn - (t - out_mean) / out_std)^2.
+  h1 = relu(W1 xn + b1), h2 = relu(W2 h1 + b2), u = (W3 h2 + b3) * out_std + out_mean,
+and its output keeps the trace of the trial log strain (the Drucker-Prager
+cone return moves only the deviatoric part):
+  y = u + (x_0 + x_1 + x_2 - u_0 - u_1 - u_2) / 3.
+The training loss is the mean squared error of the normalised outputs,
+L = mean over samples and outputs of ((y - out_mean) / out_std - (t - out_mean) / out_std)^2.
 Its gradient comes from torch autograd in float64.  Parameter vector order:
 W1 (64x6) b1 W2 (64x64) b2 W3 (3x64) b3, row-major [out][in].
 
@@ -41,8 +43,11 @@ def forward(p, norm, x):
     xn = (x - torch.as_tensor(norm["in_mean"], dtype=DT)) / torch.as_tensor(norm["in_std"], dtype=DT)
     h1 = torch.relu(xn @ W1.T + b1)
     h2 = torch.relu(h1 @ W2.T + b2)
-    yn = h2 @ W3.T + b3
-    return yn * torch.as_tensor(norm["out_std"], dtype=DT) + torch.as_tensor(norm["out_mean"], dtype=DT), yn
+    sd = torch.as_tensor(norm["out_std"], dtype=DT)
+    mn = torch.as_tensor(norm["out_mean"], dtype=DT)
+    u = (h2 @ W3.T + b3) * sd + mn
+    y = u + ((x[:, 0:3].sum(1) - u.sum(1)) / 3.0)[:, None]
+    return y, (y - mn) / sd
 
 
 def loss_and_grad(p, norm, records):

@@ -90,21 +90,27 @@ class MLP:
         return p, norm, pb
 
 
-def sand_scene(seed: int, n_particles: int = 120_000, n_grid: int = 96, steps: int = 100):
+def sand_scene(seed: int, n_particles: int = 60_000, n_grid: Optional[int] = None, steps: int = 100):
     """Seeded sand-impact scene: four boxes resting on the floor band from
-    the first step, moving down at 0.5..2 m/s with a sideways drift, with
-    friction angles, cohesion and Poisson ratios drawn from [20, 40] deg,
-    [0, 0.01], [0.2, 0.35]; the impact drives the cone-case returns."""
+    the first step, moving down at 0.5..2 m/s with a sideways drift.  Per box,
+    the friction angle is drawn from [20, 40] deg, the Poisson ratio from
+    [0.2, 0.35] (E = 1e3), and the cohesion is 0 for half of the boxes and
+    drawn from [0, 0.01] for the others.  Without n_grid the grid is one of
+    64^3, 128^3, 256^3; dt = 6.4e-3 / n_grid keeps the elastic CFL number
+    at 0.21.  The impact drives the cone-case returns."""
     rng = np.random.default_rng(np.random.SeedSequence([20230302, 5, seed]))
+    if n_grid is None:
+        n_grid = int(rng.choice([64, 128, 256]))
     dx = 1.0 / n_grid
-    dt = 5e-5
+    dt = 6.4e-3 / n_grid
     boxes = []
     per = n_particles // 4
     for b in range(4):
         E = 1e3
         nu = rng.uniform(0.2, 0.35)
         mu, lam = scenes.lame(E, nu)
-        m = scenes.Material(scenes.SAND, mu, lam, 1.0, friction_deg=rng.uniform(20, 40), cohesion=rng.uniform(0, 0.01))
+        coh = 0.0 if rng.random() < 0.5 else rng.uniform(0, 0.01)
+        m = scenes.Material(scenes.SAND, mu, lam, 1.0, friction_deg=rng.uniform(20, 40), cohesion=coh)
         lo = np.array([0.12 + 0.2 * b, 3 * dx, rng.uniform(0.15, 0.6)])
         side = np.array([0.15, 0.25, 0.2])
         pos = lo + side * rng.random((per, 3))
@@ -116,21 +122,30 @@ def sand_scene(seed: int, n_particles: int = 120_000, n_grid: int = 96, steps: i
     return sc
 
 
-def generate_samples(target: int, device="cuda", max_scenes: int = 64, steps: int = 100) -> torch.Tensor:
-    """Run seeded sand rollouts with the exact projection, logging cone-case
-    samples until `target` records are collected."""
+def generate_samples(target: int, device="cuda", n_scenes: int = 32, steps: int = 100, window: int = 4,
+                     seed: int = 0) -> torch.Tensor:
+    """Cone-case samples of the exact projection from seeded sand rollouts:
+    each scene contributes at most target / n_scenes records, logged during a
+    window of `window` steps that starts at a seeded step of its rollout, so
+    that the set spans materials, grids and impact stages."""
     from .sim import Simulator
+    rng = np.random.default_rng(np.random.SeedSequence([20230302, 7, seed]))
     buf = torch.zeros(target, RECORD, dtype=torch.float32, device=device)
+    quota = -(-target // n_scenes)
     have = 0
-    for seed in range(max_scenes):
-        sc = sand_scene(seed, steps=steps)
-        sim = Simulator(sc)
-        cnt = torch.zeros(1, dtype=torch.int64, device=device)
-        sim.log_samples(buf[have:], cnt)
-        sim.step(steps)
-        got = int(cnt.item())
-        have += min(got, target - have)
-        sim.close()
+    for s in range(4 * n_scenes):
         if have >= target:
             break
+        sc = sand_scene(s, steps=steps)
+        sim = Simulator(sc)
+        t0 = int(rng.integers(0, steps - window + 1))
+        if t0 > 0:
+            sim.step(t0)
+        cap = min(quota, target - have)
+        cnt = torch.zeros(1, dtype=torch.int64, device=device)
+        sim.log_samples(buf[have:have + cap], cnt)
+        sim.step(window)
+        sim.log_samples(None)
+        have += min(int(cnt.item()), cap)
+        sim.close()
     return buf[:have]

@@ -4,8 +4,10 @@
 //
 // Input (per sample): log singular values of the trial F sorted descending,
 // then the cone slope alpha, the cohesion c and kappa = (3 lam + 2 mu)/(2 mu).
-// Output: the projected log singular values (same order).  Inputs and outputs
-// are normalised with fixed means and deviations stored with the weights.
+// Output: the projected log singular values (same order), shifted equally so
+// that their sum equals that of the trial ones (the return is deviatoric).
+// Inputs and outputs are normalised with fixed means and deviations stored
+// with the weights.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -164,6 +166,11 @@ __device__ inline void mlp_wave_forward(const MlpBlob& W, const float* x, float*
   }
 #pragma unroll
   for (int o = 0; o < MLP_OUT; o++) y[o] = S.y[l * MLP_OUT + o] * W.out_std[o] + W.out_mean[o];
+  // the cone return changes only the deviatoric part of the log strain, so
+  // the output is projected onto the inputs' trace: tr y = tr x
+  const float dtr = ((x[0] + x[1] + x[2]) - (y[0] + y[1] + y[2])) * (1.f / 3.f);
+#pragma unroll
+  for (int o = 0; o < MLP_OUT; o++) y[o] += dtr;
   __syncwarp();
 }
 

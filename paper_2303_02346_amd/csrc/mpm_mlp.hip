@@ -145,16 +145,21 @@ __global__ __launch_bounds__(256) void k_mlp_batch(const MlpBlob* __restrict__ b
   }
   double loss = 0.0;
   if (has && rec) {
-    // normalised output error; dL/dy_n for L = mean over batch and outputs
-    float dy[MLP_OUT];
+    // normalised error of the trace-projected output y; the adjoint of the
+    // network's normalised output yn goes back through the projection
+    // y = P(yn * std + mean), P(u) = u + (tr x - sum u) / 3
+    float g[MLP_OUT], dy[MLP_OUT], gs = 0.f;
 #pragma unroll
     for (int c = 0; c < MLP_OUT; c++) {
       const float yn = (y[c] - W.out_mean[c]) / W.out_std[c];
       const float tn = (t[c] - W.out_mean[c]) / W.out_std[c];
       const float e = yn - tn;
       loss += (double)e * e;
-      dy[c] = 2.f * e / (float)(MLP_OUT * nb);
+      g[c] = 2.f * e / (float)(MLP_OUT * nb) / W.out_std[c];   // dL/dy
+      gs += g[c];
     }
+#pragma unroll
+    for (int c = 0; c < MLP_OUT; c++) dy[c] = (g[c] - gs * (1.f / 3.f)) * W.out_std[c];
 #pragma unroll
     for (int c = 0; c < MLP_IN; c++) rec[c] = (x[c] - W.in_mean[c]) / W.in_std[c];
     // dh2 = W3^T dy masked by ReLU; dh1 = W2^T dh2 masked by ReLU (BF16 weights)

@@ -238,6 +238,29 @@ def config4(n_scenes: int = 64, steps: int = 100, n_min: int = 10_000, n_max: in
     return scenes
 
 
+def paper_point(n_particles: int = 100_000, steps: int = 200) -> Scene:
+    """The paper's operating point (section 4.2, App. B.1): about 1e5
+    particles on a 64^3 grid at substeps of 1e-4 s.  Three boxes of Table 4
+    materials (water, a viscous liquid, an elastic solid) on the floor band
+    and the cylinder stirring the water with a seeded trajectory."""
+    r_geo, r_pos, r_traj, r_tgt = _rngs(6)
+    n_grid, dt = 64, 1e-4
+    dx = 1.0 / n_grid
+    per = [n_particles // 3] * 3
+    per[0] += n_particles - sum(per)
+    side = 0.2
+    mats = [Material(LIQUID, 0.0, WATER_LAMBDA, 1.0),
+            Material(LIQUID, 0.0, WATER_LAMBDA, 1.0, viscosity=0.1),
+            Material(ELASTIC, SOLID_MU, SOLID_LAMBDA, 1.0)]
+    boxes = []
+    for b in range(3):
+        lo = np.array([0.12 + 0.27 * b, 3 * dx, r_geo.uniform(0.2, 0.6)])
+        boxes.append((_box_particles(r_pos, lo, lo + side, per[b]), mats[b], side ** 3))
+    acts = smooth_actions(r_traj, steps, dt, u_mean=(0.0, 0.0, 0.3))
+    c0 = np.array([0.22, 0.5, boxes[0][0][:, 2].mean()])
+    return _assemble(n_grid, dt, boxes, acts, cyl_radius=0.05, cyl_pos0=c0, name="paper64")
+
+
 def config5(n_particles: int = 1_000_000, steps: int = 100) -> Scene:
     """1M sand particles in a 0.2x0.3x0.2 box hitting the floor of a 256^3
     grid at 1 m/s (its base is inside the wall band from the first step),

@@ -94,7 +94,7 @@ def test_training_and_closure_in_the_simulator():
     from paper_2303_02346_amd.closure import MLP, generate_samples, sand_scene
     from paper_2303_02346_amd.sim import Simulator
     t0 = time.time()
-    samples = generate_samples(400_000, max_scenes=4, steps=60)
+    samples = generate_samples(400_000, n_scenes=8, steps=60)
     say(f"  generated {samples.shape[0]} samples in {time.time() - t0:.1f} s")
     assert samples.shape[0] > 10000
     perm = torch.randperm(samples.shape[0], device="cuda")

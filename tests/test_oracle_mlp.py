@@ -22,11 +22,20 @@ def test_parameter_count():
     assert sum(int(np.prod(s)) for s in M.SIZES) == 4803
 
 
+def trace_shift(u, x):
+    """u shifted equally in its three components so that its sum is that of x[:, :3]."""
+    return u + ((x[:, :3].sum(1) - u.sum(1)) / 3.0)[:, None]
+
+
 def test_identity_network_closed_form():
     rng = np.random.default_rng(0)
     x = rng.normal(0, 1, (50, 6))
     y, _ = M.forward(identity_net(), NORM0, x)
-    assert np.allclose(y.numpy(), np.maximum(x[:, :3], 0), atol=0)
+    assert np.allclose(y.numpy(), trace_shift(np.maximum(x[:, :3], 0), x), atol=1e-15)
+    # non-negative inputs pass through unchanged
+    xp = np.abs(x)
+    yp, _ = M.forward(identity_net(), NORM0, xp)
+    assert np.allclose(yp.numpy(), xp[:, :3], atol=1e-15)
 
 
 def test_normalisation_is_applied():
@@ -36,8 +45,18 @@ def test_normalisation_is_applied():
     x = rng.normal(0, 1, (20, 6))
     y, yn = M.forward(identity_net(), norm, x)
     xn = (x - norm["in_mean"]) / norm["in_std"]
-    assert np.allclose(yn.numpy(), np.maximum(xn[:, :3], 0))
-    assert np.allclose(y.numpy(), np.maximum(xn[:, :3], 0) * norm["out_std"] + norm["out_mean"])
+    u = np.maximum(xn[:, :3], 0) * norm["out_std"] + norm["out_mean"]
+    assert np.allclose(y.numpy(), trace_shift(u, x))
+    assert np.allclose(yn.numpy(), (trace_shift(u, x) - norm["out_mean"]) / norm["out_std"])
+
+
+def test_output_keeps_the_trial_trace():
+    """The cone return is deviatoric: any network's output has the trial sum."""
+    rng = np.random.default_rng(5)
+    p = rng.normal(0, 0.5, 4803)
+    x = rng.normal(0, 0.05, (100, 6))
+    y, _ = M.forward(p, NORM0, x)
+    assert np.allclose(y.numpy().sum(1), x[:, :3].sum(1), atol=1e-13)
 
 
 def test_loss_gradient_fd():
