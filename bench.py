@@ -37,6 +37,30 @@ KERNEL_BYTES = {
 }
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_g2p2g_config2_traffic.md")
+TRAFFIC_SOURCES = ["mpm_fast.hip", "mpm_fast.h", "mpm_blocks.h", "mpm_phys.h", "mpm_math.h", "mpm_internal.h"]
+
+
+def counted_traffic():
+    """HBM bytes per fused launch from the committed counter summary, or None
+    when the kernel's sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m_b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    m_h = re.search(r"source-sha256:\s*([0-9a-f]+)", text)
+    if not m_b or not m_h:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2303_02346_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_b.group(1)) if h.hexdigest()[:16] == m_h.group(1) else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -277,8 +301,9 @@ def main():
         bytes_launch = per[0] * n_sol + per[1] * n_liq + per[2] * n_act
         avg_s = k_ms / k_launches * 1e-3
         ach = bytes_launch / avg_s / 1e9
+        traffic = counted_traffic() if k_name == "k_g2p2g" else None
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": k_name,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": k_name,
                 "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_launch)}
     step_bytes = BYTES_SOLID * n_sol + BYTES_LIQUID * n_liq + BYTES_NODE * n_act
     step_frac = step_bytes / (t_fwd / args.steps) / 1e9 / HBM_PEAK_GBS
