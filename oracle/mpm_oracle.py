@@ -46,7 +46,7 @@ import torch
 import torch.utils.checkpoint
 
 DT = torch.float64
-ELASTIC, LIQUID, SAND = 0, 1, 2
+ELASTIC, LIQUID, SAND, VONMISES = 0, 1, 2, 3
 
 
 class OracleDomainError(RuntimeError):
@@ -270,6 +270,56 @@ def make_g_dp(alpha, kappa, cohesion):
 
 
 # ----------------------------------------------------------------------------
+# Von Mises projection in log-strain space (section 3.2: the non-Newtonian
+# liquid is an elastoplastic continuum whose plastic part follows the von
+# Mises criterion).  Hencky elasticity as for sand; with dev = eps - tr/3, the
+# yield surface is |dev| = rho, rho = yield stress / (2 mu).
+# ----------------------------------------------------------------------------
+def vm_project(eps: torch.Tensor, rho):
+    """|dev| <= rho -> unchanged (case 0); else eps' = tr/3 + rho dev/|dev|
+    (case 2): the trace is kept and the deviatoric part is scaled back onto
+    the yield surface along its own direction."""
+    t = eps.sum(-1, keepdim=True)
+    dev = eps - t / 3.0
+    ndev = torch.linalg.norm(dev, dim=-1, keepdim=True)
+    yielding = ndev > rho[:, None]
+    nsafe = torch.where(ndev > 0, ndev, torch.ones_like(ndev))
+    out = torch.where(yielding, t / 3.0 + rho[:, None] * dev / nsafe, eps)
+    case = torch.where(yielding[:, 0], 2, 0)
+    return out, case
+
+
+def vm_jacobian(eps, rho):
+    """d eps'/d eps of vm_project (N,3,3): identity inside; when yielding
+    11^T/3 + (rho/|dev|)(I - nh nh^T - 11^T/3)."""
+    t = eps.sum(-1, keepdim=True)
+    dev = eps - t / 3.0
+    ndev = torch.linalg.norm(dev, dim=-1, keepdim=True)
+    N = eps.shape[0]
+    eye = torch.eye(3, dtype=DT).expand(N, 3, 3)
+    ones = torch.ones(N, 3, 3, dtype=DT)
+    yielding = ndev[:, 0] > rho
+    nsafe = torch.where(ndev > 0, ndev, torch.ones_like(ndev))
+    nh = dev / nsafe
+    Jy = ones / 3.0 + (rho[:, None, None] / nsafe[:, :, None]) * (eye - nh[:, :, None] * nh[:, None, :] - ones / 3.0)
+    return torch.where(yielding[:, None, None], Jy, eye)
+
+
+def make_g_vm(rho):
+    """Projected deformation as an isotropic map of the trial F:
+    F' = U diag(exp(P_vm(log sigma))) V^T."""
+    def g(s):
+        if torch.any(s <= 0):
+            raise OracleDomainError("plastic singular value <= 0")
+        eps = torch.log(s)
+        ep, _ = vm_project(eps, rho)
+        gv = torch.exp(ep)
+        dg = gv[:, :, None] * vm_jacobian(eps, rho) / s[:, None, :]
+        return gv, dg
+    return g
+
+
+# ----------------------------------------------------------------------------
 # Scene parameters (oracle-side copy of the inputs)
 # ----------------------------------------------------------------------------
 @dataclass
@@ -285,6 +335,7 @@ class Params:
     alpha: torch.Tensor
     kappa: torch.Tensor
     cohesion: torch.Tensor
+    yield_radius: torch.Tensor   # von Mises: yield stress / (2 mu)
     vol: torch.Tensor
     mass: torch.Tensor
     cyl_radius: float
@@ -293,6 +344,7 @@ class Params:
     idx_el: torch.Tensor = field(default=None)
     idx_liq: torch.Tensor = field(default=None)
     idx_sand: torch.Tensor = field(default=None)
+    idx_vm: torch.Tensor = field(default=None)
 
     @property
     def dx(self):
@@ -308,13 +360,17 @@ def params_from_scene(sc) -> Params:
     phi = [sc.materials[m].friction_deg for m in range(len(sc.materials))]
     alpha = torch.tensor([dp_alpha(p) for p in phi], dtype=DT)[torch.from_numpy(mat).long()]
     kappa = torch.where(mu > 0, (3.0 * lam + 2.0 * mu) / (2.0 * torch.where(mu > 0, mu, torch.ones_like(mu))), torch.zeros_like(mu))
+    ys = torch.tensor([getattr(sc.materials[m], "yield_stress", 0.0) for m in range(len(sc.materials))],
+                      dtype=DT)[torch.from_numpy(mat).long()]
+    yrad = torch.where(mu > 0, ys / (2.0 * torch.where(mu > 0, mu, torch.ones_like(mu))), torch.zeros_like(mu))
     p = Params(n_grid=sc.n_grid, dt=sc.dt, gravity=torch.tensor(sc.gravity, dtype=DT), bound=sc.bound,
                kind=kind, mu=mu, lam=lam, eta=per("viscosity"), alpha=alpha, kappa=kappa,
-               cohesion=per("cohesion"), vol=per("p_vol"), mass=per("p_mass"),
+               cohesion=per("cohesion"), yield_radius=yrad, vol=per("p_vol"), mass=per("p_mass"),
                cyl_radius=sc.cyl_radius, contact_band=sc.contact_band, friction=sc.contact_friction)
     p.idx_el = torch.nonzero(kind == ELASTIC)[:, 0]
     p.idx_liq = torch.nonzero(kind == LIQUID)[:, 0]
     p.idx_sand = torch.nonzero(kind == SAND)[:, 0]
+    p.idx_vm = torch.nonzero(kind == VONMISES)[:, 0]
     return p
 
 
@@ -341,6 +397,9 @@ def kirchhoff_stress(st, p: Params):
     if p.idx_sand.numel():
         i = p.idx_sand
         tau = tau.index_put((i,), stress_sand(st["F"][i], p.mu[i], p.lam[i]))
+    if p.idx_vm.numel():
+        i = p.idx_vm
+        tau = tau.index_put((i,), stress_sand(st["F"][i], p.mu[i], p.lam[i]))   # Hencky as well
     return tau
 
 
@@ -436,7 +495,8 @@ def grid_update(m, mv, pose_c, pose_R, action, p: Params):
 def g2p(st, vgrid, p: Params):
     """Grid-to-particle: v' = sum w v_i; C' = (4/dx^2) sum w v_i (x_i - x_p)^T;
     x' = x + dt v'; F_tr = (I + dt C') F; elastic F' = F_tr; liquid
-    J' = J det(I + dt C'); sand F' = Drucker-Prager projection of F_tr."""
+    J' = J det(I + dt C'); sand F' = Drucker-Prager projection of F_tr;
+    von Mises F' = von Mises projection of F_tr."""
     n, dx, dt = p.n_grid, p.dx, p.dt
     base, f, W, dpos = bspline(st["x"], dx)
     idx = node_index(base, n)
@@ -456,6 +516,9 @@ def g2p(st, vgrid, p: Params):
     if p.idx_sand.numel():
         i = p.idx_sand
         F_new = F_new.index_put((i,), IsotropicMap.apply(F_tr[i], make_g_dp(p.alpha[i], p.kappa[i], p.cohesion[i])))
+    if p.idx_vm.numel():
+        i = p.idx_vm
+        F_new = F_new.index_put((i,), IsotropicMap.apply(F_tr[i], make_g_vm(p.yield_radius[i])))
     out = {"x": x_new, "v": v_new, "C": C_new, "F": F_new, "J": J_new}
     for k, t in out.items():
         if not torch.isfinite(t).all():

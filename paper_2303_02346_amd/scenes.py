@@ -23,11 +23,21 @@ import numpy as np
 ELASTIC = 0   # fixed-corotated elastic solid
 LIQUID = 1    # weakly compressible liquid, J-based pressure + Newtonian viscosity
 SAND = 2      # Hencky elasticity + Drucker-Prager plasticity
+VONMISES = 3  # Hencky elasticity + von Mises plasticity (the non-Newtonian ice cream)
 
 # Table 4 (Appendix B.1) constants used by the synthetic scenes.
 WATER_LAMBDA = 277.78
 SOLID_MU = 416.67
 SOLID_LAMBDA = 277.78
+
+
+ICE_CREAM_YIELD = 5.0   # not in Table 4; deviatoric flow from |dev log strain| = 0.006
+
+
+def ice_cream():
+    """Table 4's non-Newtonian ice cream (mu 416.67, lambda 277.78, rho 0.5)
+    as a von Mises elastoplastic continuum."""
+    return Material(VONMISES, SOLID_MU, SOLID_LAMBDA, 0.5, yield_stress=ICE_CREAM_YIELD)
 
 
 def lame(E: float, nu: float):
@@ -46,6 +56,7 @@ class Material:
     viscosity: float = 0.0
     friction_deg: float = 30.0
     cohesion: float = 0.0
+    yield_stress: float = 0.0   # von Mises yield stress (Kirchhoff)
     p_vol: float = 0.0    # initial particle volume V_p = V_box / N_box
     p_mass: float = 0.0   # m_p = rho * V_p
 
@@ -297,6 +308,8 @@ def tiny(n_particles: int = 125, n_grid: int = 16, steps: int = 10, seed: int = 
             m = Material(ELASTIC, SOLID_MU, SOLID_LAMBDA, 1.0)
         elif kind == LIQUID:
             m = Material(LIQUID, 0.0, WATER_LAMBDA, 1.0, viscosity=0.1)
+        elif kind == VONMISES:
+            m = ice_cream()
         else:
             m = Material(SAND, SOLID_MU, SOLID_LAMBDA, 1.0, friction_deg=30.0, cohesion=0.0)
         boxes.append((pos, m, side ** 3))

@@ -240,3 +240,79 @@ def test_dp_isotropic_map_derivative_fd():
     gbar = torch.tensor(rng.normal(0, 1, (n, 3, 3)), dtype=DT)
     ga, num = fd_check(fun, F, gbar, eps=1e-7)
     assert torch.allclose(ga, num, atol=2e-6)
+
+
+# ---------------------------------------------------------------------------
+# von Mises return in log strain (the non-Newtonian ice cream)
+# ---------------------------------------------------------------------------
+def test_vm_projection_closed_form():
+    """Pure shear trial strain (a, -a, 0): |dev| = sqrt(2) a; beyond the
+    radius the return is rho (1, -1, 0)/sqrt(2); a pure dilation never yields."""
+    rho = torch.tensor([0.006, 0.006], dtype=DT)
+    eps = torch.tensor([[0.01, -0.01, 0.0], [0.003, -0.003, 0.0]], dtype=DT)
+    ep, case = O.vm_project(eps, rho)
+    assert case.tolist() == [2, 0]
+    assert torch.allclose(ep[0], torch.tensor([0.006, -0.006, 0.0], dtype=DT) / math.sqrt(2.0), atol=1e-17)
+    assert torch.equal(ep[1], eps[1])
+    dil = torch.full((1, 3), 0.2, dtype=DT)
+    ep2, case2 = O.vm_project(dil, rho[:1])
+    assert case2.item() == 0 and torch.equal(ep2, dil)
+
+
+def test_vm_projection_properties():
+    rng = np.random.default_rng(31)
+    n = 20000
+    eps = torch.tensor(rng.normal(0, 0.01, (n, 3)), dtype=DT)
+    rho = torch.tensor(rng.uniform(0.002, 0.01, n), dtype=DT)
+    ep, case = O.vm_project(eps, rho)
+    y = case == 2
+    assert y.any() and (~y).any()
+    tr, tr0 = ep.sum(-1), eps.sum(-1)
+    dev, dev0 = ep - tr[:, None] / 3, eps - tr0[:, None] / 3
+    assert torch.allclose(tr, tr0, atol=1e-16)                                   # trace kept
+    assert (dev[y].norm(dim=-1) - rho[y]).abs().max() < 1e-16                     # on the surface
+    cosang = (dev[y] * dev0[y]).sum(-1) / (dev[y].norm(dim=-1) * dev0[y].norm(dim=-1))
+    assert torch.allclose(cosang, torch.ones_like(cosang), atol=1e-12)           # direction kept
+    assert torch.equal(ep[~y], eps[~y])
+    ep2, _ = O.vm_project(ep, rho * (1 + 1e-12))                                 # idempotent
+    assert torch.allclose(ep2, ep, atol=1e-16)
+    d = torch.tensor(rng.normal(0, 1, (n, 3)), dtype=DT) * 1e-9                  # Lipschitz across the surface
+    e3, _ = O.vm_project(eps + d, rho)
+    assert ((e3 - ep).norm(dim=-1) <= 2e-9 * (1 + d.norm(dim=-1) / 1e-9)).all()
+
+
+def test_vm_jacobian_fd():
+    rng = np.random.default_rng(32)
+    n = 400
+    eps = torch.tensor(rng.normal(0, 0.01, (n, 3)), dtype=DT)
+    rho = torch.full((n,), 0.006, dtype=DT)
+    Jm = O.vm_jacobian(eps, rho)
+    h = 1e-8
+    for k in range(3):
+        ep_p, cp = O.vm_project(eps + h * torch.eye(3, dtype=DT)[k], rho)
+        ep_m, cm = O.vm_project(eps - h * torch.eye(3, dtype=DT)[k], rho)
+        same = cp == cm
+        num = (ep_p - ep_m) / (2 * h)
+        assert torch.allclose(Jm[same][:, :, k], num[same], atol=1e-6)
+
+
+def test_vm_isotropic_map_derivative_fd():
+    """Derivative of F_tr -> U exp(P_vm(log sigma)) V^T, yielding and not,
+    at distinct and repeated singular values."""
+    rng = np.random.default_rng(33)
+    sig = np.array([[1.02, 0.99, 0.985],        # yields
+                    [1.01, 1.01, 0.98],         # yields, repeated pair
+                    [1.002, 1.0, 0.999],        # inside
+                    [0.99, 0.99, 0.99],         # inside, triple
+                    [1.03, 0.98, 0.98]])        # yields, repeated pair
+    n = sig.shape[0]
+    U = Rotation.random(n, random_state=34).as_matrix()
+    V = Rotation.random(n, random_state=35).as_matrix()
+    F = torch.tensor(U @ (sig[:, :, None] * np.swapaxes(V, -1, -2)), dtype=DT)
+    rho = torch.full((n,), 0.006, dtype=DT)
+    _, case = O.vm_project(torch.log(torch.tensor(sig)), rho)
+    assert set(case.tolist()) == {0, 2}
+    fun = lambda X: O.IsotropicMap.apply(X, O.make_g_vm(rho))
+    gbar = torch.tensor(rng.normal(0, 1, (n, 3, 3)), dtype=DT)
+    ga, num = fd_check(fun, F, gbar, eps=1e-7)
+    assert torch.allclose(ga, num, atol=2e-6)
