@@ -59,14 +59,16 @@ typedef enum {
 typedef enum {
   MPM_ELASTIC_FCR = 0,  /* fixed-corotated elastic solid (the paper's corotated model) */
   MPM_LIQUID_J = 1,     /* liquid: J-based pressure + Newtonian viscosity (F reset, section 3.2) */
-  MPM_SAND_DP = 2       /* Hencky elasticity + Drucker-Prager projection (Klar et al. 2016) */
+  MPM_SAND_DP = 2,      /* Hencky elasticity + Drucker-Prager projection (Klar et al. 2016) */
+  MPM_PLASTIC_VM = 3    /* Hencky elasticity + von Mises projection in log strain: the
+                           non-Newtonian ice cream of section 3.2 */
 } mpm_material_kind;
 
 /* Error bits of the device error word (returned by mpm_last_error_bits). */
 enum {
   MPM_ERR_OUTSIDE = 1,     /* a particle stencil left the grid */
   MPM_ERR_NONFINITE = 2,   /* a non-finite particle value */
-  MPM_ERR_SAND_SIGMA = 4,  /* a sand singular value <= 0 */
+  MPM_ERR_SAND_SIGMA = 4,  /* a sand or von Mises singular value <= 0 */
   MPM_ERR_TILE = 8         /* a particle moved farther than the kernels' tiles allow (CFL > 1) */
 };
 
@@ -82,6 +84,8 @@ typedef struct {
   float friction_deg;    /* sand: Drucker-Prager friction angle (degrees) */
   float cohesion;        /* sand: apex shift in log-strain */
   float p_vol, p_mass;
+  float yield_stress;    /* von Mises: yield stress; the return radius in log strain is
+                            yield_stress / (2 mu) */
 } mpm_material;
 
 /* Particle state: SoA device pointers, see Conventions.  mat may be NULL in

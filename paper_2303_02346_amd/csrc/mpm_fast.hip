@@ -412,8 +412,8 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
             } else {
               double e[3] = {log(s[0]), log(s[1]), log(s[2])}, ep[3];
               DPInfo I;
-              dp_project(e, M, ep, I);
-              if (FEAT != FEAT_NONE && I.cse == 2) {
+              plastic_project(e, M, ep, I);
+              if (FEAT != FEAT_NONE && M.kind == KIND_SAND && I.cse == 2) {
                 cone = true;
 #pragma unroll
                 for (int a = 0; a < 3; a++) { xin[a] = (float)e[a]; eex[a] = (float)ep[a]; }

@@ -6,7 +6,7 @@
 
 namespace mpm {
 
-enum { KIND_ELASTIC = 0, KIND_LIQUID = 1, KIND_SAND = 2 };
+enum { KIND_ELASTIC = 0, KIND_LIQUID = 1, KIND_SAND = 2, KIND_VONMISES = 3 };
 enum { ERR_OUTSIDE = 1, ERR_NONFINITE = 2, ERR_SAND_SIGMA = 4, ERR_TILE = 8 };
 
 // Per-material constants as the kernels use them (alpha, kappa precomputed).
@@ -15,7 +15,8 @@ struct MatDev {
   float mu, lam, eta;
   float alpha, kappa, coh;
   float vol, mass;
-  float pad[3];
+  float yrad;          // von Mises return radius in log strain, yield / (2 mu)
+  float pad[2];
 };
 
 // Particle state, structure of arrays: component k of particle p at ptr[k*N + p].

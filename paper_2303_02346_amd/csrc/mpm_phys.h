@@ -193,9 +193,13 @@ MPM_DI void stress_solid_adjoint(const float* Ff, const MatDev& M, const float* 
 // Drucker-Prager return map in log-strain (Klar et al. 2016), FP64.
 // case 0 inside, 1 apex, 2 cone.
 // ---------------------------------------------------------------------------
+// Result of a return map in log strain.  In the flowing case (cse 2) the
+// map is eps' = t/3 1 + k0 + beta |dev| nh - k1 t nh with nh = dev/|dev|, so
+// its Jacobian is 11^T/3 - k1 nh 1^T + beta (I - nh nh^T - 11^T/3) and
+// eps'_i - eps'_j = beta (eps_i - eps_j).
 struct DPInfo {
-  int cse;
-  double t, ndev, beta;
+  int cse;            // 0 inside, 1 apex (Drucker-Prager only), 2 flowing
+  double t, ndev, beta, k1;
   double nh[3];
 };
 
@@ -222,6 +226,33 @@ MPM_DI void dp_project(const double* e, const MatDev& M, double* ep, DPInfo& I) 
     for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] / nd; ep[a] = es[a] - dg * I.nh[a] + c; }
     I.beta = -ka * t / nd;
   }
+  I.k1 = ka;
+}
+
+// Von Mises return (section 3.2, non-Newtonian liquid): |dev| <= r inside,
+// else the deviatoric part is scaled back to radius r, the trace kept.
+MPM_DI void vm_project(const double* e, const MatDev& M, double* ep, DPInfo& I) {
+  const double t = e[0] + e[1] + e[2];
+  const double dev[3] = {e[0] - t / 3.0, e[1] - t / 3.0, e[2] - t / 3.0};
+  const double nd = sqrt(dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]);
+  const double r = (double)M.yrad;
+  I.t = t; I.ndev = nd; I.k1 = 0.0;
+  if (nd <= r) {
+    I.cse = 0; I.beta = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) { ep[a] = e[a]; I.nh[a] = 0.0; }
+  } else {
+    I.cse = 2;
+    I.beta = r / nd;
+#pragma unroll
+    for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] / nd; ep[a] = t / 3.0 + r * I.nh[a]; }
+  }
+}
+
+// The return map of a plastic material (sand or von Mises).
+MPM_DI void plastic_project(const double* e, const MatDev& M, double* ep, DPInfo& I) {
+  if (M.kind == KIND_VONMISES) vm_project(e, M, ep, I);
+  else dp_project(e, M, ep, I);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,7 +298,7 @@ MPM_DI void particle_update(const float* x, const float* vn, const float* B, con
       } else {
         double e[3] = {log(s[0]), log(s[1]), log(s[2])}, ep[3], g[3], Fo[9];
         DPInfo I;
-        dp_project(e, M, ep, I);
+        plastic_project(e, M, ep, I);
         if (I.cse == 0) {
 #pragma unroll
           for (int k = 0; k < 9; k++) U.F[k] = (float)Ft[k];
@@ -332,7 +363,7 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
 #pragma unroll
       for (int a = 0; a < 3; a++) e[a] = ok ? log(s[a]) : 0.0;
       DPInfo I;
-      dp_project(e, M, ep, I);
+      plastic_project(e, M, ep, I);
       if (!ok || I.cse == 0) {
 #pragma unroll
         for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
@@ -344,12 +375,11 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
 #pragma unroll
           for (int k = 0; k < 9; k++) { dg[k] = 0.0; sdd[k] = 0.0; }
         } else {
-          double ka = (double)M.kappa * (double)M.alpha;
 #pragma unroll
           for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-              double Jik = 1.0 / 3.0 - ka * I.nh[i] - ka * I.t * ((i == k ? 1.0 : 0.0) - I.nh[i] * I.nh[k] - 1.0 / 3.0) / I.ndev;
+              double Jik = 1.0 / 3.0 - I.k1 * I.nh[i] + I.beta * ((i == k ? 1.0 : 0.0) - I.nh[i] * I.nh[k] - 1.0 / 3.0);
               dg[i * 3 + k] = g[i] * Jik / s[k];
             }
 #pragma unroll
