@@ -46,7 +46,7 @@ import torch
 import torch.utils.checkpoint
 
 DT = torch.float64
-ELASTIC, LIQUID, SAND, VONMISES = 0, 1, 2, 3
+ELASTIC, LIQUID, SAND, VONMISES, BOX = 0, 1, 2, 3, 4
 
 
 class OracleDomainError(RuntimeError):
@@ -320,6 +320,23 @@ def make_g_vm(rho):
 
 
 # ----------------------------------------------------------------------------
+# Box yield (section 3.2's plastic material, Stomakhin et al. 2013): after
+# each update the singular values of F are clamped to [1 - theta_c,
+# 1 + theta_s]; the corotated stress acts on the clamped F.  No hardening.
+# ----------------------------------------------------------------------------
+def make_g_box(lo, hi):
+    """F' = U diag(clamp(sigma, lo, hi)) V^T as an isotropic map."""
+    def g(s):
+        if torch.any(s <= 0):
+            raise OracleDomainError("plastic singular value <= 0")
+        gv = torch.minimum(torch.maximum(s, lo[:, None]), hi[:, None])
+        inside = ((s > lo[:, None]) & (s < hi[:, None])).to(DT)
+        dg = torch.diag_embed(inside)
+        return gv, dg
+    return g
+
+
+# ----------------------------------------------------------------------------
 # Scene parameters (oracle-side copy of the inputs)
 # ----------------------------------------------------------------------------
 @dataclass
@@ -336,6 +353,8 @@ class Params:
     kappa: torch.Tensor
     cohesion: torch.Tensor
     yield_radius: torch.Tensor   # von Mises: yield stress / (2 mu)
+    box_lo: torch.Tensor         # Box yield: 1 - theta_c
+    box_hi: torch.Tensor         # Box yield: 1 + theta_s
     vol: torch.Tensor
     mass: torch.Tensor
     cyl_radius: float
@@ -345,6 +364,7 @@ class Params:
     idx_liq: torch.Tensor = field(default=None)
     idx_sand: torch.Tensor = field(default=None)
     idx_vm: torch.Tensor = field(default=None)
+    idx_box: torch.Tensor = field(default=None)
 
     @property
     def dx(self):
@@ -360,17 +380,22 @@ def params_from_scene(sc) -> Params:
     phi = [sc.materials[m].friction_deg for m in range(len(sc.materials))]
     alpha = torch.tensor([dp_alpha(p) for p in phi], dtype=DT)[torch.from_numpy(mat).long()]
     kappa = torch.where(mu > 0, (3.0 * lam + 2.0 * mu) / (2.0 * torch.where(mu > 0, mu, torch.ones_like(mu))), torch.zeros_like(mu))
-    ys = torch.tensor([getattr(sc.materials[m], "yield_stress", 0.0) for m in range(len(sc.materials))],
-                      dtype=DT)[torch.from_numpy(mat).long()]
+    def per_opt(attr):
+        return torch.tensor([getattr(sc.materials[m], attr, 0.0) for m in range(len(sc.materials))],
+                            dtype=DT)[torch.from_numpy(mat).long()]
+    ys = per_opt("yield_stress")
     yrad = torch.where(mu > 0, ys / (2.0 * torch.where(mu > 0, mu, torch.ones_like(mu))), torch.zeros_like(mu))
     p = Params(n_grid=sc.n_grid, dt=sc.dt, gravity=torch.tensor(sc.gravity, dtype=DT), bound=sc.bound,
                kind=kind, mu=mu, lam=lam, eta=per("viscosity"), alpha=alpha, kappa=kappa,
-               cohesion=per("cohesion"), yield_radius=yrad, vol=per("p_vol"), mass=per("p_mass"),
+               cohesion=per("cohesion"), yield_radius=yrad,
+               box_lo=1.0 - per_opt("theta_c"), box_hi=1.0 + per_opt("theta_s"),
+               vol=per("p_vol"), mass=per("p_mass"),
                cyl_radius=sc.cyl_radius, contact_band=sc.contact_band, friction=sc.contact_friction)
     p.idx_el = torch.nonzero(kind == ELASTIC)[:, 0]
     p.idx_liq = torch.nonzero(kind == LIQUID)[:, 0]
     p.idx_sand = torch.nonzero(kind == SAND)[:, 0]
     p.idx_vm = torch.nonzero(kind == VONMISES)[:, 0]
+    p.idx_box = torch.nonzero(kind == BOX)[:, 0]
     return p
 
 
@@ -400,6 +425,9 @@ def kirchhoff_stress(st, p: Params):
     if p.idx_vm.numel():
         i = p.idx_vm
         tau = tau.index_put((i,), stress_sand(st["F"][i], p.mu[i], p.lam[i]))   # Hencky as well
+    if p.idx_box.numel():
+        i = p.idx_box
+        tau = tau.index_put((i,), stress_fixed_corotated(st["F"][i], p.mu[i], p.lam[i]))
     return tau
 
 
@@ -496,7 +524,8 @@ def g2p(st, vgrid, p: Params):
     """Grid-to-particle: v' = sum w v_i; C' = (4/dx^2) sum w v_i (x_i - x_p)^T;
     x' = x + dt v'; F_tr = (I + dt C') F; elastic F' = F_tr; liquid
     J' = J det(I + dt C'); sand F' = Drucker-Prager projection of F_tr;
-    von Mises F' = von Mises projection of F_tr."""
+    von Mises F' = von Mises projection of F_tr; Box yield F' = F_tr with its
+    singular values clamped."""
     n, dx, dt = p.n_grid, p.dx, p.dt
     base, f, W, dpos = bspline(st["x"], dx)
     idx = node_index(base, n)
@@ -519,6 +548,9 @@ def g2p(st, vgrid, p: Params):
     if p.idx_vm.numel():
         i = p.idx_vm
         F_new = F_new.index_put((i,), IsotropicMap.apply(F_tr[i], make_g_vm(p.yield_radius[i])))
+    if p.idx_box.numel():
+        i = p.idx_box
+        F_new = F_new.index_put((i,), IsotropicMap.apply(F_tr[i], make_g_box(p.box_lo[i], p.box_hi[i])))
     out = {"x": x_new, "v": v_new, "C": C_new, "F": F_new, "J": J_new}
     for k, t in out.items():
         if not torch.isfinite(t).all():

@@ -24,6 +24,7 @@ ELASTIC = 0   # fixed-corotated elastic solid
 LIQUID = 1    # weakly compressible liquid, J-based pressure + Newtonian viscosity
 SAND = 2      # Hencky elasticity + Drucker-Prager plasticity
 VONMISES = 3  # Hencky elasticity + von Mises plasticity (the non-Newtonian ice cream)
+BOX = 4       # corotated elasticity + Box yield (the plastic material, Stomakhin 2013)
 
 # Table 4 (Appendix B.1) constants used by the synthetic scenes.
 WATER_LAMBDA = 277.78
@@ -38,6 +39,13 @@ def ice_cream():
     """Table 4's non-Newtonian ice cream (mu 416.67, lambda 277.78, rho 0.5)
     as a von Mises elastoplastic continuum."""
     return Material(VONMISES, SOLID_MU, SOLID_LAMBDA, 0.5, yield_stress=ICE_CREAM_YIELD)
+
+
+def plasticine():
+    """A Box-yield plastic with Table 4's solid constants (mu 416.67,
+    lambda 277.78, rho 1) and Stomakhin et al.'s critical compression and
+    stretch (2.5e-2, 7.5e-3)."""
+    return Material(BOX, SOLID_MU, SOLID_LAMBDA, 1.0, theta_c=2.5e-2, theta_s=7.5e-3)
 
 
 def lame(E: float, nu: float):
@@ -57,6 +65,8 @@ class Material:
     friction_deg: float = 30.0
     cohesion: float = 0.0
     yield_stress: float = 0.0   # von Mises yield stress (Kirchhoff)
+    theta_c: float = 0.0        # Box yield: critical compression
+    theta_s: float = 0.0        # Box yield: critical stretch
     p_vol: float = 0.0    # initial particle volume V_p = V_box / N_box
     p_mass: float = 0.0   # m_p = rho * V_p
 
@@ -310,6 +320,8 @@ def tiny(n_particles: int = 125, n_grid: int = 16, steps: int = 10, seed: int = 
             m = Material(LIQUID, 0.0, WATER_LAMBDA, 1.0, viscosity=0.1)
         elif kind == VONMISES:
             m = ice_cream()
+        elif kind == BOX:
+            m = plasticine()
         else:
             m = Material(SAND, SOLID_MU, SOLID_LAMBDA, 1.0, friction_deg=30.0, cohesion=0.0)
         boxes.append((pos, m, side ** 3))

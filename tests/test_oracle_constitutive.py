@@ -316,3 +316,39 @@ def test_vm_isotropic_map_derivative_fd():
     gbar = torch.tensor(rng.normal(0, 1, (n, 3, 3)), dtype=DT)
     ga, num = fd_check(fun, F, gbar, eps=1e-7)
     assert torch.allclose(ga, num, atol=2e-6)
+
+
+# ---------------------------------------------------------------------------
+# Box yield (the plastic material): clamped singular values
+# ---------------------------------------------------------------------------
+def test_box_clamp_closed_forms():
+    lo = torch.tensor([0.975], dtype=DT)
+    hi = torch.tensor([1.0075], dtype=DT)
+    g = O.make_g_box(lo, hi)
+    gv, dg = g(torch.tensor([[1.02, 1.0, 0.95]], dtype=DT))
+    assert torch.equal(gv, torch.tensor([[1.0075, 1.0, 0.975]], dtype=DT))
+    assert torch.equal(torch.diagonal(dg[0]), torch.tensor([0.0, 1.0, 0.0], dtype=DT))
+    # a rotation is untouched; a uniform stretch beyond the limit comes back to it
+    R = torch.tensor(Rotation.random(1, random_state=40).as_matrix(), dtype=DT)
+    assert torch.allclose(O.IsotropicMap.apply(R, g), R, atol=1e-14)
+    Fs = 1.1 * R
+    assert torch.allclose(O.IsotropicMap.apply(Fs, g), 1.0075 * R, atol=1e-14)
+
+
+def test_box_isotropic_map_derivative_fd():
+    rng = np.random.default_rng(41)
+    sig = np.array([[1.02, 0.99, 0.96],          # stretch and compression clamped
+                    [1.001, 1.0, 0.999],         # inside
+                    [1.001, 1.001, 0.99],        # inside, repeated pair
+                    [1.03, 1.03, 0.98],          # clamped repeated pair
+                    [0.97, 0.96, 0.95]])         # all compressed
+    n = sig.shape[0]
+    U = Rotation.random(n, random_state=42).as_matrix()
+    V = Rotation.random(n, random_state=43).as_matrix()
+    F = torch.tensor(U @ (sig[:, :, None] * np.swapaxes(V, -1, -2)), dtype=DT)
+    lo = torch.full((n,), 0.975, dtype=DT)
+    hi = torch.full((n,), 1.0075, dtype=DT)
+    fun = lambda X: O.IsotropicMap.apply(X, O.make_g_box(lo, hi))
+    gbar = torch.tensor(rng.normal(0, 1, (n, 3, 3)), dtype=DT)
+    ga, num = fd_check(fun, F, gbar, eps=1e-7)
+    assert torch.allclose(ga, num, atol=2e-6)

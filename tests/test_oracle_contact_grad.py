@@ -162,11 +162,13 @@ def _generic_loss(st, wx, wv):
     return (st["x"] * wx).sum() + (st["v"] * wv).sum()
 
 
-@pytest.mark.parametrize("seed,kinds", [(0, None), (1, None), (2, (scenes.VONMISES, scenes.LIQUID))])
+@pytest.mark.parametrize("seed,kinds", [(0, None), (1, None), (2, (scenes.VONMISES, scenes.LIQUID)),
+                                        (3, (scenes.BOX, scenes.LIQUID))])
 def test_rollout_gradient_fd(seed, kinds):
     """d L / d actions and d L / d x_0 by autograd against central FD in
     float64 on a tiny scene with the cylinder in contact (5 steps): all three
-    base materials, or the von Mises ice cream with water."""
+    base materials, or the von Mises ice cream or the Box-yield plastic with
+    water."""
     kw = {} if kinds is None else {"kinds": kinds, "velocity": 3.0}
     sc = scenes.tiny(n_particles=45, n_grid=16, steps=5, seed=seed, **kw)
     rng = np.random.default_rng(100 + seed)
