@@ -60,15 +60,17 @@ typedef enum {
   MPM_ELASTIC_FCR = 0,  /* fixed-corotated elastic solid (the paper's corotated model) */
   MPM_LIQUID_J = 1,     /* liquid: J-based pressure + Newtonian viscosity (F reset, section 3.2) */
   MPM_SAND_DP = 2,      /* Hencky elasticity + Drucker-Prager projection (Klar et al. 2016) */
-  MPM_PLASTIC_VM = 3    /* Hencky elasticity + von Mises projection in log strain: the
+  MPM_PLASTIC_VM = 3,   /* Hencky elasticity + von Mises projection in log strain: the
                            non-Newtonian ice cream of section 3.2 */
+  MPM_PLASTIC_BOX = 4   /* corotated elasticity + Box yield (singular values of F clamped to
+                           [1 - theta_c, 1 + theta_s]): the plastic material of section 3.2 */
 } mpm_material_kind;
 
 /* Error bits of the device error word (returned by mpm_last_error_bits). */
 enum {
   MPM_ERR_OUTSIDE = 1,     /* a particle stencil left the grid */
   MPM_ERR_NONFINITE = 2,   /* a non-finite particle value */
-  MPM_ERR_SAND_SIGMA = 4,  /* a sand or von Mises singular value <= 0 */
+  MPM_ERR_SAND_SIGMA = 4,  /* a sand, von Mises or Box-yield singular value <= 0 */
   MPM_ERR_TILE = 8         /* a particle moved farther than the kernels' tiles allow (CFL > 1) */
 };
 
@@ -86,6 +88,7 @@ typedef struct {
   float p_vol, p_mass;
   float yield_stress;    /* von Mises: yield stress; the return radius in log strain is
                             yield_stress / (2 mu) */
+  float theta_c, theta_s; /* Box yield: critical compression (0 <= theta_c < 1) and stretch */
 } mpm_material;
 
 /* Particle state: SoA device pointers, see Conventions.  mat may be NULL in

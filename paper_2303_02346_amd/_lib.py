@@ -13,7 +13,8 @@ MPM_OK, MPM_EINVAL, MPM_EWORKSPACE, MPM_EHIP, MPM_EDOMAIN, MPM_ESTATE = 0, -1, -
 class MpmMaterial(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("mu", ctypes.c_float), ("lambda_", ctypes.c_float),
                 ("viscosity", ctypes.c_float), ("friction_deg", ctypes.c_float), ("cohesion", ctypes.c_float),
-                ("p_vol", ctypes.c_float), ("p_mass", ctypes.c_float), ("yield_stress", ctypes.c_float)]
+                ("p_vol", ctypes.c_float), ("p_mass", ctypes.c_float), ("yield_stress", ctypes.c_float),
+                ("theta_c", ctypes.c_float), ("theta_s", ctypes.c_float)]
 
 
 class MpmState(ctypes.Structure):

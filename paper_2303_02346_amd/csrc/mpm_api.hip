@@ -219,7 +219,7 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   memset(c->mats.data(), 0, 256 * sizeof(MatDev));
   for (int m = 0; m < d->n_materials; m++) {
     const mpm_material& src = d->materials[m];
-    if (src.kind < 0 || src.kind > 3 || !(src.p_mass > 0.f) || !(src.p_vol > 0.f)) { delete c; return MPM_EINVAL; }
+    if (src.kind < 0 || src.kind > 4 || !(src.p_mass > 0.f) || !(src.p_vol > 0.f)) { delete c; return MPM_EINVAL; }
     MatDev& M = c->mats[m];
     M.kind = src.kind;
     M.mu = src.mu;
@@ -234,6 +234,12 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
     M.yrad = src.mu > 0.f ? src.yield_stress / (2.f * src.mu) : 0.f;
     if ((src.kind == MPM_SAND_DP || src.kind == MPM_PLASTIC_VM) && !(src.mu > 0.f)) { delete c; return MPM_EINVAL; }
     if (src.kind == MPM_PLASTIC_VM && !(src.yield_stress >= 0.f)) { delete c; return MPM_EINVAL; }
+    M.box_lo = 1.f - src.theta_c;
+    M.box_hi = 1.f + src.theta_s;
+    if (src.kind == MPM_PLASTIC_BOX && !(src.theta_c >= 0.f && src.theta_c < 1.f && src.theta_s >= 0.f)) {
+      delete c;
+      return MPM_EINVAL;
+    }
   }
   c->cyl_radius.assign(d->cyl_radius, d->cyl_radius + S);
   c->cyl_pos0.assign(d->cyl_pos0, d->cyl_pos0 + 3 * S);

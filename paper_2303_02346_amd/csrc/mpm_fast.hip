@@ -409,6 +409,12 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
               ok = false;
 #pragma unroll
               for (int k = 0; k < 9; k++) F[k] = (float)Ft[k];
+            } else if (M.kind == KIND_BOX) {
+              double gg[3], Fo[9];
+              const bool clamped = box_clamp(s, M, gg);
+              if (clamped) usv(Uu, gg, V, Fo);
+#pragma unroll
+              for (int k = 0; k < 9; k++) F[k] = (float)(clamped ? Fo[k] : Ft[k]);
             } else {
               double e[3] = {log(s[0]), log(s[1]), log(s[2])}, ep[3];
               DPInfo I;

@@ -6,7 +6,7 @@
 
 namespace mpm {
 
-enum { KIND_ELASTIC = 0, KIND_LIQUID = 1, KIND_SAND = 2, KIND_VONMISES = 3 };
+enum { KIND_ELASTIC = 0, KIND_LIQUID = 1, KIND_SAND = 2, KIND_VONMISES = 3, KIND_BOX = 4 };
 enum { ERR_OUTSIDE = 1, ERR_NONFINITE = 2, ERR_SAND_SIGMA = 4, ERR_TILE = 8 };
 
 // Per-material constants as the kernels use them (alpha, kappa precomputed).
@@ -16,7 +16,7 @@ struct MatDev {
   float alpha, kappa, coh;
   float vol, mass;
   float yrad;          // von Mises return radius in log strain, yield / (2 mu)
-  float pad[2];
+  float box_lo, box_hi; // Box yield: singular values clamped to [box_lo, box_hi]
 };
 
 // Particle state, structure of arrays: component k of particle p at ptr[k*N + p].

@@ -79,10 +79,14 @@ MPM_DI void stress_liquid_adjoint(float J, const float* C, const MatDev& M, cons
 // Solids, FP64 inside: fixed corotated tau = 2 mu (F - R) F^T + lam J (J-1) I
 // with R = U V^T; Hencky tau = U diag(2 mu eps + lam tr eps) U^T, eps = log s.
 // Returns false when a sand singular value is not positive.
+// Solids with the corotated stress (elastic and Box-yield plastic); the
+// other solids (sand, von Mises) use Hencky.
+MPM_DI bool corotated_kind(int kind) { return kind == KIND_ELASTIC || kind == KIND_BOX; }
+
 // The stress from a given signed SVD F = U diag(s) V^T of the FP64 copy F.
 MPM_DI bool stress_solid_usv(const double* F, const double* U, const double* s, const double* V, const MatDev& M,
                              float* tau) {
-  if (M.kind == KIND_ELASTIC) {
+  if (corotated_kind(M.kind)) {
     double R[9], D[9], T[9];
     matmul_nt(U, V, R);
 #pragma unroll
@@ -126,7 +130,7 @@ MPM_DI void stress_solid_adjoint_usv(const double* F, const double* U, const dou
 #pragma unroll
   for (int k = 0; k < 9; k++) tb[k] = (double)taubf[k];
   double Fb[9];
-  if (M.kind == KIND_ELASTIC) {
+  if (corotated_kind(M.kind)) {
     double R[9], D[9], T1[9], T2[9], Rb[9];
     matmul_nt(U, V, R);
 #pragma unroll
@@ -249,6 +253,18 @@ MPM_DI void vm_project(const double* e, const MatDev& M, double* ep, DPInfo& I) 
   }
 }
 
+// Box yield (section 3.2's plastic material, Stomakhin et al. 2013): the
+// singular values clamped to [box_lo, box_hi]; returns whether any changed.
+MPM_DI bool box_clamp(const double* s, const MatDev& M, double* g) {
+  bool changed = false;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    g[a] = fmin(fmax(s[a], (double)M.box_lo), (double)M.box_hi);
+    changed |= g[a] != s[a];
+  }
+  return changed;
+}
+
 // The return map of a plastic material (sand or von Mises).
 MPM_DI void plastic_project(const double* e, const MatDev& M, double* ep, DPInfo& I) {
   if (M.kind == KIND_VONMISES) vm_project(e, M, ep, I);
@@ -295,6 +311,12 @@ MPM_DI void particle_update(const float* x, const float* vn, const float* B, con
         U.ok_sigma = false;
 #pragma unroll
         for (int k = 0; k < 9; k++) U.F[k] = (float)Ft[k];
+      } else if (M.kind == KIND_BOX) {
+        double g[3], Fo[9];
+        bool clamped = box_clamp(s, M, g);
+        if (clamped) usv(Uu, g, V, Fo);
+#pragma unroll
+        for (int k = 0; k < 9; k++) U.F[k] = (float)(clamped ? Fo[k] : Ft[k]);
       } else {
         double e[3] = {log(s[0]), log(s[1]), log(s[2])}, ep[3], g[3], Fo[9];
         DPInfo I;
@@ -363,6 +385,32 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
 #pragma unroll
       for (int a = 0; a < 3; a++) e[a] = ok ? log(s[a]) : 0.0;
       DPInfo I;
+      if (M.kind == KIND_BOX) {
+        // clamp: dg = diag(inside), divided differences (g_i - g_j)/(s_i - s_j)
+        double g[3], dg[9], sdd[9], Pb[9], Fr[9];
+        const bool clamped = ok && box_clamp(s, M, g);
+        if (!clamped) {
+#pragma unroll
+          for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) dg[i * 3 + k] = (i == k && g[i] == s[i]) ? 1.0 : 0.0;
+#pragma unroll
+          for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+              const double d = s[i] - s[j];
+              sdd[i * 3 + j] = (i == j) ? 0.0 : (fabs(d) > 1e-12 ? (g[i] - g[j]) / d : dg[i * 3 + i]);
+            }
+#pragma unroll
+          for (int k = 0; k < 9; k++) Pb[k] = (double)Fb[k];
+          iso_adjoint(Uu, s, V, g, dg, sdd, Pb, Fr);
+#pragma unroll
+          for (int k = 0; k < 9; k++) Ftb[k] = (float)Fr[k];
+        }
+      } else {
       plastic_project(e, M, ep, I);
       if (!ok || I.cse == 0) {
 #pragma unroll
@@ -393,6 +441,7 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
         iso_adjoint(Uu, s, V, g, dg, sdd, Pb, Fr);
 #pragma unroll
         for (int k = 0; k < 9; k++) Ftb[k] = (float)Fr[k];
+      }
       }
     }
     // F_tr = Md F : Cbar += dt Ftb F^T ; Fbar = Md^T Ftb

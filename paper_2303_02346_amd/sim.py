@@ -50,7 +50,7 @@ class Simulator:
         self._mats = (_lib.MpmMaterial * len(mats))()
         for i, m in enumerate(mats):
             self._mats[i] = _lib.MpmMaterial(m.kind, m.mu, m.lam, m.viscosity, m.friction_deg, m.cohesion, m.p_vol, m.p_mass,
-                                             m.yield_stress)
+                                             m.yield_stress, m.theta_c, m.theta_s)
         self._offs = (ctypes.c_int64 * (self.S + 1))(*[int(o) for o in offs])
         self._rad = (ctypes.c_float * self.S)(*[float(sc.cyl_radius) for sc in self.scenes])
         self._pos = (ctypes.c_float * (3 * self.S))(*np.concatenate([np.asarray(sc.cyl_pos0, np.float64) for sc in self.scenes]).tolist())

@@ -230,3 +230,40 @@ def test_von_mises_gradient_vs_oracle(adjoint):
     say(f"  loss gpu {loss.item():.8f} ref {L.item():.8f}; actions rel {ea:.2e}, dL/dx0 rel {ex:.2e}")
     assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
     assert ea <= 1e-4 and ex <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Box-yield plastic (section 3.2's plastic material)
+# ---------------------------------------------------------------------------
+def _plasticine_scene(steps, n=600, seed=7):
+    return scenes.tiny(n_particles=n, n_grid=24, steps=steps, seed=seed,
+                       kinds=(scenes.BOX, scenes.LIQUID), velocity=3.0, dt=1e-4)
+
+
+def test_box_yield_forward_vs_oracle():
+    sc = _plasticine_scene(20)
+    say("Box-yield plastic, 20 steps")
+    sim = sim_of(sc)
+    sim.step(20)
+    compare_states(sim.state_numpy(), oracle_state(sc, 20), liquid_mask(sc), tol_x=1e-5, tol=2e-3)
+
+
+@pytest.mark.parametrize("adjoint", ["tiled", "plain"])
+def test_box_yield_gradient_vs_oracle(adjoint):
+    sc = _plasticine_scene(8, n=120, seed=8)
+    say(f"Box-yield gradient, {adjoint} adjoint")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=3, adjoint=adjoint)
+    sim.step(sc.horizon)
+    loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
+    ga, g0 = sim.backward(g[0:3], torch.zeros_like(g[0:3]), want_grad0=True)
+    p = O.params_from_scene(sc)
+    acts = torch.tensor(sc.actions, dtype=torch.float64, requires_grad=True)
+    st0 = O.state_from_scene(sc, requires_grad=True)
+    st = O.rollout(sc, actions=acts, state=st0, params=p)
+    L = O.blob_loss(st["x"], p.kind == O.LIQUID, torch.tensor(sc.target_mu, dtype=torch.float64), sc.target_sigma)
+    L.backward()
+    ea = rel(ga[:, 0].double().cpu().numpy(), acts.grad.numpy())
+    ex = rel(g0[0:3].T.double().cpu().numpy(), st0["x"].grad.numpy())
+    say(f"  loss gpu {loss.item():.8f} ref {L.item():.8f}; actions rel {ea:.2e}, dL/dx0 rel {ex:.2e}")
+    assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
+    assert ea <= 1e-4 and ex <= 1e-4
