@@ -20,7 +20,8 @@ struct AdjArgs {
   int2* tile_box;
   const uint32_t* gen;       // stamp epoch
   uint32_t sid;              // stamp step id of the velocity-adjoint tiles
-  const uint32_t* won;       // per list entry: neighbour blocks claimed by the recompute
+  const uint32_t* cl_list;   // blocks claimed by the recompute of step t
+  const uint32_t* cl_count;
   const float4* mmv;         // node momenta and masses of step t (block layout)
   float4* mmvb;              // their adjoints (block layout)
 };

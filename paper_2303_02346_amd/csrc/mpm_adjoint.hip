@@ -305,46 +305,46 @@ __global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P
 __global__ __launch_bounds__(256) void k_grid_adj_tiled(AdjArgs A, StepParams P, FastGeom g,
                                                         const double* __restrict__ pose_t,
                                                         const float* __restrict__ act_t, double* __restrict__ acc_t) {
-  const uint32_t n_list = A.list_n[0];
+  const uint32_t n_cl = A.cl_count[0];
   const uint32_t stamp = (A.gen[0] << 16) | A.sid;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane >> 4, lj = (lane >> 2) & 3, lk = lane & 3;
-  for (uint32_t e = blockIdx.x; e < n_list; e += gridDim.x) {
-    uint32_t mask = A.won[e];
-    if (!mask) continue;
-    int sc, bx, by, bz;
-    key_decode(g, (uint32_t)A.list[e].x, sc, bx, by, bz);
-    for (int jb = 0; mask; jb++) {
-      const int d = __ffs(mask) - 1;
-      mask &= mask - 1u;
-      if ((jb & 3) != wv) continue;
-      const int cx = bx + d / 9 - 1, cy = by + (d / 3) % 3 - 1, cz = bz + d % 3 - 1;
-      const uint32_t key = block_key(g, sc, cx, cy, cz);
+  // one claimed block per wavefront (see k_grid)
+  const uint32_t n_waves = 4u * gridDim.x;
+  for (uint32_t it = 4u * blockIdx.x + (uint32_t)wv; it < n_cl && it < (uint32_t)g.n_keys; it += n_waves) {
+    const uint32_t key = A.cl_list[it];
+    int sc, cx, cy, cz;
+    key_decode(g, key, sc, cx, cy, cz);
+    {
       int2 nbox = make_int2(0, 0);
+      uint32_t nkey = 0;
       if (lane < 27) {
         const int sx = cx + lane / 9 - 1, sy = cy + (lane / 3) % 3 - 1, sz = cz + lane % 3 - 1;
         if (sx >= 0 && sy >= 0 && sz >= 0 && sx < g.nb && sy < g.nb && sz < g.nb) {
-          nbox = A.tile_box[block_key(g, sc, sx, sy, sz)];
+          nkey = block_key(g, sc, sx, sy, sz);
+          nbox = A.tile_box[nkey];
           if ((uint32_t)nbox.y != stamp) nbox.y = 0;
         }
       }
       const int gx = 4 * cx + li, gy = 4 * cy + lj, gz = 4 * cz + lk;
+      // branch-free over the 27 neighbours (see k_grid)
       float vb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int dd = 0; dd < 27; dd++) {
         const int bxv = __shfl(nbox.x, dd);
         const int valid = __shfl(nbox.y, dd);
-        if (!valid) continue;
+        const uint32_t kk = __shfl(nkey, dd);
         const int sx = cx + dd / 9 - 1, sy = cy + (dd / 3) % 3 - 1, sz = cz + dd % 3 - 1;
         const int qi = gx - (4 * sx - 2), qj = gy - (4 * sy - 2), qk = gz - (4 * sz - 2);
         const int lo0 = bxv & 15, lo1 = (bxv >> 4) & 15, lo2 = (bxv >> 8) & 15;
         const int hi0 = (bxv >> 12) & 15, hi1 = (bxv >> 16) & 15, hi2 = (bxv >> 20) & 15;
-        if (qi < lo0 || qi > hi0 || qj < lo1 || qj > hi1 || qk < lo2 || qk > hi2) continue;
-        const int q = (qi * TILE + qj) * TILE + qk;
-        const float* T = A.tiles + (size_t)block_key(g, sc, sx, sy, sz) * 4 * TILE_NODES;
-        vb[0] += T[q];
-        vb[1] += T[TILE_NODES + q];
-        vb[2] += T[2 * TILE_NODES + q];
+        const bool in = valid && qi >= lo0 && qi <= hi0 && qj >= lo1 && qj <= hi1 && qk >= lo2 && qk <= hi2;
+        const int q = in ? (qi * TILE + qj) * TILE + qk : 0;
+        const float* T = A.tiles + (size_t)(in ? kk : 0u) * 4 * TILE_NODES;
+        const float t0 = T[q], t1 = T[TILE_NODES + q], t2 = T[2 * TILE_NODES + q];
+        vb[0] += in ? t0 : 0.f;
+        vb[1] += in ? t1 : 0.f;
+        vb[2] += in ? t2 : 0.f;
       }
       const size_t node = (size_t)key * 64 + lane;
       const float4 gm = A.mmv[node];

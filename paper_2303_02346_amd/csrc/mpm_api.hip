@@ -21,7 +21,7 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 // Per-step record of a block-sorted segment state of the tiled adjoint
 // (offsets relative to the record's start).
 struct SortedRec {
-  size_t f, id, key, rank, mat, map, list, list_n, vgrid, mmv, won, bytes;
+  size_t f, id, key, rank, mat, map, list, list_n, vgrid, mmv, cl_list, cl_count, bytes;
   bool has_grid;
 };
 
@@ -33,7 +33,8 @@ SortedRec sorted_rec(size_t N, size_t n_keys, bool with_grid) {
   auto take = [&](size_t b) { size_t q = o; o += align_up(b); return q; };
   r.vgrid = with_grid ? take(n_keys * 64 * sizeof(float4)) : 0;
   r.mmv = with_grid ? take(n_keys * 64 * sizeof(float4)) : 0;
-  r.won = with_grid ? take(n_keys * 4) : 0;
+  r.cl_list = with_grid ? take(n_keys * 4) : 0;
+  r.cl_count = with_grid ? take(16) : 0;
   r.f = take(STATE_FLOATS * N * sizeof(float));
   r.id = take(N * 4);
   r.key = take(N * 4);
@@ -366,7 +367,8 @@ static SortedState sorted_state(mpm_ctx* c, size_t base, bool tmp = false) {
   SortedState S;
   S.vgrid = r.has_grid ? (float4*)(b + r.vgrid) : nullptr;
   S.mmv = r.has_grid ? (float4*)(b + r.mmv) : nullptr;
-  S.won = r.has_grid ? (uint32_t*)(b + r.won) : nullptr;
+  S.cl_list = r.has_grid ? (uint32_t*)(b + r.cl_list) : nullptr;
+  S.cl_count = r.has_grid ? (uint32_t*)(b + r.cl_count) : nullptr;
   S.b.f = (float*)(b + r.f);
   S.b.id = (uint32_t*)(b + r.id);
   S.b.key = (uint32_t*)(b + r.key);
@@ -425,7 +427,8 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
       A.tile_box = f.tile_box;
       A.gen = f.gen;
       A.sid = fast_next_sid(f);
-      A.won = Si.won;
+      A.cl_list = Si.cl_list;
+      A.cl_count = Si.cl_count;
       A.mmv = Si.mmv;
       A.mmvb = mmvb_blk;
       launch_g2p_adj_tiled(A, P, f.g, f.part_wgs, s);

@@ -57,7 +57,8 @@ struct FastPath {
   int4* list[3];           // occupied-block lists (rotating)
   uint32_t* list_n;        // [3]
   uint32_t* claim;         // per-block stamp: which step last updated the block
-  uint32_t* won;           // per list entry: mask of the neighbour blocks it claimed
+  uint32_t* cl_list;       // keys of the blocks claimed in the current step
+  uint32_t* cl_count;      // [2]: claims of odd and even step ids
   int2* tile_box;          // {packed lo/hi, stamp}
   float* tiles;            // n_keys x 4 x TILE_NODES
   float4* vgrid;           // n_keys x 64
@@ -93,10 +94,11 @@ struct SortedState {
   uint32_t* list_n;
   // the step's grid, kept for the adjoint (block layout; NULL = the path's
   // shared arrays): updated velocities and masses, node momenta and masses,
-  // and the per-entry masks of the blocks claimed by its P2G
+  // and the list and number of the blocks claimed by its P2G
   float4* vgrid;
   float4* mmv;
-  uint32_t* won;
+  uint32_t* cl_list;
+  uint32_t* cl_count;      // [2]
 };
 
 size_t fast_workspace_bytes(int n_grid, int n_scenes, int N);

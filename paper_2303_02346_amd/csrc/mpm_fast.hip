@@ -153,11 +153,12 @@ __device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ 
 }
 
 // the import's scan; also advances the per-call epoch of the step stamps
+// (and clears the two claimed-block counters of the steps that follow)
 __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
-                                               uint32_t* __restrict__ epoch) {
+                                               uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count) {
   scan_keys<1024>(counts, offsets, list, list_n, n_keys);
-  if (threadIdx.x == 0) epoch[0] = epoch[0] + 1;
+  if (threadIdx.x == 0) { epoch[0] = epoch[0] + 1; cl_count[0] = 0u; cl_count[1] = 0u; }
 }
 
 
@@ -256,7 +257,8 @@ struct PartArgs {
   int2* tile_box;
   int n_keys;
   uint32_t* claim;             // per-block stamp of the step that claimed it
-  uint32_t* won;               // per entry: mask of the 27 neighbours it claimed
+  uint32_t* cl_list;           // keys of the blocks claimed in this step
+  uint32_t* cl_count;          // their number
   const uint32_t* gen;         // per-call epoch
   uint32_t step_id;            // 1-based step within the call
   const float4* vgrid;
@@ -734,22 +736,31 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
           A.tile_box[bkey] = make_int2(packed, (int)stamp);
         }
         // claim the blocks this tile touches: the first entry to claim a block
-        // in this step updates it in the grid kernel
+        // in this step appends it to the list the grid kernel works through
         if (tid < 64) {
           bool won = false;
+          uint32_t nk = 0;
           if (tid < 27) {
             const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
             const int nbx = bx + dx, nby = by + dy, nbz = bz + dz;
             const int l0 = 4 * dx + 2, l1 = 4 * dy + 2, l2 = 4 * dz + 2;
             const bool hit = nbx >= 0 && nby >= 0 && nbz >= 0 && nbx < g.nb && nby < g.nb && nbz < g.nb &&
                              l0 <= hi0 && l0 + 3 >= lo0 && l1 <= hi1 && l1 + 3 >= lo1 && l2 <= hi2 && l2 + 3 >= lo2;
-            if (hit) won = atomicExch(&A.claim[block_key(g, sc, nbx, nby, nbz)], stamp) != stamp;
+            if (hit) {
+              nk = block_key(g, sc, nbx, nby, nbz);
+              won = atomicExch(&A.claim[nk], stamp) != stamp;
+            }
           }
           const unsigned long long wm = __ballot(won);
-          if (tid == 0) A.won[e] = (uint32_t)wm;
+          if (wm) {
+            uint32_t base = 0;
+            if (tid == 0) base = atomicAdd(A.cl_count, (uint32_t)__popcll(wm));
+            base = __shfl(base, 0);
+            // a block is claimed once per step, so at most n_keys keys arrive
+            const uint32_t slot = base + (uint32_t)__popcll(wm & ((1ull << tid) - 1ull));
+            if (won && slot < (uint32_t)A.n_keys) A.cl_list[slot] = nk;
+          }
         }
-      } else if (tid == 0) {
-        A.won[e] = 0u;
       }
       __syncthreads();
     }
@@ -773,8 +784,8 @@ struct ScanArgs {
 
 // With do_scan, workgroup 0 scans the key counts of this step's particle
 // kernel (independent of the grid work) and the others do the grid update.
-__global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const int4* __restrict__ list,
-                                              const uint32_t* __restrict__ list_n, const uint32_t* __restrict__ won,
+__global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const uint32_t* __restrict__ cl_list,
+                                              const uint32_t* __restrict__ cl_count, uint32_t* __restrict__ cl_zero,
                                               const int2* __restrict__ tile_box, const float* __restrict__ tiles,
                                               const uint32_t* __restrict__ gen, uint32_t step_id,
                                               float4* __restrict__ vgrid, const double* __restrict__ pose_base,
@@ -791,48 +802,50 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const in
   const size_t t = t_fixed >= 0 ? (size_t)t_fixed : (size_t)t0_dev[0] + step_id - 1;
   const double* pose_t = pose_base + t * g.S * POSE_DOUBLES;
   const float* act_t = act_base + t * g.S * 6;
-  const uint32_t n_list = list_n[0];
+  const uint32_t n_cl = cl_count[0];
+  // the counter of the next step's claims starts at zero (nothing reads it now)
+  if (cl_zero && wg == 0 && threadIdx.x == 0) cl_zero[0] = 0u;
   const uint32_t stamp = (gen[0] << 16) | step_id;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane >> 4, lj = (lane >> 2) & 3, lk = lane & 3;
-  for (uint32_t e = wg; e < n_list; e += n_wg) {
-    uint32_t mask = won[e];
-    if (!mask) continue;
-    int sc, bx, by, bz;
-    key_decode(g, (uint32_t)list[e].x, sc, bx, by, bz);
-    // the j-th claimed block goes to wavefront j % 4
-    for (int j = 0; mask; j++) {
-      const int d = __ffs(mask) - 1;
-      mask &= mask - 1u;
-      if ((j & 3) != wv) continue;
-      const int cx = bx + d / 9 - 1, cy = by + (d / 3) % 3 - 1, cz = bz + d % 3 - 1;
-      const uint32_t key = block_key(g, sc, cx, cy, cz);
+  // one claimed block per wavefront
+  const uint32_t n_waves = 4u * n_wg;
+  for (uint32_t it = 4u * wg + (uint32_t)wv; it < n_cl && it < (uint32_t)g.n_keys; it += n_waves) {
+    const uint32_t key = cl_list[it];
+    int sc, cx, cy, cz;
+    key_decode(g, key, sc, cx, cy, cz);
+    {
       int2 nbox = make_int2(0, 0);
+      uint32_t nkey = 0;
       if (lane < 27) {
         const int sx = cx + lane / 9 - 1, sy = cy + (lane / 3) % 3 - 1, sz = cz + lane % 3 - 1;
         if (sx >= 0 && sy >= 0 && sz >= 0 && sx < g.nb && sy < g.nb && sz < g.nb) {
-          nbox = tile_box[block_key(g, sc, sx, sy, sz)];
+          nkey = block_key(g, sc, sx, sy, sz);
+          nbox = tile_box[nkey];
           if ((uint32_t)nbox.y != stamp) nbox.y = 0;
         }
       }
       const int gx = 4 * cx + li, gy = 4 * cy + lj, gz = 4 * cz + lk;
+      // branch-free over the 27 neighbours so that all tile loads are in
+      // flight together (a lane outside a tile's box reads slot 0 and adds 0)
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int dd = 0; dd < 27; dd++) {
         const int bxv = __shfl(nbox.x, dd);
         const int valid = __shfl(nbox.y, dd);
-        if (!valid) continue;
+        const uint32_t kk = __shfl(nkey, dd);
         const int sx = cx + dd / 9 - 1, sy = cy + (dd / 3) % 3 - 1, sz = cz + dd % 3 - 1;
         const int qi = gx - (4 * sx - 2), qj = gy - (4 * sy - 2), qk = gz - (4 * sz - 2);
         const int lo0 = bxv & 15, lo1 = (bxv >> 4) & 15, lo2 = (bxv >> 8) & 15;
         const int hi0 = (bxv >> 12) & 15, hi1 = (bxv >> 16) & 15, hi2 = (bxv >> 20) & 15;
-        if (qi < lo0 || qi > hi0 || qj < lo1 || qj > hi1 || qk < lo2 || qk > hi2) continue;
-        const int q = (qi * TILE + qj) * TILE + qk;
-        const float* T = tiles + (size_t)block_key(g, sc, sx, sy, sz) * 4 * TILE_NODES;
-        acc.w += T[q];
-        acc.x += T[TILE_NODES + q];
-        acc.y += T[2 * TILE_NODES + q];
-        acc.z += T[3 * TILE_NODES + q];
+        const bool in = valid && qi >= lo0 && qi <= hi0 && qj >= lo1 && qj <= hi1 && qk >= lo2 && qk <= hi2;
+        const int q = in ? (qi * TILE + qj) * TILE + qk : 0;
+        const float* T = tiles + (size_t)(in ? kk : 0u) * 4 * TILE_NODES;
+        const float t0 = T[q], t1 = T[TILE_NODES + q], t2 = T[2 * TILE_NODES + q], t3 = T[3 * TILE_NODES + q];
+        acc.w += in ? t0 : 0.f;
+        acc.x += in ? t1 : 0.f;
+        acc.y += in ? t2 : 0.f;
+        acc.z += in ? t3 : 0.f;
       }
       float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
       if (acc.w > 0.f && gx < g.n && gy < g.n && gz < g.n) {
@@ -863,7 +876,7 @@ static FastGeom make_geom(int n_grid, int S) {
 
 struct FastLayout {
   size_t buf_f[2], buf_id[2], buf_key[2], buf_rank[2], buf_mat[2], list[3];
-  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, won, tile_box, tiles, vgrid, gen, t0;
+  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, cl_list, cl_count, tile_box, tiles, vgrid, gen, t0;
   size_t total;
 };
 
@@ -886,7 +899,8 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   L.offsets = take((size_t)g.n_keys * 4);
   L.list_n = take(16);
   L.claim = take((size_t)g.n_keys * 4);
-  L.won = take((size_t)g.n_keys * 4);
+  L.cl_list = take((size_t)g.n_keys * 4);
+  L.cl_count = take(16);
   L.tile_box = take((size_t)g.n_keys * 8);
   L.tiles = take((size_t)g.n_keys * 4 * TILE_NODES * 4);
   L.vgrid = take((size_t)g.n_keys * 64 * 16);
@@ -920,7 +934,8 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.offsets = (uint32_t*)(ws + L.offsets);
   f.list_n = (uint32_t*)(ws + L.list_n);
   f.claim = (uint32_t*)(ws + L.claim);
-  f.won = (uint32_t*)(ws + L.won);
+  f.cl_list = (uint32_t*)(ws + L.cl_list);
+  f.cl_count = (uint32_t*)(ws + L.cl_count);
   f.tile_box = (int2*)(ws + L.tile_box);
   f.tiles = (float*)(ws + L.tiles);
   f.vgrid = (float4*)(ws + L.vgrid);
@@ -944,6 +959,7 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   launch_zero(ws + L.counts, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.list_n, 256, s);
   launch_zero(ws + L.claim, a256((size_t)f.g.n_keys * 4), s);
+  launch_zero(ws + L.cl_count, 256, s);
   launch_zero(ws + L.tile_box, a256((size_t)f.g.n_keys * 8), s);
   launch_zero(ws + L.vgrid, a256((size_t)f.g.n_keys * 64 * 16), s);
   launch_zero(ws + L.gen, 256, s);
@@ -972,7 +988,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   const FastGeom g = f.g;
   const int N = f.N;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.counts, f.key_tmp, f.rank_tmp);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.list[0], f.list_n + 0, g.n_keys, f.gen);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.list[0], f.list_n + 0, g.n_keys, f.gen, f.cl_count);
   k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, f.buf[0], f.key_tmp, f.rank_tmp, f.offsets);
   PartArgs A;
   A.N = N;
@@ -984,7 +1000,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   A.vgrid = f.vgrid;
   A.n_keys = g.n_keys;
   A.claim = f.claim;
-  A.won = f.won;
+  A.cl_list = f.cl_list;
   A.mlp = (const MlpBlob*)f.mlp_blob;
   A.closure_tol = f.closure_tol;
   A.closure_stats = f.closure_stats;
@@ -1001,6 +1017,9 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     A.list = f.list[rd];
     A.list_n = f.list_n + rd;
     A.step_id = (uint32_t)(step + 1);
+    // claims of step_id s go to counter s & 1 (the other is cleared by the
+    // grid kernel of step s for step s + 1)
+    A.cl_count = f.cl_count + ((step + 1) & 1);
     if (step == n) {
       k_particles<MODE_G2P, NT, FEAT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
       cur ^= 1;
@@ -1028,7 +1047,8 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     SA.list = f.list[nwr];
     SA.list_n = f.list_n + nwr;
     SA.n_keys = g.n_keys;
-    k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.list[rd], f.list_n + rd, f.won, f.tile_box, f.tiles, f.gen,
+    k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.cl_list, f.cl_count + ((step + 1) & 1),
+                                               f.cl_count + ((step + 2) & 1), f.tile_box, f.tiles, f.gen,
                                                (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA, -1, nullptr);
     if (do_scan) {
       cur ^= 1;
@@ -1104,7 +1124,8 @@ void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, Sorted
   const int N = f.N;
   new_epoch(f, s);
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.counts, f.key_tmp, f.rank_tmp);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen,
+                            out.cl_count ? out.cl_count : f.cl_count);
   k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, out.b, f.key_tmp, f.rank_tmp, f.offsets);
 }
 
@@ -1113,7 +1134,8 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
   const int N = f.N;
   new_epoch(f, s);
   k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen,
+                            out.cl_count ? out.cl_count : f.cl_count);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 
@@ -1130,7 +1152,8 @@ static PartArgs sorted_args(FastPath& f, const SortedState& st, uint32_t sid) {
   A.tile_box = f.tile_box;
   A.n_keys = f.g.n_keys;
   A.claim = f.claim;
-  A.won = st.won ? st.won : f.won;
+  A.cl_list = st.cl_list ? st.cl_list : f.cl_list;
+  A.cl_count = st.cl_count ? st.cl_count : f.cl_count;
   A.gen = f.gen;
   A.step_id = sid;
   A.vgrid = st.vgrid ? st.vgrid : f.vgrid;
@@ -1145,7 +1168,8 @@ void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t 
 void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
                const float* act_base, hipStream_t s) {
   ScanArgs SA = {};
-  k_grid<<<f.grid_wgs, 256, 0, s>>>(P, f.g, st.list, st.list_n, st.won ? st.won : f.won, f.tile_box, f.tiles, f.gen,
+  k_grid<<<f.grid_wgs, 256, 0, s>>>(P, f.g, st.cl_list ? st.cl_list : f.cl_list, st.cl_count ? st.cl_count : f.cl_count,
+                                    nullptr, f.tile_box, f.tiles, f.gen,
                                     sid, st.vgrid ? st.vgrid : f.vgrid, pose_base, act_base, f.t0_dev, 0, SA, t, st.mmv);
 }
 
