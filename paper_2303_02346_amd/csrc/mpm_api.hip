@@ -338,19 +338,20 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
       plain_step(c, P, us, us, t);
     }
   } else if (c->d.requires_grad) {
-    // tiled path in runs that end on checkpoint boundaries
-    int k = c->d.ckpt_every;
-    for (int t = c->t; t < c->t + n_steps;) {
-      if (t % k == 0) {
-        PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)(t / k) * c->state_bytes), N);
-        launch_copy_state(us, ck, c->stream);
-      }
-      int run = k - t % k;
-      if (run > c->t + n_steps - t) run = c->t + n_steps - t;
-      int rc = fast_run(c->fast, P, us, t, run, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
-      if (rc != MPM_OK) return MPM_EHIP;
-      t += run;
+    // tiled path in one call; the checkpoints inside it are written by the
+    // call itself, the one at its start is copied here
+    const int k = c->d.ckpt_every;
+    if (c->t % k == 0) {
+      PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)(c->t / k) * c->state_bytes), N);
+      launch_copy_state(us, ck, c->stream);
     }
+    c->fast.ck_base = c->ws + c->L.ckpt;
+    c->fast.ck_stride = c->state_bytes;
+    c->fast.ck_k = k;
+    c->fast.ck_t0 = c->t;
+    int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
+    c->fast.ck_k = 0;
+    if (rc != MPM_OK) return MPM_EHIP;
   } else {
     int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
     if (rc != MPM_OK) return rc;
@@ -536,7 +537,7 @@ int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value) {
   switch (key) {
     case MPM_OPT_GRAPH: c->fast.use_graph = value != 0; return MPM_OK;
     case MPM_OPT_PART_THREADS:
-      if (value != 128 && value != 256) return MPM_EINVAL;
+      if (value != 128 && value != 256 && value != 512) return MPM_EINVAL;
       c->fast.part_threads = value;
       return MPM_OK;
     case MPM_OPT_PART_WGS:
@@ -577,7 +578,7 @@ int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best) {
   PState us = user_pstate(&c->user, c->d.n_particles);
   hipStream_t s = c->stream;
   launch_pose(c->d.n_scenes, c->t, n_steps, c->d.dt, (const float*)(c->ws + c->L.act), (double*)(c->ws + c->L.pose), s);
-  const int pts[2] = {128, 256};
+  const int pts[3] = {128, 256, 512};
   const int pws[4] = {512, 1024, 2048, 4096};
   const int gws[3] = {512, 1024, 2048};
   const int save_pt = c->fast.part_threads, save_pw = c->fast.part_wgs, save_gw = c->fast.grid_wgs;
@@ -587,7 +588,7 @@ int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best) {
   int bpt = save_pt, bpw = save_pw, bgw = save_gw;
   c->fast.do_export = false;     // the trial runs leave the user state untouched
   int rc = MPM_OK;
-  for (int a = 0; a < 2 && rc == MPM_OK; a++)
+  for (int a = 0; a < 3 && rc == MPM_OK; a++)
     for (int b = 0; b < 4 && rc == MPM_OK; b++)
       for (int d = 0; d < 3 && rc == MPM_OK; d++) {
         c->fast.part_threads = pts[a];

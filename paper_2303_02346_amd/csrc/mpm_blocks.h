@@ -44,6 +44,8 @@ struct WaveRank {
   int leader;
   uint32_t prefix;
   uint32_t lbase;
+  bool lead;      // this lane reserved its key's range
+  uint32_t key;
 };
 __device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid) {
   const int lane = __lane_id();
@@ -52,6 +54,7 @@ __device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid
   R.leader = lane;
   R.prefix = 0;
   R.lbase = 0;
+  R.key = key;
   uint32_t lcount = 0;
   while (pending) {
     int leader = __ffsll((long long)pending) - 1;
@@ -61,16 +64,28 @@ __device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid
     if (lane == leader) lcount = (uint32_t)__popcll(m);
     pending &= ~m;
   }
-  if (lcount > 0) R.lbase = atomicAdd(&counts[key], lcount);
+  R.lead = lcount > 0;
+  if (R.lead) R.lbase = atomicAdd(&counts[key], lcount);
   return R;
 }
-__device__ inline uint32_t rank_finish(const WaveRank& R) { return __shfl(R.lbase, R.leader) + R.prefix; }
+// The key's first reservation in the step (base 0) also appends the key to
+// the list of touched keys, which is what the scan works through.
+__device__ inline void touch_key(uint32_t key, uint32_t* touched, uint32_t* n_touched, uint32_t n_keys) {
+  const uint32_t slot = atomicAdd(n_touched, 1u);
+  if (slot < n_keys) touched[slot] = key;
+}
+// (touched == NULL: no list is kept, for a scan over all keys)
+__device__ inline uint32_t rank_finish(const WaveRank& R, uint32_t* touched, uint32_t* n_touched, uint32_t n_keys) {
+  if (touched && R.lead && R.lbase == 0) touch_key(R.key, touched, n_touched, n_keys);
+  return __shfl(R.lbase, R.leader) + R.prefix;
+}
 
 // Rank of each lane's key among equal keys of the wavefront, with one global
 // atomic per distinct key, all issued together (one round trip however many
 // distinct keys the wavefront holds).  Every lane of the wave must call it.
-__device__ inline uint32_t wave_rank(uint32_t* counts, uint32_t key, bool valid) {
-  return rank_finish(rank_issue(counts, key, valid));
+__device__ inline uint32_t wave_rank(uint32_t* counts, uint32_t key, bool valid, uint32_t* touched, uint32_t* n_touched,
+                                     uint32_t n_keys) {
+  return rank_finish(rank_issue(counts, key, valid), touched, n_touched, n_keys);
 }
 
 __device__ inline void load_state(const PBuf& b, int N, int j, float* x, float* v, float* C, float* F, float& J) {

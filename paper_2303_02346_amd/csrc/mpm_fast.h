@@ -54,6 +54,7 @@ struct FastPath {
   PBuf buf[2];
   uint32_t *key_tmp, *rank_tmp;
   uint32_t *counts, *offsets;
+  uint32_t *touched, *n_touched;   // keys counted in the current step, in first-touch order
   int4* list[3];           // occupied-block lists (rotating)
   uint32_t* list_n;        // [3]
   uint32_t* claim;         // per-block stamp: which step last updated the block
@@ -79,6 +80,12 @@ struct FastPath {
   unsigned long long* log_count;
   unsigned long long log_cap;
   int grid_wgs, part_wgs;
+  // checkpoints written inside a call (requires_grad contexts): the state at
+  // every time t0 + s with (t0 + s) % ck_k == 0, 0 < s < n, goes to slot
+  // (t0 + s) / ck_k of ck_base (user order, ck_stride bytes apart); ck_k = 0: none
+  char* ck_base;
+  size_t ck_stride;
+  int ck_k, ck_t0;
   // plain dense grid (shared with the adjoint path), unused here
   float4* mmv;
   float4* vdense;

@@ -42,7 +42,8 @@ inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 // import: block key and rank of every particle (user order)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, FastGeom g, uint32_t* __restrict__ counts,
-                                                     uint32_t* __restrict__ key_tmp, uint32_t* __restrict__ rank_tmp) {
+                                                     uint32_t* __restrict__ key_tmp, uint32_t* __restrict__ rank_tmp,
+                                                     uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   bool has = p < u.N;
   uint32_t key = 0;
@@ -56,13 +57,61 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
       key = block_key(g, P.pscene[p], S.base[0] >> 2, S.base[1] >> 2, S.base[2] >> 2);
     }
   }
-  uint32_t r = wave_rank(counts, key, has);
+  uint32_t r = wave_rank(counts, key, has, touched, n_touched, (uint32_t)g.n_keys);
   if (has) { key_tmp[p] = key; rank_tmp[p] = r; }
 }
 
-// Exclusive scan of counts -> offsets, compact list of occupied keys, and
-// zero the counts.  Run by one workgroup of NT threads; each thread owns a
-// contiguous range of keys, loaded as independent 16-byte loads.
+// Exclusive scan of the counts of the touched keys -> their offsets, the
+// list of occupied keys {key, offset, count}, and the counts and the touched
+// counter cleared.  Run by one workgroup of NT threads.  The blocks follow the
+// order in which their keys were first touched; only contiguity matters.
+template <int NT>
+__device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
+                             const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
+                             int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys) {
+  constexpr int NW = NT / 64;
+  __shared__ uint32_t s_sum[NW];
+  __shared__ uint32_t s_run;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const uint32_t n = min(n_touched[0], (uint32_t)n_keys);
+  if (t == 0) s_run = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < n; c0 += NT) {
+    const uint32_t i = c0 + t;
+    uint32_t key = 0, c = 0;
+    if (i < n) { key = touched[i]; c = counts[key]; }
+    uint32_t is = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = __shfl_up(is, off);
+      if (lane >= off) is += o;
+    }
+    if (lane == 63) s_sum[wv] = is;
+    __syncthreads();
+    uint32_t woff = s_run, tot = s_run;
+#pragma unroll
+    for (int q = 0; q < NW; q++) {
+      if (q < wv) woff += s_sum[q];
+      tot += s_sum[q];
+    }
+    if (i < n) {
+      const uint32_t o = woff + is - c;
+      offsets[key] = o;
+      counts[key] = 0u;
+      list[i] = make_int4((int)key, (int)o, (int)c, 0);
+    }
+    __syncthreads();
+    if (t == 0) s_run = tot;
+    __syncthreads();
+  }
+  if (t == 0) { list_n[0] = n; n_touched[0] = 0u; }
+}
+
+// Dense variant: exclusive scan of all counts -> offsets, the list of
+// occupied keys in key (Morton) order, and the counts zeroed.  Run by one
+// workgroup of NT threads; each thread owns a contiguous range of keys,
+// loaded as independent 16-byte loads.  The adjoint's segment sorts use it:
+// its kernels run faster on blocks in Morton order.
 template <int NT>
 __device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, int4* __restrict__ list,
                           uint32_t* __restrict__ list_n, int n_keys) {
@@ -155,9 +204,16 @@ __device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ 
 // the import's scan; also advances the per-call epoch of the step stamps
 // (and clears the two claimed-block counters of the steps that follow)
 __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
+                                               const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
-                                               uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count) {
-  scan_keys<1024>(counts, offsets, list, list_n, n_keys);
+                                               uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count,
+                                               int dense) {
+  if (dense) {
+    scan_keys<1024>(counts, offsets, list, list_n, n_keys);
+    if (threadIdx.x == 0) n_touched[0] = 0u;
+  } else {
+    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys);
+  }
   if (threadIdx.x == 0) { epoch[0] = epoch[0] + 1; cl_count[0] = 0u; cl_count[1] = 0u; }
 }
 
@@ -188,7 +244,8 @@ __global__ __launch_bounds__(256) void k_permute(PState u, const uint8_t* __rest
 // the scene comes from the previous key
 __global__ __launch_bounds__(256) void k_keys_next(const float* __restrict__ xf, const uint32_t* __restrict__ key_prev,
                                                    int N, StepParams P, FastGeom g, uint32_t* __restrict__ counts,
-                                                   uint32_t* __restrict__ key_tmp, uint32_t* __restrict__ rank_tmp) {
+                                                   uint32_t* __restrict__ key_tmp, uint32_t* __restrict__ rank_tmp,
+                                                   uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   bool has = p < N;
   uint32_t key = 0;
@@ -199,7 +256,7 @@ __global__ __launch_bounds__(256) void k_keys_next(const float* __restrict__ xf,
     if (!stencil_setup(x, P, S) || sc >= (uint32_t)g.S) atomicOr(P.err, ERR_OUTSIDE);
     else key = block_key(g, (int)sc, S.base[0] >> 2, S.base[1] >> 2, S.base[2] >> 2);
   }
-  uint32_t r = wave_rank(counts, key, has);
+  uint32_t r = wave_rank(counts, key, has, touched, n_touched, (uint32_t)g.n_keys);
   if (has) { key_tmp[p] = key; rank_tmp[p] = r; }
 }
 
@@ -253,6 +310,8 @@ struct PartArgs {
   const uint32_t* list_n;
   const uint32_t* offsets;     // destination offsets of the keys stored with `in`
   uint32_t* counts;            // histogram of the new keys
+  uint32_t* touched;           // keys counted in this step (first touch appends)
+  uint32_t* n_touched;
   float* tiles;
   int2* tile_box;
   int n_keys;
@@ -288,8 +347,9 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
   __shared__ int s_itile[4 * TILE_NODES];
   __shared__ float4 s_v[VT_NODES];
   __shared__ int s_lo[3], s_hi[3];
-  __shared__ float s_red[16], s_scale[8];
-  __shared__ int s_ired[32];
+  __shared__ float s_red[NW * 4], s_scale[8];
+  __shared__ int s_ired[NW * 6 + 6];   // per-wave boxes, then the chunk's box at RB
+  constexpr int RB = NW * 6;
   const int tid = threadIdx.x;
   const int N = A.N;
   const uint32_t n_list = A.list_n[0];
@@ -639,8 +699,8 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
             int lo = s_ired[a], hi = s_ired[3 + a];
 #pragma unroll
             for (int w = 1; w < NW; w++) { lo = min(lo, s_ired[w * 6 + a]); hi = max(hi, s_ired[w * 6 + 3 + a]); }
-            s_ired[24 + a] = lo;
-            s_ired[27 + a] = hi;
+            s_ired[RB + a] = lo;
+            s_ired[RB + 3 + a] = hi;
             if (lo <= hi) { s_lo[a] = min(s_lo[a], lo); s_hi[a] = max(s_hi[a], hi); }
           }
         }
@@ -684,8 +744,8 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
         __syncthreads();
         {
           // flush the chunk's box into the float tile and clear the integers
-          const int lo0 = s_ired[24], lo1 = s_ired[25], lo2 = s_ired[26];
-          const int hi0 = s_ired[27], hi1 = s_ired[28], hi2 = s_ired[29];
+          const int lo0 = s_ired[RB], lo1 = s_ired[RB + 1], lo2 = s_ired[RB + 2];
+          const int hi0 = s_ired[RB + 3], hi1 = s_ired[RB + 4], hi2 = s_ired[RB + 5];
           if (lo0 <= hi0) {
             const int ex = hi0 - lo0 + 3, ey = hi1 - lo1 + 3, ez = hi2 - lo2 + 3;
             const int cnt = ex * ey * ez;
@@ -704,11 +764,12 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
         }
         __syncthreads();
         if (MODE == MODE_FUSED) {
-          uint32_t r = rank_finish(WR);
+          uint32_t r = rank_finish(WR, A.touched, A.n_touched, (uint32_t)A.n_keys);
           if (has && dst < (uint32_t)N) { A.out.key[dst] = nkey; A.out.rank[dst] = counted ? r : 0u; }
           // a particle that could not be counted keeps a valid (key 0) slot
           if (has && !counted && dst < (uint32_t)N) {
             uint32_t r0 = atomicAdd(&A.counts[0], 1u);
+            if (r0 == 0u) touch_key(0u, A.touched, A.n_touched, (uint32_t)A.n_keys);
             A.out.key[dst] = 0u;
             A.out.rank[dst] = r0;
           }
@@ -777,6 +838,8 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
 struct ScanArgs {
   uint32_t* counts;
   uint32_t* offsets;
+  uint32_t* touched;
+  uint32_t* n_touched;
   int4* list;
   uint32_t* list_n;
   int n_keys;
@@ -792,7 +855,7 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
                                               const float* __restrict__ act_base, const int* __restrict__ t0_dev,
                                               int do_scan, ScanArgs SA, int t_fixed, float4* __restrict__ mmv_out) {
   if (do_scan && blockIdx.x == 0) {
-    scan_keys<256>(SA.counts, SA.offsets, SA.list, SA.list_n, SA.n_keys);
+    scan_touched<256>(SA.counts, SA.offsets, SA.touched, SA.n_touched, SA.list, SA.list_n, SA.n_keys);
     return;
   }
   const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
@@ -876,7 +939,8 @@ static FastGeom make_geom(int n_grid, int S) {
 
 struct FastLayout {
   size_t buf_f[2], buf_id[2], buf_key[2], buf_rank[2], buf_mat[2], list[3];
-  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, cl_list, cl_count, tile_box, tiles, vgrid, gen, t0;
+  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, cl_list, cl_count, touched, n_touched, tile_box, tiles,
+      vgrid, gen, t0;
   size_t total;
 };
 
@@ -901,6 +965,8 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   L.claim = take((size_t)g.n_keys * 4);
   L.cl_list = take((size_t)g.n_keys * 4);
   L.cl_count = take(16);
+  L.touched = take((size_t)g.n_keys * 4);
+  L.n_touched = take(16);
   L.tile_box = take((size_t)g.n_keys * 8);
   L.tiles = take((size_t)g.n_keys * 4 * TILE_NODES * 4);
   L.vgrid = take((size_t)g.n_keys * 64 * 16);
@@ -936,6 +1002,8 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.claim = (uint32_t*)(ws + L.claim);
   f.cl_list = (uint32_t*)(ws + L.cl_list);
   f.cl_count = (uint32_t*)(ws + L.cl_count);
+  f.touched = (uint32_t*)(ws + L.touched);
+  f.n_touched = (uint32_t*)(ws + L.n_touched);
   f.tile_box = (int2*)(ws + L.tile_box);
   f.tiles = (float*)(ws + L.tiles);
   f.vgrid = (float4*)(ws + L.vgrid);
@@ -952,6 +1020,10 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.log_cap = 0;
   f.part_wgs = 2048;
   f.calls = 0;
+  f.ck_base = nullptr;
+  f.ck_stride = 0;
+  f.ck_k = 0;
+  f.ck_t0 = 0;
   f.grid_wgs = 2048;
   f.valid = false;
   f.sid = 0;
@@ -960,6 +1032,7 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   launch_zero(ws + L.list_n, 256, s);
   launch_zero(ws + L.claim, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.cl_count, 256, s);
+  launch_zero(ws + L.n_touched, 256, s);
   launch_zero(ws + L.tile_box, a256((size_t)f.g.n_keys * 8), s);
   launch_zero(ws + L.vgrid, a256((size_t)f.g.n_keys * 64 * 16), s);
   launch_zero(ws + L.gen, 256, s);
@@ -987,12 +1060,15 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
                          const float* act, hipStream_t s, std::vector<hipEvent_t>* ev) {
   const FastGeom g = f.g;
   const int N = f.N;
-  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.counts, f.key_tmp, f.rank_tmp);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.list[0], f.list_n + 0, g.n_keys, f.gen, f.cl_count);
+  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.counts, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
+                            f.cl_count, 0);
   k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, f.buf[0], f.key_tmp, f.rank_tmp, f.offsets);
   PartArgs A;
   A.N = N;
   A.counts = f.counts;
+  A.touched = f.touched;
+  A.n_touched = f.n_touched;
   A.offsets = f.offsets;
   A.tiles = f.tiles;
   A.tile_box = f.tile_box;
@@ -1031,6 +1107,11 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
       if (ev) hipEventRecord((*ev)[2 * ei], s);
       k_particles<MODE_FUSED, NT, FEAT><<<f.part_wgs, NT, 0, s>>>(A, P, g);
       if (ev) { hipEventRecord((*ev)[2 * ei + 1], s); ei++; }
+      // the state at time t0 + step now sits in the output buffer
+      if (f.ck_k > 0 && (f.ck_t0 + step) % f.ck_k == 0) {
+        PState ck = packed_state((float*)(f.ck_base + (size_t)((f.ck_t0 + step) / f.ck_k) * f.ck_stride), N);
+        k_export<<<nblk(N, 256), 256, 0, s>>>(A.out, ck, P.mats);
+      }
     }
     // grid update of this step; from step 1 on, workgroup 0 also scans the
     // keys the particle kernel counted (the step-0 kernel counts nothing and
@@ -1044,6 +1125,8 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     ScanArgs SA;
     SA.counts = f.counts;
     SA.offsets = f.offsets;
+    SA.touched = f.touched;
+    SA.n_touched = f.n_touched;
     SA.list = f.list[nwr];
     SA.list_n = f.list_n + nwr;
     SA.n_keys = g.n_keys;
@@ -1064,6 +1147,7 @@ static void enqueue(FastPath& f, const StepParams& P, const PState& user, int n,
   if (f.mlp_blob) enqueue_call<256, FEAT_CLOSURE>(f, P, user, n, pose, act, s, ev);
   else if (f.log_buf) enqueue_call<256, FEAT_LOG>(f, P, user, n, pose, act, s, ev);
   else if (f.part_threads == 128) enqueue_call<128, FEAT_NONE>(f, P, user, n, pose, act, s, ev);
+  else if (f.part_threads == 512) enqueue_call<512, FEAT_NONE>(f, P, user, n, pose, act, s, ev);
   else enqueue_call<256, FEAT_NONE>(f, P, user, n, pose, act, s, ev);
 }
 
@@ -1083,7 +1167,7 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   // a timed call runs eagerly: its per-launch events bracket real launches
   // (events recorded inside a captured graph do not give elapsed times here)
   const bool timed = timer && timer->on;
-  if (!f.use_graph || timed) {
+  if (!f.use_graph || timed || f.ck_k > 0) {
     std::vector<hipEvent_t> ev;
     if (timed) {
       ev.resize(2 * (size_t)(n - 1));
@@ -1123,9 +1207,9 @@ uint32_t fast_next_sid(FastPath& f) { return ++f.sid; }
 void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s) {
   const int N = f.N;
   new_epoch(f, s);
-  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.counts, f.key_tmp, f.rank_tmp);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count);
+  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.counts, f.key_tmp, f.rank_tmp, nullptr, f.n_touched);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
+                            out.cl_count ? out.cl_count : f.cl_count, 1);
   k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, out.b, f.key_tmp, f.rank_tmp, f.offsets);
 }
 
@@ -1133,9 +1217,10 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
                     uint32_t* map, hipStream_t s) {
   const int N = f.N;
   new_epoch(f, s);
-  k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count);
+  k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp, nullptr,
+                                           f.n_touched);
+  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
+                            out.cl_count ? out.cl_count : f.cl_count, 1);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 
@@ -1148,6 +1233,8 @@ static PartArgs sorted_args(FastPath& f, const SortedState& st, uint32_t sid) {
   A.list_n = st.list_n;
   A.offsets = f.offsets;
   A.counts = f.counts;
+  A.touched = f.touched;
+  A.n_touched = f.n_touched;
   A.tiles = f.tiles;
   A.tile_box = f.tile_box;
   A.n_keys = f.g.n_keys;
