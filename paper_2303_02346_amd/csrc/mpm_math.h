@@ -121,15 +121,26 @@ MPM_DI void svd3(const double* F, double* U, double* s, double* V) {
   double B[9];
   matmul(F, V, B);
   double b0[3] = {B[0], B[3], B[6]}, b1[3] = {B[1], B[4], B[7]}, b2[3] = {B[2], B[5], B[8]};
-  double n0 = sqrt(b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2]);
+  // norms and normalisations from one reciprocal square root each
+  const double q0 = b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2];
+  double n0 = 0.0;
   double u0[3], u1[3], u2[3];
-  if (n0 > 1e-300) { u0[0] = b0[0] / n0; u0[1] = b0[1] / n0; u0[2] = b0[2] / n0; }
-  else { u0[0] = 1; u0[1] = 0; u0[2] = 0; }
+  if (q0 > 0.0) {
+    const double r0 = rsqrt(q0);
+    n0 = q0 * r0;
+    u0[0] = b0[0] * r0; u0[1] = b0[1] * r0; u0[2] = b0[2] * r0;
+  } else {
+    u0[0] = 1; u0[1] = 0; u0[2] = 0;
+  }
   double d01 = u0[0] * b1[0] + u0[1] * b1[1] + u0[2] * b1[2];
   double w1[3] = {b1[0] - d01 * u0[0], b1[1] - d01 * u0[1], b1[2] - d01 * u0[2]};
-  double n1 = sqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2]);
-  if (n1 > 1e-14 * (n0 + 1e-300)) { u1[0] = w1[0] / n1; u1[1] = w1[1] / n1; u1[2] = w1[2] / n1; }
-  else {
+  const double q1 = w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2];
+  double n1 = 0.0;
+  if (q1 > 1e-28 * q0 && q1 > 0.0) {
+    const double r1 = rsqrt(q1);
+    n1 = q1 * r1;
+    u1[0] = w1[0] * r1; u1[1] = w1[1] * r1; u1[2] = w1[2] * r1;
+  } else {
     // any unit vector orthogonal to u0
     double a[3] = {0, 0, 0};
     int k = (fabs(u0[0]) < 0.57) ? 0 : ((fabs(u0[1]) < 0.57) ? 1 : 2);

@@ -226,9 +226,10 @@ MPM_DI void dp_project(const double* e, const MatDev& M, double* ep, DPInfo& I) 
     for (int a = 0; a < 3; a++) { ep[a] = e[a]; I.nh[a] = 0.0; }
   } else {
     I.cse = 2;
+    const double ind = 1.0 / nd;
 #pragma unroll
-    for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] / nd; ep[a] = es[a] - dg * I.nh[a] + c; }
-    I.beta = -ka * t / nd;
+    for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] * ind; ep[a] = es[a] - dg * I.nh[a] + c; }
+    I.beta = -ka * t * ind;
   }
   I.k1 = ka;
 }
@@ -247,9 +248,10 @@ MPM_DI void vm_project(const double* e, const MatDev& M, double* ep, DPInfo& I) 
     for (int a = 0; a < 3; a++) { ep[a] = e[a]; I.nh[a] = 0.0; }
   } else {
     I.cse = 2;
-    I.beta = r / nd;
+    const double ind = 1.0 / nd;
+    I.beta = r * ind;
 #pragma unroll
-    for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] / nd; ep[a] = t / 3.0 + r * I.nh[a]; }
+    for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] * ind; ep[a] = t * (1.0 / 3.0) + r * I.nh[a]; }
   }
 }
 
