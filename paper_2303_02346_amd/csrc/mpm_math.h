@@ -184,12 +184,15 @@ MPM_DI void iso_adjoint(const double* U, const double* s, const double* V, const
   double A[9];
 #pragma unroll
   for (int k = 0; k < 3; k++) A[k * 4] = M[0] * dg[0 * 3 + k] + M[4] * dg[1 * 3 + k] + M[8] * dg[2 * 3 + k];
+  // (g_i + g_j)/(s_i + s_j) is symmetric: one division per pair
+  const double t01 = (g[0] + g[1]) / (s[0] + s[1]), t02 = (g[0] + g[2]) / (s[0] + s[2]),
+               t12 = (g[1] + g[2]) / (s[1] + s[2]);
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int j = 0; j < 3; j++) {
       if (i == j) continue;
-      double t = (g[i] + g[j]) / (s[i] + s[j]);
+      const double t = (i + j == 1) ? t01 : ((i + j == 2) ? t02 : t12);
       A[i * 3 + j] = sdd[i * 3 + j] * 0.5 * (M[i * 3 + j] + M[j * 3 + i]) + t * 0.5 * (M[i * 3 + j] - M[j * 3 + i]);
     }
   matmul(U, A, T1);
@@ -207,6 +210,21 @@ MPM_DI double log_divdiff(double a, double b) {
 MPM_DI double expm1_ratio(double beta, double d) {
   if (fabs(d) < 1e-6) return beta * (1.0 + 0.5 * (beta - 1.0) * d);
   return expm1(beta * d) / expm1(d);
+}
+
+// Both expm1(beta d)/expm1(d) (into r) and expm1(-beta d)/expm1(-d) (into
+// rm) from one pair of expm1 evaluations: with E1 = expm1(beta d) and
+// E0 = expm1(d), expm1(-x) = -expm1(x)/(1 + expm1(x)) gives
+// rm = r (1 + E0)/(1 + E1).
+MPM_DI void expm1_ratio_pair(double beta, double d, double& r, double& rm) {
+  if (fabs(d) < 1e-6) {
+    r = beta * (1.0 + 0.5 * (beta - 1.0) * d);
+    rm = beta * (1.0 - 0.5 * (beta - 1.0) * d);
+    return;
+  }
+  const double E1 = expm1(beta * d), E0 = expm1(d);
+  r = E1 / E0;
+  rm = r * (1.0 + E0) / (1.0 + E1);
 }
 
 }  // namespace mpm

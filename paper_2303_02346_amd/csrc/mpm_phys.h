@@ -157,21 +157,23 @@ MPM_DI void stress_solid_adjoint_usv(const double* F, const double* U, const dou
     for (int a = 0; a < 3; a++) e[a] = ok ? log(s[a]) : 0.0;
     double tr = e[0] + e[1] + e[2];
     double mu = M.mu, lam = M.lam;
-    double h[3];
+    double h[3], is[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) { h[a] = 2.0 * mu * e[a] + lam * tr; g[a] = h[a] / s[a]; }
+    for (int a = 0; a < 3; a++) { is[a] = 1.0 / s[a]; h[a] = 2.0 * mu * e[a] + lam * tr; g[a] = h[a] * is[a]; }
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
       for (int k = 0; k < 3; k++)
-        dg[i * 3 + k] = (2.0 * mu * (i == k) + lam) / (s[k] * s[i]) - (i == k ? h[i] / (s[i] * s[i]) : 0.0);
+        dg[i * 3 + k] = (2.0 * mu * (i == k) + lam) * is[k] * is[i] - (i == k ? h[i] * is[i] * is[i] : 0.0);
+    // (log s_i - log s_j)/(s_i - s_j) is symmetric: one evaluation per pair
+    const double L01 = log_divdiff(s[0], s[1]), L02 = log_divdiff(s[0], s[2]), L12 = log_divdiff(s[1], s[2]);
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
       for (int j = 0; j < 3; j++) {
         if (i == j) { sdd[i * 3 + j] = 0.0; continue; }
-        double L = log_divdiff(s[i], s[j]);
-        sdd[i * 3 + j] = (2.0 * mu * (s[j] * L - e[j]) - lam * tr) / (s[i] * s[j]);
+        const double L = (i + j == 1) ? L01 : ((i + j == 2) ? L02 : L12);
+        sdd[i * 3 + j] = (2.0 * mu * (s[j] * L - e[j]) - lam * tr) * is[i] * is[j];
       }
     double Pm[9], Pb[9], T1[9], Fr[9];
     usv(U, g, V, Pm);
@@ -425,18 +427,24 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
 #pragma unroll
           for (int k = 0; k < 9; k++) { dg[k] = 0.0; sdd[k] = 0.0; }
         } else {
+          const double is[3] = {1.0 / s[0], 1.0 / s[1], 1.0 / s[2]};
 #pragma unroll
           for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
               double Jik = 1.0 / 3.0 - I.k1 * I.nh[i] + I.beta * ((i == k ? 1.0 : 0.0) - I.nh[i] * I.nh[k] - 1.0 / 3.0);
-              dg[i * 3 + k] = g[i] * Jik / s[k];
+              dg[i * 3 + k] = g[i] * Jik * is[k];
             }
-#pragma unroll
-          for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++)
-              sdd[i * 3 + j] = (i == j) ? 0.0 : exp(ep[j] - e[j]) * expm1_ratio(I.beta, e[i] - e[j]);
+          // exp(ep_j - e_j) = g_j / s_j; the ratios of a pair share their expm1s
+          double r01, r10, r02, r20, r12, r21;
+          expm1_ratio_pair(I.beta, e[0] - e[1], r01, r10);
+          expm1_ratio_pair(I.beta, e[0] - e[2], r02, r20);
+          expm1_ratio_pair(I.beta, e[1] - e[2], r12, r21);
+          const double q[3] = {g[0] * is[0], g[1] * is[1], g[2] * is[2]};
+          sdd[0] = sdd[4] = sdd[8] = 0.0;
+          sdd[1] = q[1] * r01; sdd[3] = q[0] * r10;
+          sdd[2] = q[2] * r02; sdd[6] = q[0] * r20;
+          sdd[5] = q[2] * r12; sdd[7] = q[1] * r21;
         }
 #pragma unroll
         for (int k = 0; k < 9; k++) Pb[k] = (double)Fb[k];
