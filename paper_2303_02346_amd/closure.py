@@ -122,7 +122,7 @@ def sand_scene(seed: int, n_particles: int = 60_000, n_grid: Optional[int] = Non
     return sc
 
 
-def generate_samples(target: int, device="cuda", n_scenes: int = 32, steps: int = 100, window: int = 4,
+def generate_samples(target: int, device="cuda", n_scenes: int = 32, steps: int = 100, window: int = 8,
                      seed: int = 0) -> torch.Tensor:
     """Cone-case samples of the exact projection from seeded sand rollouts:
     each scene contributes at most target / n_scenes records, logged during a
@@ -133,7 +133,7 @@ def generate_samples(target: int, device="cuda", n_scenes: int = 32, steps: int 
     buf = torch.zeros(target, RECORD, dtype=torch.float32, device=device)
     quota = -(-target // n_scenes)
     have = 0
-    for s in range(4 * n_scenes):
+    for s in range(8 * n_scenes):
         if have >= target:
             break
         sc = sand_scene(s, steps=steps)
