@@ -267,3 +267,48 @@ def test_box_yield_gradient_vs_oracle(adjoint):
     say(f"  loss gpu {loss.item():.8f} ref {L.item():.8f}; actions rel {ea:.2e}, dL/dx0 rel {ex:.2e}")
     assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
     assert ea <= 1e-4 and ex <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# launch shapes, extreme sizes and degenerate inputs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("threads,part_wgs,grid_wgs", [(128, 512, 512), (256, 4096, 2048), (512, 1024, 1024)])
+def test_config2_launch_shapes_vs_oracle(threads, part_wgs, grid_wgs):
+    """Every launch shape the autotuner can pick gives the oracle's answer
+    (config 2 at full size, 3 steps)."""
+    sc = scenes.config2()
+    say(f"config 2, launch shape {threads} threads, {part_wgs} particle / {grid_wgs} grid workgroups")
+    sim = sim_of(sc)
+    sim.set_option(_lib.MPM_OPT_PART_THREADS, threads)
+    sim.set_option(_lib.MPM_OPT_PART_WGS, part_wgs)
+    sim.set_option(_lib.MPM_OPT_GRID_WGS, grid_wgs)
+    sim.step(3)
+    compare_states(sim.state_numpy(), oracle_state(sc, 3), liquid_mask(sc), tol_x=1e-6, tol=1e-3)
+
+
+def test_single_particle():
+    """One particle (a single block, a single lane): free fall with the
+    oracle's answer."""
+    sc = scenes.tiny(n_particles=1, n_grid=16, steps=5, seed=9, kinds=(scenes.ELASTIC,), with_cylinder=False)
+    say("single particle, 5 steps")
+    sim = sim_of(sc)
+    sim.step(5)
+    g, ref = sim.state_numpy(), oracle_state(sc, 5)
+    ex, ev = rel(g["x"], ref["x"]), rel(g["v"], ref["v"])
+    # C and F - I are round-off on both sides (uniform velocity), so they are
+    # compared in absolute terms against the velocity gradient scale |v| / dx
+    scale = np.abs(ref["v"]).max() * sc.n_grid
+    eC = np.abs(g["C"] - ref["C"]).max() / scale
+    eF = np.abs(g["F"] - ref["F"]).max()
+    say(f"  rel err x {ex:.2e} v {ev:.2e}; |C - C_ref| / (|v|/dx) {eC:.2e}, |F - F_ref| {eF:.2e}")
+    assert ex <= 1e-6 and ev <= 1e-5 and eC <= 1e-5 and eF <= 1e-6
+
+
+def test_config5_largest_scene_first_steps_vs_oracle():
+    """The largest single scene (config 5: 1M sand particles on 256^3, in
+    floor contact), 2 steps against the oracle."""
+    sc = scenes.config5(steps=2)
+    say("config 5 (1M particles, 256^3), 2 steps")
+    sim = sim_of(sc)
+    sim.step(2)
+    compare_states(sim.state_numpy(), oracle_state(sc, 2), liquid_mask(sc), tol_x=1e-6, tol=1e-3)
