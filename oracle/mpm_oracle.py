@@ -46,7 +46,7 @@ import torch
 import torch.utils.checkpoint
 
 DT = torch.float64
-ELASTIC, LIQUID, SAND, VONMISES, BOX = 0, 1, 2, 3, 4
+ELASTIC, LIQUID, SAND, VONMISES, BOX, RIGID = 0, 1, 2, 3, 4, 5
 
 
 class OracleDomainError(RuntimeError):
@@ -337,6 +337,36 @@ def make_g_box(lo, hi):
 
 
 # ----------------------------------------------------------------------------
+# Rigid bodies represented by particles (section 3.2): the body's particles
+# are first updated as an elastic (corotated) solid; then the object-level
+# rigid transformation is computed and imposed.  Shape matching: centroid c
+# and rotation R = polar(sum m (x - c) r^T) of the rest offsets r; positions
+# c + R r; velocities the rigid field v_cm + w x (R r) with the body's linear
+# momentum and its angular momentum L = sum m (x - c) x (v - v_cm) about c
+# (w = R I_rest^-1 R^T L); C = [w]x; F = R.
+# ----------------------------------------------------------------------------
+def rigid_project(st, b, p: "Params"):
+    i = b["idx"]
+    m = p.mass[i]
+    M = m.sum()
+    x, v = st["x"][i], st["v"][i]
+    c = (m[:, None] * x).sum(0) / M
+    vcm = (m[:, None] * v).sum(0) / M
+    A = (m[:, None, None] * (x - c)[:, :, None] * b["r"][:, None, :]).sum(0)
+    R = polar_rotation(A[None])[0]
+    L = (m[:, None] * torch.cross(x - c, v - vcm, dim=-1)).sum(0)
+    w = R @ (b["Iinv"] @ (R.T @ L))
+    q = b["r"] @ R.T
+    out = dict(st)
+    out["x"] = st["x"].index_put((i,), c + q)
+    out["v"] = st["v"].index_put((i,), vcm + torch.cross(w.expand_as(q), q, dim=-1))
+    W = skew(w)
+    out["C"] = st["C"].index_put((i,), W.expand(i.numel(), 3, 3))
+    out["F"] = st["F"].index_put((i,), R.expand(i.numel(), 3, 3))
+    return out
+
+
+# ----------------------------------------------------------------------------
 # Scene parameters (oracle-side copy of the inputs)
 # ----------------------------------------------------------------------------
 @dataclass
@@ -365,6 +395,9 @@ class Params:
     idx_sand: torch.Tensor = field(default=None)
     idx_vm: torch.Tensor = field(default=None)
     idx_box: torch.Tensor = field(default=None)
+    # rigid bodies (one per rigid material): particle indices, rest offsets
+    # from the body's mass-weighted rest centroid, inverse rest inertia
+    rigid: list = field(default=None)
 
     @property
     def dx(self):
@@ -396,6 +429,20 @@ def params_from_scene(sc) -> Params:
     p.idx_sand = torch.nonzero(kind == SAND)[:, 0]
     p.idx_vm = torch.nonzero(kind == VONMISES)[:, 0]
     p.idx_box = torch.nonzero(kind == BOX)[:, 0]
+    p.rigid = []
+    x0 = torch.tensor(np.asarray(sc.x), dtype=DT)
+    matl = torch.from_numpy(mat).long()
+    for m in range(len(sc.materials)):
+        if sc.materials[m].kind != RIGID:
+            continue
+        idx = torch.nonzero(matl == m)[:, 0]
+        if idx.numel() == 0:
+            continue
+        w = p.mass[idx]
+        X = x0[idx]
+        r = X - (w[:, None] * X).sum(0) / w.sum()
+        I = (w[:, None, None] * ((r * r).sum(-1)[:, None, None] * torch.eye(3, dtype=DT) - r[:, :, None] * r[:, None, :])).sum(0)
+        p.rigid.append({"idx": idx, "r": r, "Iinv": torch.linalg.inv(I)})
     return p
 
 
@@ -427,6 +474,9 @@ def kirchhoff_stress(st, p: Params):
         tau = tau.index_put((i,), stress_sand(st["F"][i], p.mu[i], p.lam[i]))   # Hencky as well
     if p.idx_box.numel():
         i = p.idx_box
+        tau = tau.index_put((i,), stress_fixed_corotated(st["F"][i], p.mu[i], p.lam[i]))
+    for b in p.rigid:
+        i = b["idx"]
         tau = tau.index_put((i,), stress_fixed_corotated(st["F"][i], p.mu[i], p.lam[i]))
     return tau
 
@@ -552,6 +602,8 @@ def g2p(st, vgrid, p: Params):
         i = p.idx_box
         F_new = F_new.index_put((i,), IsotropicMap.apply(F_tr[i], make_g_box(p.box_lo[i], p.box_hi[i])))
     out = {"x": x_new, "v": v_new, "C": C_new, "F": F_new, "J": J_new}
+    for b in p.rigid:
+        out = rigid_project(out, b, p)
     for k, t in out.items():
         if not torch.isfinite(t).all():
             raise OracleDomainError(f"non-finite {k}")

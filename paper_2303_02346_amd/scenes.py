@@ -25,6 +25,7 @@ LIQUID = 1    # weakly compressible liquid, J-based pressure + Newtonian viscosi
 SAND = 2      # Hencky elasticity + Drucker-Prager plasticity
 VONMISES = 3  # Hencky elasticity + von Mises plasticity (the non-Newtonian ice cream)
 BOX = 4       # corotated elasticity + Box yield (the plastic material, Stomakhin 2013)
+RIGID = 5     # rigid body from particles: corotated update, then the object-level rigid projection
 
 # Table 4 (Appendix B.1) constants used by the synthetic scenes.
 WATER_LAMBDA = 277.78
@@ -46,6 +47,11 @@ def plasticine():
     lambda 277.78, rho 1) and Stomakhin et al.'s critical compression and
     stretch (2.5e-2, 7.5e-3)."""
     return Material(BOX, SOLID_MU, SOLID_LAMBDA, 1.0, theta_c=2.5e-2, theta_s=7.5e-3)
+
+
+def rigid_object():
+    """Table 4's rigid object (mu 416.67, lambda 277.78, rho 5.0)."""
+    return Material(RIGID, SOLID_MU, SOLID_LAMBDA, 5.0)
 
 
 def lame(E: float, nu: float):
@@ -322,6 +328,8 @@ def tiny(n_particles: int = 125, n_grid: int = 16, steps: int = 10, seed: int = 
             m = ice_cream()
         elif kind == BOX:
             m = plasticine()
+        elif kind == RIGID:
+            m = rigid_object()
         else:
             m = Material(SAND, SOLID_MU, SOLID_LAMBDA, 1.0, friction_deg=30.0, cohesion=0.0)
         boxes.append((pos, m, side ** 3))

@@ -216,3 +216,89 @@ def test_blob_loss_closed_form():
     mask = torch.tensor([True, True, False])
     L = O.blob_loss(x, mask, torch.tensor([0.5, 0.0, 0.0], dtype=DT), 0.1)
     assert abs(L.item() - (0.25 + 3 * 0.01)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# rigid bodies represented by particles
+# ---------------------------------------------------------------------------
+def _rigid_scene(steps=6, **kw):
+    return scenes.tiny(n_particles=200, n_grid=24, steps=steps, seed=3, kinds=(scenes.RIGID, scenes.LIQUID),
+                       velocity=1.0, **kw)
+
+
+def test_rigid_projection_keeps_shape_and_momenta():
+    """After the projection the body is its rest shape moved rigidly, its
+    velocities are a rigid field, and its linear and angular momentum
+    (about the centroid) equal those of the elastic state it came from."""
+    sc = _rigid_scene()
+    p = O.params_from_scene(sc)
+    b = p.rigid[0]
+    i = b["idx"]
+    rng = np.random.default_rng(50)
+    st = O.state_from_scene(sc)
+    st["x"] = st["x"] + torch.tensor(rng.normal(0, 1e-3, (sc.n, 3)), dtype=DT)   # a deformed elastic state
+    st["v"] = torch.tensor(rng.normal(0, 0.5, (sc.n, 3)), dtype=DT)
+    out = O.rigid_project(st, b, p)
+    m = p.mass[i][:, None]
+    x0, v0, x1, v1 = st["x"][i], st["v"][i], out["x"][i], out["v"][i]
+    X = torch.tensor(sc.x, dtype=DT)[i]
+    d1 = (x1[:, None] - x1[None]).norm(dim=-1)
+    d0 = (X[:, None] - X[None]).norm(dim=-1)
+    assert (d1 - d0).abs().max() < 1e-15
+    c0 = (m * x0).sum(0) / m.sum()
+    c1 = (m * x1).sum(0) / m.sum()
+    assert torch.allclose(c0, c1, atol=1e-15)
+    assert torch.allclose((m * v1).sum(0), (m * v0).sum(0), atol=1e-14)
+    L0 = (m * torch.cross(x0 - c0, v0 - (m * v0).sum(0) / m.sum(), dim=-1)).sum(0)
+    L1 = (m * torch.cross(x1 - c1, v1, dim=-1)).sum(0)
+    assert torch.allclose(L1, L0, atol=1e-15)
+    W = out["C"][i[0]]
+    w = torch.stack([W[2, 1], W[0, 2], W[1, 0]])
+    assert torch.allclose(W, -W.T, atol=0)
+    assert torch.allclose(v1 - (m * v1).sum(0) / m.sum(), torch.cross(w.expand_as(x1), x1 - c1, dim=-1), atol=1e-15)
+    R = out["F"][i[0]]
+    assert torch.allclose(R @ R.T, torch.eye(3, dtype=DT), atol=1e-14) and abs(torch.linalg.det(R) - 1) < 1e-14
+
+
+def test_rigid_body_in_free_fall():
+    """A rigid body alone, at rest, without collider: it falls as a point
+    mass, x_n = X + g dt^2 n (n + 1) / 2, and keeps its shape exactly."""
+    sc = scenes.tiny(n_particles=120, n_grid=24, steps=20, seed=4, kinds=(scenes.RIGID,), velocity=0.0,
+                     with_cylinder=False)
+    st = O.rollout(sc)
+    n, dt = 20, sc.dt
+    ref = torch.tensor(sc.x, dtype=DT) + torch.tensor([0.0, -9.8, 0.0], dtype=DT) * dt * dt * n * (n + 1) / 2
+    assert torch.allclose(st["x"], ref, atol=1e-13)
+
+
+def test_rigid_rollout_gradient_fd():
+    """Action and initial-position gradients through a rigid body in contact
+    with water and the cylinder, autograd against central FD (float64)."""
+    sc = scenes.tiny(n_particles=60, n_grid=16, steps=5, seed=5, kinds=(scenes.RIGID, scenes.LIQUID), velocity=1.0)
+    rng = np.random.default_rng(105)
+    wx = torch.tensor(rng.normal(0, 1, (sc.n, 3)), dtype=DT)
+    wv = torch.tensor(rng.normal(0, 1, (sc.n, 3)), dtype=DT) * 1e-2
+    p = O.params_from_scene(sc)
+    acts = torch.tensor(sc.actions, dtype=DT, requires_grad=True)
+    st0 = O.state_from_scene(sc, requires_grad=True)
+    L = _generic_loss(O.rollout(sc, actions=acts, state=st0, params=p), wx, wv)
+    L.backward()
+    def Lof(a, x0):
+        st = O.state_from_scene(sc)
+        st["x"] = x0
+        return _generic_loss(O.rollout(sc, actions=a, state=st, params=p), wx, wv).item()
+    a0 = torch.tensor(sc.actions, dtype=DT)
+    x0 = torch.tensor(sc.x, dtype=DT)
+    eps = 1e-6
+    for (t, k) in [(0, 0), (1, 3), (2, 1), (4, 5)]:
+        ap, am = a0.clone(), a0.clone()
+        ap[t, k] += eps
+        am[t, k] -= eps
+        num = (Lof(ap, x0) - Lof(am, x0)) / (2 * eps)
+        assert abs(num - acts.grad[t, k].item()) <= 1e-6 * max(1.0, abs(num))
+    for (q, a) in [(0, 0), (10, 1), (29, 2), (31, 0), (50, 1)]:
+        xp, xm = x0.clone(), x0.clone()
+        xp[q, a] += eps
+        xm[q, a] -= eps
+        num = (Lof(a0, xp) - Lof(a0, xm)) / (2 * eps)
+        assert abs(num - st0["x"].grad[q, a].item()) <= 1e-6 * max(1.0, abs(num)), (q, a)
