@@ -62,9 +62,28 @@ typedef enum {
   MPM_SAND_DP = 2,      /* Hencky elasticity + Drucker-Prager projection (Klar et al. 2016) */
   MPM_PLASTIC_VM = 3,   /* Hencky elasticity + von Mises projection in log strain: the
                            non-Newtonian ice cream of section 3.2 */
-  MPM_PLASTIC_BOX = 4   /* corotated elasticity + Box yield (singular values of F clamped to
+  MPM_PLASTIC_BOX = 4,  /* corotated elasticity + Box yield (singular values of F clamped to
                            [1 - theta_c, 1 + theta_s]): the plastic material of section 3.2 */
+  MPM_RIGID = 5         /* rigid body represented by particles (section 3.2), one body per
+                           material: see "Rigid bodies" below */
 } mpm_material_kind;
+
+/* Rigid bodies.  The particles of a material of kind MPM_RIGID form one body.
+ * Each step they first take the G2P update of a corotated elastic solid;
+ * then the body's rigid transformation is found by shape matching and
+ * imposed: with rest offsets r_p (the particle positions at mpm_set_state
+ * about their mass-weighted centroid, kept for the life of the state), the
+ * centroid c and velocity v_cm of the updated particles, the rotation R of
+ * the polar decomposition of sum m (x - c) r^T and the angular velocity
+ * w = R I_rest^-1 R^T L from the angular momentum L about c, every particle
+ * is set to x = c + R r, v = v_cm + w x (R r), C = [w]x, F = R.  Linear and
+ * angular momentum are kept.  The rest offsets are constants of the body:
+ * gradients do not flow into them.  A body whose particles do not span 3-D
+ * space (singular rest inertia) makes mpm_set_state return MPM_EINVAL.
+ * Scenes with rigid bodies step unfused (the projection needs the whole body
+ * between G2P and the next P2G): MPM_OPT_GRAPH and the kernel timer do not
+ * apply to them, and sample logging and the learned closure are refused
+ * (MPM_ESTATE).  Give each body of each batched scene its own material. */
 
 /* Error bits of the device error word (returned by mpm_last_error_bits). */
 enum {
@@ -133,7 +152,7 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
 
 /* Borrow the particle state arrays (device) and reset the clock to t = 0,
  * with the cylinder at its initial pose.  mpm_step advances these arrays in
- * place. */
+ * place.  Rigid bodies take their rest shapes from this state. */
 int mpm_set_state(mpm_ctx* c, const mpm_state* st);
 
 /* Copy n steps of actions (device, [n][n_scenes][6]: ux uy uz wx wy wz in

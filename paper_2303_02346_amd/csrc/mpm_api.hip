@@ -10,6 +10,7 @@
 #include "mpm_internal.h"
 #include "mpm_adjoint.h"
 #include "mpm_fast.h"
+#include "mpm_rigid.h"
 
 using namespace mpm;
 
@@ -52,9 +53,19 @@ struct Layout {
   size_t fast, cstats;
   size_t tmp, mmvb_blk;   // tiled adjoint: G2P output, node adjoints of (mv, m)
   SortedRec rec, tmp_rec;
+  // rigid bodies: rest offsets, material -> body table, body constants,
+  // sums, per-step projection records, adjoint terms, set-up sums, status
+  size_t r_rest, r_body_of, r_bodies, r_acc, r_rec, r_adj, r_rest_acc, r_status;
+  int n_bodies, n_rec;
   size_t total;
   int n_ckpt;
 };
+
+int count_bodies(const mpm_desc* d) {
+  int n = 0;
+  for (int m = 0; m < d->n_materials; m++) n += d->materials[m].kind == MPM_RIGID ? 1 : 0;
+  return n;
+}
 
 bool desc_ok(const mpm_desc* d) {
   if (!d) return false;
@@ -119,6 +130,21 @@ Layout plan(const mpm_desc* d) {
     L.tmp = L.mmvb_blk = 0;
     L.rec = L.tmp_rec = SortedRec{};
   }
+  L.n_bodies = count_bodies(d);
+  L.n_rec = d->requires_grad ? d->ckpt_every : 1;
+  if (L.n_bodies > 0) {
+    size_t B = L.n_bodies;
+    L.r_rest = take(3 * N * sizeof(float));
+    L.r_body_of = take(256 * sizeof(int));
+    L.r_bodies = take(B * sizeof(RigidBody));
+    L.r_acc = take(B * RIGID_ACC * sizeof(double));
+    L.r_rec = take((size_t)L.n_rec * B * RIGID_REC * sizeof(double));
+    L.r_adj = take(B * sizeof(RigidAdjTerms));
+    L.r_rest_acc = take(B * 16 * sizeof(double));
+    L.r_status = take(64);
+  } else {
+    L.r_rest = L.r_body_of = L.r_bodies = L.r_acc = L.r_rec = L.r_adj = L.r_rest_acc = L.r_status = 0;
+  }
   L.total = o;
   return L;
 }
@@ -141,7 +167,13 @@ struct mpm_ctx {
   FastPath fast;
   KernelTimer timer;
   bool plain_adjoint;
+  RigidCtx rigid;           // n_bodies = 0: no rigid bodies
 };
+
+// Projection record slot i of the rigid bodies.
+static double* rigid_rec(mpm_ctx* c, int i) {
+  return (double*)(c->ws + c->L.r_rec) + (size_t)i * c->L.n_bodies * RIGID_REC;
+}
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_EHIP; }
 
@@ -220,7 +252,7 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   memset(c->mats.data(), 0, 256 * sizeof(MatDev));
   for (int m = 0; m < d->n_materials; m++) {
     const mpm_material& src = d->materials[m];
-    if (src.kind < 0 || src.kind > 4 || !(src.p_mass > 0.f) || !(src.p_vol > 0.f)) { delete c; return MPM_EINVAL; }
+    if (src.kind < 0 || src.kind > MPM_RIGID || !(src.p_mass > 0.f) || !(src.p_vol > 0.f)) { delete c; return MPM_EINVAL; }
     MatDev& M = c->mats[m];
     M.kind = src.kind;
     M.mu = src.mu;
@@ -242,6 +274,26 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
       return MPM_EINVAL;
     }
   }
+  // rigid bodies: one per rigid material
+  std::vector<int> body_of(256, -1);
+  {
+    int nb = 0;
+    for (int m = 0; m < d->n_materials; m++)
+      if (d->materials[m].kind == MPM_RIGID) body_of[m] = nb++;
+  }
+  c->rigid = RigidCtx{};
+  c->rigid.n_bodies = L.n_bodies;
+  if (L.n_bodies > 0) {
+    char* w = (char*)workspace_dev;
+    c->rigid.body_of = (const int*)(w + L.r_body_of);
+    c->rigid.rest = (float*)(w + L.r_rest);
+    c->rigid.bodies = (RigidBody*)(w + L.r_bodies);
+    c->rigid.acc = (double*)(w + L.r_acc);
+    c->rigid.rec = (double*)(w + L.r_rec);
+    c->rigid.adj = (RigidAdjTerms*)(w + L.r_adj);
+    c->rigid.rest_acc = (double*)(w + L.r_rest_acc);
+    c->rigid.status = (int*)(w + L.r_status);
+  }
   c->cyl_radius.assign(d->cyl_radius, d->cyl_radius + S);
   c->cyl_pos0.assign(d->cyl_pos0, d->cyl_pos0 + 3 * S);
   c->cyl_rot0.assign(d->cyl_rot0, d->cyl_rot0 + 9 * S);
@@ -256,6 +308,12 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
       hipMemcpyAsync(c->ws + L.cyl_radius, c->cyl_radius.data(), S * sizeof(float), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemsetAsync(c->ws + L.err, 0, 64, c->stream) != hipSuccess)
     rc = MPM_EHIP;
+  if (rc == MPM_OK && L.n_bodies > 0) {
+    if (hipMemcpyAsync(c->ws + L.r_body_of, body_of.data(), 256 * sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      rc = MPM_EHIP;
+    else
+      launch_zero(c->ws + L.r_acc, (size_t)L.n_bodies * RIGID_ACC * sizeof(double), c->stream);
+  }
   if (rc == MPM_OK) {
     launch_scene_index((const int64_t*)(c->ws + L.offs), S, d->n_particles, (int*)(c->ws + L.pscene), c->stream);
     launch_zero(c->ws + L.vgrid, (size_t)d->n_grid * d->n_grid * d->n_grid * S * sizeof(float4), c->stream);
@@ -284,8 +342,21 @@ int mpm_set_state(mpm_ctx* c, const mpm_state* st) {
   }
   if (hipMemcpyAsync(c->ws + c->L.pose, pose0.data(), pose0.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return MPM_EHIP;
-  // pose0 is a host temporary: wait for the copy
-  return hip_ok(hipStreamSynchronize(c->stream));
+  int rstat = 0;
+  if (c->rigid.n_bodies > 0) {
+    // rest shapes of the rigid bodies from this state
+    StepParams P = make_params(c);
+    rigid_setup(c->rigid, P, user_pstate(st, c->d.n_particles), c->stream);
+    if (hipMemcpyAsync(&rstat, c->rigid.status, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return MPM_EHIP;
+  }
+  // pose0 and rstat are host temporaries: wait for the copies
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return MPM_EHIP;
+  if (rstat) {
+    c->has_state = false;
+    return MPM_EINVAL;
+  }
+  return MPM_OK;
 }
 
 int mpm_set_actions(mpm_ctx* c, int32_t t0, int32_t n, const float* actions_dev) {
@@ -304,8 +375,9 @@ static const float* act_at(mpm_ctx* c, int t) {
   return (const float*)(c->ws + c->L.act) + (size_t)t * c->d.n_scenes * 6;
 }
 
-// One plain step: state `in` -> `out` (may alias).
-static void plain_step(mpm_ctx* c, const StepParams& P, const PState& in, const PState& out, int t) {
+// One plain step: state `in` -> `out` (may alias); with rigid bodies, the
+// projection follows G2P and its record goes to slot rec_slot.
+static void plain_step(mpm_ctx* c, const StepParams& P, const PState& in, const PState& out, int t, int rec_slot) {
   size_t nodes = (size_t)c->d.n_grid * c->d.n_grid * c->d.n_grid * c->d.n_scenes;
   launch_zero(G(c, c->L.mmv), nodes * sizeof(float4), c->stream);
   c->timer.begin(c->stream);
@@ -313,6 +385,35 @@ static void plain_step(mpm_ctx* c, const StepParams& P, const PState& in, const 
   c->timer.end(c->stream);
   launch_grid_plain(P, G(c, c->L.mmv), G(c, c->L.vgrid), pose_at(c, t), act_at(c, t), c->stream);
   launch_g2p_plain(in, out, P, G(c, c->L.vgrid), c->stream);
+  if (c->rigid.n_bodies > 0)
+    rigid_forward(c->rigid, P, RigidRows{out, P.mat, nullptr}, rigid_rec(c, rec_slot), true, c->stream);
+}
+
+// n steps on the block-sorted path for scenes with rigid bodies.  The
+// projection needs every particle of a body after G2P, so the steps run
+// unfused: P2G, grid update, G2P into the second buffer, projection, sort
+// back into the first buffer.  Checkpoints as in fast_run.
+static void rigid_tiled_run(mpm_ctx* c, const StepParams& P, const PState& us, int t0, int n) {
+  FastPath& f = c->fast;
+  hipStream_t s = c->stream;
+  const int N = c->d.n_particles;
+  SortedState R0 = fast_own_state(f, 0);
+  const PBuf tmp = f.buf[1];
+  const RigidRows rows{packed_state(tmp.f, N), tmp.mat, tmp.id};
+  fast_sort_user(f, P, us, R0, s);
+  for (int t = t0; t < t0 + n; t++) {
+    const uint32_t sid = fast_next_sid(f);
+    fast_p2g(f, P, R0, sid, s);
+    fast_grid(f, P, R0, sid, t, pose_at(c, 0), act_at(c, 0), s);
+    fast_g2p(f, P, R0, tmp, s);
+    rigid_forward(c->rigid, P, rows, rigid_rec(c, 0), true, s);
+    if (t + 1 == t0 + n) break;
+    if (f.ck_k > 0 && (t + 1) % f.ck_k == 0)
+      fast_export(f, P, tmp, packed_state((float*)(f.ck_base + (size_t)((t + 1) / f.ck_k) * f.ck_stride), N), s);
+    // (the G2P buffer's key row is free: it serves as the sort's row map)
+    fast_sort_next(f, P, R0, tmp, R0, tmp.key, s);
+  }
+  if (f.do_export) fast_export(f, P, tmp, us, s);
 }
 
 int mpm_step(mpm_ctx* c, int32_t n_steps) {
@@ -335,7 +436,7 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
         PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)(t / k) * c->state_bytes), N);
         launch_copy_state(us, ck, c->stream);
       }
-      plain_step(c, P, us, us, t);
+      plain_step(c, P, us, us, t, 0);
     }
   } else if (c->d.requires_grad) {
     // tiled path in one call; the checkpoints inside it are written by the
@@ -349,9 +450,13 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
     c->fast.ck_stride = c->state_bytes;
     c->fast.ck_k = k;
     c->fast.ck_t0 = c->t;
-    int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
+    int rc = MPM_OK;
+    if (c->rigid.n_bodies > 0) rigid_tiled_run(c, P, us, c->t, n_steps);
+    else rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
     c->fast.ck_k = 0;
     if (rc != MPM_OK) return MPM_EHIP;
+  } else if (c->rigid.n_bodies > 0) {
+    rigid_tiled_run(c, P, us, c->t, n_steps);
   } else {
     int rc = fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), c->stream, &c->timer);
     if (rc != MPM_OK) return rc;
@@ -391,6 +496,8 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
   const size_t rb = c->L.rec.bytes;
   SortedState tmp = sorted_state(c, c->L.tmp, true);
   float4* mmvb_blk = G(c, c->L.mmvb_blk);
+  const bool rigid = c->rigid.n_bodies > 0;
+  const RigidRows trows{packed_state(tmp.b.f, N), tmp.b.mat, tmp.b.id};
   const int n_seg = (T + k - 1) / k;
   for (int seg = n_seg - 1; seg >= 0; seg--) {
     const int ts = seg * k, te = ts + k < T ? ts + k : T;
@@ -404,9 +511,13 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
       const uint32_t sid = fast_next_sid(f);
       fast_p2g(f, P, Si, sid, s);
       fast_grid(f, P, Si, sid, t, pose_at(c, 0), act_at(c, 0), s);
+      // (with rigid bodies the last step's G2P also runs, for its projection record)
+      if (t + 1 < te || rigid) {
+        fast_g2p(f, P, Si, tmp.b, s);
+        if (rigid) rigid_forward(c->rigid, P, trows, rigid_rec(c, t - ts), t + 1 < te, s);
+      }
       if (t + 1 < te) {
         SortedState Sn = sorted_state(c, bi + rb);
-        fast_g2p(f, P, Si, tmp.b, s);
         fast_sort_next(f, P, Si, tmp.b, Sn, sorted_map(c, bi), s);
       }
     }
@@ -432,6 +543,11 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
       A.cl_count = Si.cl_count;
       A.mmv = Si.mmv;
       A.mmvb = mmvb_blk;
+      // the adjoint of the rigid projection turns the body rows of the
+      // adjoint of s_{t+1} into the adjoint of the G2P output
+      if (rigid)
+        rigid_adjoint(c->rigid, P, RigidRows{packed_state(Si.b.f, N), Si.b.mat, Si.b.id}, A.map, a_cur.x,
+                      rigid_rec(c, t - ts), Si.vgrid, &f.g, s);
       launch_g2p_adj_tiled(A, P, f.g, f.part_wgs, s);
       launch_grid_adj_tiled(A, P, f.g, f.grid_wgs, pose_at(c, t), act_at(c, t),
                             acc + (size_t)t * c->d.n_scenes * ACC_DOUBLES, s);
@@ -478,16 +594,22 @@ int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_d
     PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)seg * c->state_bytes), N);
     PState s0 = packed_state((float*)(c->ws + c->L.seg), N);
     launch_copy_state(ck, s0, s);
-    for (int t = ts; t < te - 1; t++) {
+    // (with rigid bodies the last step runs too, into the spare slot te - ts,
+    // for its projection record)
+    const int t_end = c->rigid.n_bodies > 0 ? te : te - 1;
+    for (int t = ts; t < t_end; t++) {
       PState a = packed_state((float*)(c->ws + c->L.seg + (size_t)(t - ts) * c->state_bytes), N);
       PState b = packed_state((float*)(c->ws + c->L.seg + (size_t)(t - ts + 1) * c->state_bytes), N);
-      plain_step(c, P, a, b, t);
+      plain_step(c, P, a, b, t, t - ts);
     }
     for (int t = te - 1; t >= ts; t--) {
       PState st = packed_state((float*)(c->ws + c->L.seg + (size_t)(t - ts) * c->state_bytes), N);
       launch_zero(G(c, c->L.mmv), nodes * sizeof(float4), s);
       launch_p2g_plain(st, P, G(c, c->L.mmv), s);
       launch_grid_plain(P, G(c, c->L.mmv), G(c, c->L.vgrid), pose_at(c, t), act_at(c, t), s);
+      if (c->rigid.n_bodies > 0)
+        rigid_adjoint(c->rigid, P, RigidRows{st, P.mat, nullptr}, nullptr, a_cur.x, rigid_rec(c, t - ts),
+                      G(c, c->L.vgrid), nullptr, s);
       launch_zero(G(c, c->L.vbar), nodes * sizeof(float4), s);
       launch_g2p_adj_plain(st, a_cur, a_nxt, P, G(c, c->L.vgrid), G(c, c->L.vbar), s);
       launch_grid_adj_plain(P, G(c, c->L.mmv), G(c, c->L.vbar), G(c, c->L.mmvb), pose_at(c, t), act_at(c, t),
@@ -629,7 +751,7 @@ size_t mpm_mlp_blob_offset(void);
 int mpm_log_samples(mpm_ctx* c, float* buf_dev, uint64_t capacity, uint64_t* count_dev) {
   if (!c) return MPM_EINVAL;
   if (buf_dev && (!count_dev || capacity == 0)) return MPM_EINVAL;
-  if (buf_dev && c->fast.mlp_blob) return MPM_ESTATE;
+  if (buf_dev && (c->fast.mlp_blob || c->rigid.n_bodies > 0)) return MPM_ESTATE;
   c->fast.log_buf = buf_dev;
   c->fast.log_count = (unsigned long long*)count_dev;
   c->fast.log_cap = buf_dev ? capacity : 0;
@@ -638,7 +760,7 @@ int mpm_log_samples(mpm_ctx* c, float* buf_dev, uint64_t capacity, uint64_t* cou
 
 int mpm_set_closure(mpm_ctx* c, const void* mlp_state_dev, float residual_tol) {
   if (!c || (mlp_state_dev && !(residual_tol >= 0.f))) return MPM_EINVAL;
-  if (mlp_state_dev && (c->fast.log_buf || c->d.requires_grad)) return MPM_ESTATE;
+  if (mlp_state_dev && (c->fast.log_buf || c->d.requires_grad || c->rigid.n_bodies > 0)) return MPM_ESTATE;
   c->fast.mlp_blob = mlp_state_dev ? (const void*)((const char*)mlp_state_dev + mpm_mlp_blob_offset()) : nullptr;
   c->fast.closure_tol = residual_tol;
   return MPM_OK;

@@ -133,5 +133,9 @@ void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t 
 void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
                const float* act_base, hipStream_t s);
 void fast_g2p(FastPath& f, const StepParams& P, const SortedState& st, const PBuf& out, hipStream_t s);
+// The path's own sorted state over buffer b (0 or 1) and list b, using the
+// path's shared grid arrays; and the scatter of a sorted buffer to user order.
+SortedState fast_own_state(FastPath& f, int b);
+void fast_export(FastPath& f, const StepParams& P, const PBuf& X, const PState& user, hipStream_t s);
 
 }  // namespace mpm

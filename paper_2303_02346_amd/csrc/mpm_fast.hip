@@ -455,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, Fast
           if (liquid) {
             J = J * det3(Md);
             fin = fin && isfinite(J);
-          } else if (M.kind == KIND_ELASTIC) {
+          } else if (elastic_update_kind(M.kind)) {
             float Fn[9];
             matmul(Md, F, Fn);
 #pragma unroll
@@ -1266,6 +1266,18 @@ void fast_g2p(FastPath& f, const StepParams& P, const SortedState& st, const PBu
   PartArgs A = sorted_args(f, st, 0);
   A.out = out;
   k_particles<MODE_G2P, 256, FEAT_NONE><<<f.part_wgs, 256, 0, s>>>(A, P, f.g);
+}
+
+SortedState fast_own_state(FastPath& f, int b) {
+  SortedState S = {};
+  S.b = f.buf[b];
+  S.list = f.list[b];
+  S.list_n = f.list_n + b;
+  return S;
+}
+
+void fast_export(FastPath& f, const StepParams& P, const PBuf& X, const PState& user, hipStream_t s) {
+  k_export<<<nblk(f.N, 256), 256, 0, s>>>(X, user, P.mats);
 }
 
 void fast_destroy(FastPath& f) {

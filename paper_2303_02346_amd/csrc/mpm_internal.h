@@ -6,7 +6,7 @@
 
 namespace mpm {
 
-enum { KIND_ELASTIC = 0, KIND_LIQUID = 1, KIND_SAND = 2, KIND_VONMISES = 3, KIND_BOX = 4 };
+enum { KIND_ELASTIC = 0, KIND_LIQUID = 1, KIND_SAND = 2, KIND_VONMISES = 3, KIND_BOX = 4, KIND_RIGID = 5 };
 enum { ERR_OUTSIDE = 1, ERR_NONFINITE = 2, ERR_SAND_SIGMA = 4, ERR_TILE = 8 };
 
 // Per-material constants as the kernels use them (alpha, kappa precomputed).
@@ -121,7 +121,7 @@ struct KernelTimer {
 
 // ---- launch wrappers (mpm_kernels.hip) ----
 void launch_pose(int n_scenes, int t0, int n, float dt, const float* act, double* pose, hipStream_t s);
-void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);   // fills floor(bytes / 16) 16-byte words
 void launch_p2g_plain(const PState& st, const StepParams& P, float4* mmv, hipStream_t s);
 void launch_grid_plain(const StepParams& P, const float4* mmv, float4* vgrid, const double* pose_t,
                        const float* act_t, hipStream_t s);

@@ -79,9 +79,12 @@ MPM_DI void stress_liquid_adjoint(float J, const float* C, const MatDev& M, cons
 // Solids, FP64 inside: fixed corotated tau = 2 mu (F - R) F^T + lam J (J-1) I
 // with R = U V^T; Hencky tau = U diag(2 mu eps + lam tr eps) U^T, eps = log s.
 // Returns false when a sand singular value is not positive.
-// Solids with the corotated stress (elastic and Box-yield plastic); the
-// other solids (sand, von Mises) use Hencky.
-MPM_DI bool corotated_kind(int kind) { return kind == KIND_ELASTIC || kind == KIND_BOX; }
+// Solids with the corotated stress (elastic, Box-yield plastic and the
+// particles of rigid bodies); the other solids (sand, von Mises) use Hencky.
+MPM_DI bool corotated_kind(int kind) { return kind == KIND_ELASTIC || kind == KIND_BOX || kind == KIND_RIGID; }
+// Solids whose G2P update is the plain elastic F' = (I + dt C') F (a rigid
+// body's particles too: the rigid projection that follows replaces F).
+MPM_DI bool elastic_update_kind(int kind) { return kind == KIND_ELASTIC || kind == KIND_RIGID; }
 
 // The stress from a given signed SVD F = U diag(s) V^T of the FP64 copy F.
 MPM_DI bool stress_solid_usv(const double* F, const double* U, const double* s, const double* V, const MatDev& M,
@@ -303,7 +306,7 @@ MPM_DI void particle_update(const float* x, const float* vn, const float* B, con
     float F[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) F[k] = in.F[k * N + p];
-    if (M.kind == KIND_ELASTIC) {
+    if (elastic_update_kind(M.kind)) {
       matmul(Md, F, U.F);
     } else {
       double Mdd[9], Fd[9], Ft[9], Uu[9], s[3], V[9];
@@ -375,7 +378,7 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
     float F[9], Ftb[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) F[k] = in.F[k * N + p];
-    if (M.kind == KIND_ELASTIC) {
+    if (elastic_update_kind(M.kind)) {
 #pragma unroll
       for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
     } else {
