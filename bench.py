@@ -207,6 +207,43 @@ def bench_paper_point(torch, steps=200):
     return out
 
 
+def bench_rigid(torch, steps=100, bwd_steps=32):
+    """Rigid bodies from particles at config-2 size: the sand cube replaced
+    by a rigid cube (scenes.rigid_config2).  Such scenes step on the unfused
+    sorted path (P2G, grid, G2P, projection, sort); forward and
+    forward+backward (tiled adjoint, checkpoint every 16) rates."""
+    from paper_2303_02346_amd import scenes
+    from paper_2303_02346_amd.sim import Simulator
+    sc = scenes.rigid_config2(steps=max(steps, bwd_steps))
+    sim = Simulator(sc, horizon=steps)
+    sim.step(10)
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    sim.close()
+    simg = Simulator(sc, requires_grad=True, ckpt_every=16, horizon=bwd_steps)
+    wx = torch.ones(3, sc.n, device="cuda")
+    for rep in range(2):
+        simg.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        simg.step(bwd_steps)
+        ga = simg.backward(wx, torch.zeros_like(wx))
+        torch.cuda.synchronize()
+        t_fb = time.perf_counter() - t0
+    simg.close()
+    out = {"workload": "config-2 geometry, 125k water + 125k rigid-cube particles, 128^3, dt=5e-5",
+           "particles": sc.n, "steps": steps, "ms_per_step": t * 1e3 / steps, "particle_steps_per_s": sc.n * steps / t,
+           "fwd_bwd_steps": bwd_steps, "fwd_bwd_ms_per_step": t_fb * 1e3 / bwd_steps,
+           "fwd_bwd_particle_steps_per_s": sc.n * bwd_steps / t_fb, "grad_norm": float(ga.norm().item())}
+    log(f"[bench] rigid body scene: forward {out['ms_per_step']:.3f} ms/step, "
+        f"fwd+bwd {out['fwd_bwd_ms_per_step']:.3f} ms/step")
+    return out
+
+
 def copy_calibration(torch, mb):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
@@ -235,6 +272,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper-point", action="store_true")
+    ap.add_argument("--no-rigid", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0, help="first run a device copy of this size (counter scaling)")
     ap.add_argument("--closure", action="store_true", help="also train and time the learned closure (config 5)")
     args = ap.parse_args()
@@ -337,6 +375,8 @@ def main():
 
     paper = None if args.no_paper_point else bench_paper_point(torch)
 
+    rigid = None if args.no_rigid else bench_rigid(torch)
+
     closure = bench_closure(torch) if args.closure else None
 
     cpu = None
@@ -358,6 +398,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "batched": batched,
         "paper_point": paper,
+        "rigid": rigid,
         "closure": closure,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -137,7 +137,7 @@ Layout plan(const mpm_desc* d) {
     L.r_rest = take(3 * N * sizeof(float));
     L.r_body_of = take(256 * sizeof(int));
     L.r_bodies = take(B * sizeof(RigidBody));
-    L.r_acc = take(B * RIGID_ACC * sizeof(double));
+    L.r_acc = take((size_t)RIGID_SLOTS * B * RIGID_ACC * sizeof(double));
     L.r_rec = take((size_t)L.n_rec * B * RIGID_REC * sizeof(double));
     L.r_adj = take(B * sizeof(RigidAdjTerms));
     L.r_rest_acc = take(B * 16 * sizeof(double));
@@ -312,7 +312,7 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
     if (hipMemcpyAsync(c->ws + L.r_body_of, body_of.data(), 256 * sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess)
       rc = MPM_EHIP;
     else
-      launch_zero(c->ws + L.r_acc, (size_t)L.n_bodies * RIGID_ACC * sizeof(double), c->stream);
+      launch_zero(c->ws + L.r_acc, (size_t)RIGID_SLOTS * L.n_bodies * RIGID_ACC * sizeof(double), c->stream);
   }
   if (rc == MPM_OK) {
     launch_scene_index((const int64_t*)(c->ws + L.offs), S, d->n_particles, (int*)(c->ws + L.pscene), c->stream);
@@ -400,7 +400,8 @@ static void rigid_tiled_run(mpm_ctx* c, const StepParams& P, const PState& us, i
   SortedState R0 = fast_own_state(f, 0);
   const PBuf tmp = f.buf[1];
   const RigidRows rows{packed_state(tmp.f, N), tmp.mat, tmp.id};
-  fast_sort_user(f, P, us, R0, s);
+  // (the forward's sorts scan only the keys they counted)
+  fast_sort_user(f, P, us, R0, s, true);
   for (int t = t0; t < t0 + n; t++) {
     const uint32_t sid = fast_next_sid(f);
     fast_p2g(f, P, R0, sid, s);
@@ -411,7 +412,7 @@ static void rigid_tiled_run(mpm_ctx* c, const StepParams& P, const PState& us, i
     if (f.ck_k > 0 && (t + 1) % f.ck_k == 0)
       fast_export(f, P, tmp, packed_state((float*)(f.ck_base + (size_t)((t + 1) / f.ck_k) * f.ck_stride), N), s);
     // (the G2P buffer's key row is free: it serves as the sort's row map)
-    fast_sort_next(f, P, R0, tmp, R0, tmp.key, s);
+    fast_sort_next(f, P, R0, tmp, R0, tmp.key, s, true);
   }
   if (f.do_export) fast_export(f, P, tmp, us, s);
 }

@@ -124,11 +124,13 @@ void fast_destroy(FastPath& f);
 // one forward step's parts on a sorted state: P2G tiles and block claims
 // under step id `sid` (from fast_next_sid), the grid update of step t (with
 // st.mmv, also the node momenta and masses), and G2P into `out` in the same
-// row order.
+// row order.  The sorts scan all keys (blocks in Morton order) unless
+// `touched` is set: then only the keys counted, in first-touch order.
 uint32_t fast_next_sid(FastPath& f);
-void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s);
+void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s,
+                    bool touched = false);
 void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, const PBuf& next, SortedState& out,
-                    uint32_t* map, hipStream_t s);
+                    uint32_t* map, hipStream_t s, bool touched = false);
 void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, hipStream_t s);
 void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
                const float* act_base, hipStream_t s);

@@ -1204,23 +1204,25 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
 
 uint32_t fast_next_sid(FastPath& f) { return ++f.sid; }
 
-void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s) {
+void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s,
+                    bool touched) {
   const int N = f.N;
   new_epoch(f, s);
-  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.counts, f.key_tmp, f.rank_tmp, nullptr, f.n_touched);
+  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
+                                             touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, 1);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? 0 : 1);
   k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, out.b, f.key_tmp, f.rank_tmp, f.offsets);
 }
 
 void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, const PBuf& next, SortedState& out,
-                    uint32_t* map, hipStream_t s) {
+                    uint32_t* map, hipStream_t s, bool touched) {
   const int N = f.N;
   new_epoch(f, s);
-  k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp, nullptr,
-                                           f.n_touched);
+  k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
+                                           touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, 1);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? 0 : 1);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 

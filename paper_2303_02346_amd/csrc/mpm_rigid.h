@@ -19,6 +19,10 @@
 namespace mpm {
 
 constexpr int RIGID_ACC = 18;   // FP64 sums per body (forward and adjoint share the slots)
+// Each wavefront adds its per-body sums into one of RIGID_SLOTS copies of the
+// accumulators (by wavefront index), so that the FP64 atomics of a large body
+// do not all queue on the same 18 addresses; the solve adds the copies up.
+constexpr int RIGID_SLOTS = 128;
 constexpr int RIGID_REC = 48;   // FP64 record of one step's projection per body
 
 // Record layout (doubles): c 0, v_cm 3, R 6, w 15, L 18, z = I^-1 R^T L 21,
@@ -45,7 +49,7 @@ struct RigidCtx {
   const int* body_of;       // [256] material index -> body (-1: not a rigid material)
   float* rest;              // [3][N] rest offsets, by user particle index
   RigidBody* bodies;        // [n_bodies]
-  double* acc;              // [n_bodies][RIGID_ACC]
+  double* acc;              // [RIGID_SLOTS][n_bodies][RIGID_ACC]
   double* rec;              // [n_rec][n_bodies][RIGID_REC]
   RigidAdjTerms* adj;       // [n_bodies]
   double* rest_acc;         // [n_bodies][16] set-up sums

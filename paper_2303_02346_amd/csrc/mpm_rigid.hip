@@ -38,6 +38,30 @@ __device__ void body_reduce(int body, const double* v, double* base, int stride)
   }
 }
 
+// The accumulator copy this wavefront adds into.
+__device__ inline double* wave_slot(double* acc, int n_bodies) {
+  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  return acc + (size_t)(wave % RIGID_SLOTS) * n_bodies * RIGID_ACC;
+}
+
+// Sum of the RIGID_SLOTS copies of body b's accumulators into tot (in lane 0
+// of the calling wavefront, which must be the whole workgroup); the copies
+// are cleared for the next use.
+__device__ void gather_slots(double* acc, int n_bodies, int b, double* tot) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < RIGID_ACC; q++) tot[q] = 0.0;
+  for (int sl = lane; sl < RIGID_SLOTS; sl += 64) {
+    double* S = acc + ((size_t)sl * n_bodies + b) * RIGID_ACC;
+#pragma unroll
+    for (int q = 0; q < RIGID_ACC; q++) { tot[q] += S[q]; S[q] = 0.0; }
+  }
+#pragma unroll
+  for (int q = 0; q < RIGID_ACC; q++)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) tot[q] += __shfl_xor(tot[q], off);
+}
+
 MPM_DI void cross3(const double* a, const double* b, double* c) {
   c[0] = a[1] * b[2] - a[2] * b[1];
   c[1] = a[2] * b[0] - a[0] * b[2];
@@ -100,7 +124,7 @@ __global__ __launch_bounds__(256) void k_rigid_rest(PState u, const uint8_t* __r
 }
 
 __global__ void k_rigid_init(int n_bodies, const double* __restrict__ rest_acc, RigidBody* __restrict__ bodies,
-                             double* __restrict__ acc, int* __restrict__ status) {
+                             int* __restrict__ status) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_bodies) return;
   const double* S = rest_acc + (size_t)b * 16;
@@ -119,14 +143,12 @@ __global__ void k_rigid_init(int n_bodies, const double* __restrict__ rest_acc, 
   for (int k = 0; k < 9; k++) B.Iinv[k] = ok ? K[k] / det : 0.0;   // I symmetric: inverse = cof / det
   bodies[b] = B;
   if (!ok) atomicOr(status, 1);
-#pragma unroll
-  for (int q = 0; q < RIGID_ACC; q++) acc[(size_t)b * RIGID_ACC + q] = 0.0;
 }
 
 // ---- forward --------------------------------------------------------------
 // acc per body: [0..2] sum m x', [3..5] sum m v', [6..14] sum m x' r^T,
 // [15..17] sum m x' x v'
-__global__ __launch_bounds__(256) void k_rigid_sum(RigidRows rows, const int* __restrict__ body_of,
+__global__ __launch_bounds__(256) void k_rigid_sum(RigidRows rows, int n_bodies, const int* __restrict__ body_of,
                                                    const MatDev* __restrict__ mats, const float* __restrict__ rest,
                                                    double* __restrict__ acc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -156,14 +178,16 @@ __global__ __launch_bounds__(256) void k_rigid_sum(RigidRows rows, const int* __
 #pragma unroll
     for (int a = 0; a < 3; a++) v[15 + a] = m * xv[a];
   }
-  body_reduce<RIGID_ACC>(b, v, acc, RIGID_ACC);
+  body_reduce<RIGID_ACC>(b, v, wave_slot(acc, n_bodies), RIGID_ACC);
 }
 
-__global__ void k_rigid_solve(int n_bodies, const RigidBody* __restrict__ bodies, double* __restrict__ acc,
-                              double* __restrict__ rec) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bodies) return;
-  double* S = acc + (size_t)b * RIGID_ACC;
+// one wavefront per body
+__global__ __launch_bounds__(64) void k_rigid_solve(int n_bodies, const RigidBody* __restrict__ bodies,
+                                                    double* __restrict__ acc, double* __restrict__ rec) {
+  const int b = blockIdx.x;
+  double S[RIGID_ACC];
+  gather_slots(acc, n_bodies, b, S);
+  if (threadIdx.x != 0) return;
   double* O = rec + (size_t)b * RIGID_REC;
   const RigidBody B = bodies[b];
   const double iM = 1.0 / B.M;
@@ -207,9 +231,6 @@ __global__ void k_rigid_solve(int n_bodies, const RigidBody* __restrict__ bodies
 #pragma unroll
   for (int k = 0; k < 9; k++) { O[RR_R + k] = R[k]; O[RR_U + k] = U[k]; O[RR_V + k] = V[k]; }
   O[RR_NRM] = nrm;
-  // the sums start from zero at the next use
-#pragma unroll
-  for (int q = 0; q < RIGID_ACC; q++) S[q] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_rigid_project(RigidRows rows, const int* __restrict__ body_of,
@@ -245,7 +266,7 @@ __global__ __launch_bounds__(256) void k_rigid_project(RigidRows rows, const int
 // acc per body: [0..2] sum xbar, [3..5] sum vbar, [6..8] wbar, [9..17] Rbar,
 // where per particle (q = R r): wbar_p = q x vbar + vee(Cbar - Cbar^T) and
 // Rbar_p = (xbar + vbar x w) r^T + Fbar.
-__global__ __launch_bounds__(256) void k_rigid_adj_sum(RigidRows rows, const uint32_t* __restrict__ map,
+__global__ __launch_bounds__(256) void k_rigid_adj_sum(RigidRows rows, int n_bodies, const uint32_t* __restrict__ map,
                                                        const float* __restrict__ abar, const int* __restrict__ body_of,
                                                        const float* __restrict__ rest, const double* __restrict__ rec,
                                                        double* __restrict__ acc) {
@@ -286,14 +307,17 @@ __global__ __launch_bounds__(256) void k_rigid_adj_sum(RigidRows rows, const uin
       for (int c = 0; c < 3; c++)
         v[9 + a * 3 + c] = (xb[a] + vw[a]) * r[c] + (double)abar[(15 + a * 3 + c) * (size_t)N + jn];
   }
-  body_reduce<RIGID_ACC>(b, v, acc, RIGID_ACC);
+  body_reduce<RIGID_ACC>(b, v, wave_slot(acc, n_bodies), RIGID_ACC);
 }
 
-__global__ void k_rigid_adj_solve(int n_bodies, const RigidBody* __restrict__ bodies, double* __restrict__ acc,
-                                  const double* __restrict__ rec, RigidAdjTerms* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bodies) return;
-  double* S = acc + (size_t)b * RIGID_ACC;
+// one wavefront per body
+__global__ __launch_bounds__(64) void k_rigid_adj_solve(int n_bodies, const RigidBody* __restrict__ bodies,
+                                                        double* __restrict__ acc, const double* __restrict__ rec,
+                                                        RigidAdjTerms* __restrict__ out) {
+  const int b = blockIdx.x;
+  double S[RIGID_ACC];
+  gather_slots(acc, n_bodies, b, S);
+  if (threadIdx.x != 0) return;
   const double* O = rec + (size_t)b * RIGID_REC;
   const RigidBody B = bodies[b];
   const double* R = O + RR_R;
@@ -342,8 +366,6 @@ __global__ void k_rigid_adj_solve(int n_bodies, const RigidBody* __restrict__ bo
 #pragma unroll
   for (int k = 0; k < 9; k++) T.Ab[k] = (float)Ab[k];
   out[b] = T;
-#pragma unroll
-  for (int q = 0; q < RIGID_ACC; q++) S[q] = 0.0;
 }
 
 // Recompute v' of the rigid rows (G2P of the state s_t from the step's grid
@@ -415,24 +437,25 @@ void rigid_setup(const RigidCtx& R, const StepParams& P, const PState& user, hip
   const int N = user.N;
   launch_zero(R.rest_acc, (size_t)R.n_bodies * 16 * sizeof(double), s);
   launch_zero(R.status, 64, s);   // (the status slot is 64 bytes; the fill works in 16-byte units)
+  launch_zero(R.acc, (size_t)RIGID_SLOTS * R.n_bodies * RIGID_ACC * sizeof(double), s);
   k_rigid_rest_sum<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, R.body_of, P.mats, R.rest_acc);
   k_rigid_rest<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, R.body_of, P.mats, R.rest_acc, R.rest);
-  k_rigid_init<<<nblk(R.n_bodies, 64), 64, 0, s>>>(R.n_bodies, R.rest_acc, R.bodies, R.acc, R.status);
+  k_rigid_init<<<nblk(R.n_bodies, 64), 64, 0, s>>>(R.n_bodies, R.rest_acc, R.bodies, R.status);
 }
 
 void rigid_forward(const RigidCtx& R, const StepParams& P, const RigidRows& rows, double* rec, bool project,
                    hipStream_t s) {
   const int N = rows.st.N;
-  k_rigid_sum<<<nblk(N, 256), 256, 0, s>>>(rows, R.body_of, P.mats, R.rest, R.acc);
-  k_rigid_solve<<<nblk(R.n_bodies, 64), 64, 0, s>>>(R.n_bodies, R.bodies, R.acc, rec);
+  k_rigid_sum<<<nblk(N, 256), 256, 0, s>>>(rows, R.n_bodies, R.body_of, P.mats, R.rest, R.acc);
+  k_rigid_solve<<<R.n_bodies, 64, 0, s>>>(R.n_bodies, R.bodies, R.acc, rec);
   if (project) k_rigid_project<<<nblk(N, 256), 256, 0, s>>>(rows, R.body_of, R.rest, rec);
 }
 
 void rigid_adjoint(const RigidCtx& R, const StepParams& P, const RigidRows& rows, const uint32_t* map,
                    float* abar_next, const double* rec, const float4* vgrid, const FastGeom* g, hipStream_t s) {
   const int N = rows.st.N;
-  k_rigid_adj_sum<<<nblk(N, 256), 256, 0, s>>>(rows, map, abar_next, R.body_of, R.rest, rec, R.acc);
-  k_rigid_adj_solve<<<nblk(R.n_bodies, 64), 64, 0, s>>>(R.n_bodies, R.bodies, R.acc, rec, R.adj);
+  k_rigid_adj_sum<<<nblk(N, 256), 256, 0, s>>>(rows, R.n_bodies, map, abar_next, R.body_of, R.rest, rec, R.acc);
+  k_rigid_adj_solve<<<R.n_bodies, 64, 0, s>>>(R.n_bodies, R.bodies, R.acc, rec, R.adj);
   if (g)
     k_rigid_adj_apply<true><<<nblk(N, 256), 256, 0, s>>>(rows, map, abar_next, R.body_of, P.mats, R.rest, R.adj,
                                                          vgrid, P, *g);

@@ -183,7 +183,7 @@ def config1(n_particles: int = 4096, steps: int = 100, affine: bool = False) -> 
 
 
 def _two_box_scene(cfg_id: int, n_particles: int, n_grid: int, dt: float, steps: int,
-                   side: float = 0.2) -> Scene:
+                   side: float = 0.2, second: "Material" = None) -> Scene:
     r_geo, r_pos, r_traj, r_tgt = _rngs(cfg_id)
     dx = 1.0 / n_grid
     y0 = 5 * dx                       # two cells above the 3-node floor band
@@ -202,7 +202,7 @@ def _two_box_scene(cfg_id: int, n_particles: int, n_grid: int, dt: float, steps:
     pl = _box_particles(r_pos, liq_lo, liq_lo + side, n_liq)
     ps = _box_particles(r_pos, sand_lo, sand_lo + side, n_sand)
     liquid = Material(LIQUID, 0.0, WATER_LAMBDA, 1.0, viscosity=0.1)
-    sand = Material(SAND, SOLID_MU, SOLID_LAMBDA, 1.0, friction_deg=30.0, cohesion=0.0)
+    sand = Material(SAND, SOLID_MU, SOLID_LAMBDA, 1.0, friction_deg=30.0, cohesion=0.0) if second is None else second
     acts = smooth_actions(r_traj, steps, dt, u_mean=(0.5, 0.0, 0.0))
     # cylinder one cell from the liquid box's -x face, moving into the box on average
     c0 = np.array([xl - 0.05 - dx, 0.5, zl + 0.5 * side])
@@ -218,6 +218,15 @@ def config2(n_particles: int = 250_000, steps: int = 200) -> Scene:
     cubes of side 0.2, kinematic cylinder r=0.05, 128^3, dt=5e-5."""
     sc = _two_box_scene(2, n_particles, 128, 5e-5, steps)
     sc.name = "c2"
+    return sc
+
+
+def rigid_config2(n_particles: int = 250_000, steps: int = 200) -> Scene:
+    """Config-2 geometry with the sand box replaced by a rigid body of
+    Table 4's rigid object (rho 5.0): water pushed by the cylinder towards a
+    rigid cube; 250k particles, 128^3, dt=5e-5."""
+    sc = _two_box_scene(2, n_particles, 128, 5e-5, steps, second=rigid_object())
+    sc.name = "c2r"
     return sc
 
 

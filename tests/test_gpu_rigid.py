@@ -190,3 +190,13 @@ def test_rigid_refuses_closure_and_logging():
     with pytest.raises(_lib.MpmError) as e:
         sim.log_samples(buf, count)
     assert e.value.status == _lib.MPM_ESTATE
+
+
+def test_rigid_config2_full_size_vs_oracle():
+    """The bench's rigid workload at full size (250k particles on 128^3, a
+    125k-particle rigid cube), 3 steps against the oracle."""
+    sc = scenes.rigid_config2(steps=3)
+    say("rigid config 2 (250k particles, 128^3), 3 steps")
+    sim = sim_of(sc)
+    sim.step(3)
+    compare(sim.state_numpy(), oracle_state(sc, 3), sc, tol_x=1e-6, tol=1e-3)
