@@ -367,3 +367,80 @@ def concat_scenes(scenes: List[Scene]):
         offs.append(offs[-1] + sc.n)
     out = {k: np.concatenate(v, 0) for k, v in parts.items()}
     return out, np.asarray(offs, np.int64), mats
+
+
+# ----------------------------------------------------------------------------
+# Gas (section 3.2's advection-projection gas; the air-circulation task)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class GasScene:
+    n: tuple                       # cells per axis (nx, ny, nz)
+    h: float                       # cell size
+    dt: float
+    u: np.ndarray                  # (nx+1, ny, nz) x-face velocities
+    v: np.ndarray                  # (nx, ny+1, nz)
+    w: np.ndarray                  # (nx, ny, nz+1)
+    s: np.ndarray                  # (K, nx, ny, nz) scalars; 0 = temperature, 1 = smoke density
+    actions: np.ndarray            # (T, 6) emitter velocities ux uy uz wx wy wz (world frame)
+    src: tuple = (0.0, 1.0)        # emitter source values of the scalars (cool air, smoke)
+    buoyancy: float = 1.0          # v += dt beta (T - T_amb)
+    t_amb: float = 1.0
+    emit_sigma: float = 0.04
+    emit_kappa: float = 0.5
+    emit_speed: float = 2.0
+    emit_pos0: tuple = (0.15, 0.6, 0.5)
+    # local y axis (the outflow direction) along +x
+    emit_rot0: tuple = (0.0, 1.0, 0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 1.0)
+    sensors: np.ndarray = None     # (M,) flat cell indices of temperature sensors
+    targets: np.ndarray = None     # (M,) target temperatures
+    name: str = "gas"
+
+    @property
+    def horizon(self):
+        return self.actions.shape[0]
+
+
+def gas_room(n: int = 128, steps: int = 100, seed: int = 0, dt: float = 5e-3, velocity: float = 0.5,
+             n_scalars: int = 2, translate: bool = False) -> GasScene:
+    """A closed room of warm air (T = 1 with seeded smooth variations) and a
+    cool-air emitter near the -x wall that swings about the vertical axis
+    (the air-circulation task of section 4.1 on the 128^3 gas grid of
+    section 4.2).  The initial velocity is a seeded smooth field (not
+    divergence-free: the first projection removes its divergent part).  27
+    temperature sensors sit on a 3x3x3 lattice with seeded cool/warm targets.
+    translate: also move the emitter (small seeded translational velocities)."""
+    rng = np.random.default_rng(np.random.SeedSequence([20230302, 77, n, seed]))
+    h = 1.0 / n
+    dims = (n, n, n)
+
+    def smooth(shape, amp):
+        # sum of a few seeded low-frequency modes sampled on the grid points
+        idx = np.meshgrid(*[np.arange(m, dtype=np.float64) for m in shape], indexing="ij")
+        out = np.zeros(shape)
+        for _ in range(4):
+            k = rng.integers(1, 4, 3)
+            ph = rng.uniform(0, 2 * math.pi, 3)
+            a = rng.uniform(-amp, amp)
+            out += a * np.sin(math.pi * k[0] * idx[0] / shape[0] + ph[0]) * \
+                np.sin(math.pi * k[1] * idx[1] / shape[1] + ph[1]) * np.sin(math.pi * k[2] * idx[2] / shape[2] + ph[2])
+        return out
+
+    u = smooth((n + 1, n, n), velocity)
+    v = smooth((n, n + 1, n), velocity)
+    w = smooth((n, n, n + 1), velocity)
+    u[0] = u[-1] = 0.0
+    v[:, 0] = v[:, -1] = 0.0
+    w[:, :, 0] = w[:, :, -1] = 0.0
+    s = np.zeros((n_scalars,) + dims)
+    s[0] = 1.0 + 0.05 * smooth(dims, 1.0)
+    acts = smooth_actions(rng, steps, dt, amp_u=0.2 if translate else 0.0, amp_w=2.0)
+    acts[:, 3] = 0.0
+    acts[:, 5] = 0.0                       # the air conditioner turns about y only
+    if not translate:
+        acts[:, :3] = 0.0
+    lat = [int(round(f * n)) for f in (0.2, 0.5, 0.8)]
+    sensors = np.array([(i * n + j) * n + k for i in lat for j in lat for k in lat], np.int64)
+    targets = np.where(rng.random(sensors.size) < 0.5, 0.0, 1.0)
+    return GasScene(n=dims, h=h, dt=dt, u=u, v=v, w=w, s=s, actions=acts, sensors=sensors, targets=targets,
+                    src=(0.0, 1.0)[:n_scalars] if n_scalars <= 2 else tuple([0.0, 1.0] + [0.5] * (n_scalars - 2)),
+                    name=f"gas{n}_{seed}")
