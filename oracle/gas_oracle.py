@@ -231,12 +231,24 @@ def _pinned_factor(n, h):
     return _FACTORS[key]
 
 
+DIRECT_MAX_CELLS = 48 ** 3
+
+
 def solve_pressure(b: np.ndarray, n, h) -> np.ndarray:
     """A solution of L phi = b for a b with zero sum (the Neumann problem is
-    singular; phi is fixed by phi[0] = 0, which G does not see)."""
-    bb = b.ravel().copy()
-    bb[0] = 0.0
-    return _pinned_factor(n, h).solve(bb).reshape(n)
+    singular; phi is fixed up to a constant, which G does not see).  Grids up
+    to 48^3: sparse LU with phi[0] = 0; larger ones: conjugate gradients on
+    the consistent semi-definite system -L phi = -b to a relative residual of
+    1e-12 (the factorisation of a 128^3 Laplacian does not fit)."""
+    if int(np.prod(n)) <= DIRECT_MAX_CELLS:
+        bb = b.ravel().copy()
+        bb[0] = 0.0
+        return _pinned_factor(n, h).solve(bb).reshape(n)
+    A = -laplacian_matrix(n, h)
+    phi, info = scipy.sparse.linalg.cg(A, -b.ravel(), rtol=1e-12, atol=0.0, maxiter=20000)
+    if info != 0:
+        raise RuntimeError(f"pressure CG did not converge (info {info})")
+    return phi.reshape(n)
 
 
 def project_np(u, v, w, h):

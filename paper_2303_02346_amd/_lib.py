@@ -38,6 +38,23 @@ EXPORTS = ["mpm_workspace_bytes", "mpm_create", "mpm_set_state", "mpm_set_action
            "mpm_closure_stats", "mpm_mlp_state_bytes", "mpm_mlp_scratch_bytes", "mpm_mlp_init", "mpm_mlp_train",
            "mpm_mlp_grad", "mpm_mlp_predict", "mpm_mlp_params", "mpm_destroy", "mpm_strerror"]
 
+class GasDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("h", ctypes.c_float),
+                ("dt", ctypes.c_float), ("buoyancy", ctypes.c_float), ("t_amb", ctypes.c_float),
+                ("n_scalars", ctypes.c_int32), ("src", ctypes.POINTER(ctypes.c_float)),
+                ("emit_sigma", ctypes.c_float), ("emit_kappa", ctypes.c_float), ("emit_speed", ctypes.c_float),
+                ("emit_pos0", ctypes.c_float * 3), ("emit_rot0", ctypes.c_float * 9), ("horizon", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32), ("requires_grad", ctypes.c_int32), ("mg_cycles", ctypes.c_int32)]
+
+
+class GasState(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p), ("s", ctypes.c_void_p)]
+
+
+GAS_EXPORTS = ["gas_workspace_bytes", "gas_create", "gas_set_state", "gas_set_actions", "gas_step",
+               "gas_step_backward", "gas_sensor_loss", "gas_enable_stats", "gas_solver_residual", "gas_timing_enable",
+               "gas_timing_read", "gas_clock", "gas_destroy"]
+
 MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS, MPM_OPT_ADJOINT = 1, 2, 3, 4, 5
 
 _lib = None
@@ -90,6 +107,25 @@ def lib():
     L.mpm_destroy.argtypes = [vp]
     L.mpm_strerror.argtypes = [ctypes.c_int]
     L.mpm_strerror.restype = ctypes.c_char_p
+    gp = ctypes.POINTER(GasState)
+    L.gas_workspace_bytes.argtypes = [ctypes.POINTER(GasDesc)]
+    L.gas_workspace_bytes.restype = ctypes.c_size_t
+    L.gas_create.argtypes = [ctypes.POINTER(GasDesc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.gas_set_state.argtypes = [vp, gp]
+    L.gas_set_actions.argtypes = [vp, i32, i32, vp]
+    L.gas_step.argtypes = [vp, i32]
+    L.gas_step_backward.argtypes = [vp, gp, vp, gp]
+    L.gas_sensor_loss.argtypes = [vp, i32, vp, vp, vp, gp]
+    L.gas_enable_stats.argtypes = [vp, i32]
+    L.gas_solver_residual.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.gas_timing_enable.argtypes = [vp, i32]
+    L.gas_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(i64)]
+    L.gas_clock.argtypes = [vp, ctypes.POINTER(i32)]
+    L.gas_destroy.argtypes = [vp]
+    for name in GAS_EXPORTS:
+        if name != "gas_workspace_bytes":
+            getattr(L, name).restype = ctypes.c_int
     for name in EXPORTS:
         if name not in ("mpm_workspace_bytes", "mpm_strerror", "mpm_mlp_state_bytes", "mpm_mlp_scratch_bytes"):
             getattr(L, name).restype = ctypes.c_int

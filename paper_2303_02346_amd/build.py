@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpm.so")
-SOURCES = ["mpm_api.hip", "mpm_kernels.hip", "mpm_fast.hip", "mpm_adjoint.hip", "mpm_rigid.hip", "mpm_mlp.hip"]
+SOURCES = ["mpm_api.hip", "mpm_kernels.hip", "mpm_fast.hip", "mpm_adjoint.hip", "mpm_rigid.hip", "mpm_mlp.hip", "gas.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

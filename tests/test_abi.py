@@ -60,3 +60,47 @@ def test_host_validation_without_gpu():
     assert L.mpm_create(ctypes.byref(d), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == _lib.MPM_EWORKSPACE
     assert L.mpm_step(None, 1) == _lib.MPM_EINVAL
     assert L.mpm_strerror(_lib.MPM_EDOMAIN).startswith(b"simulation")
+
+
+def gas_declared_functions():
+    src = open(os.path.join(ROOT, "include", "gas.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gas_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_gas_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = gas_declared_functions()
+    for n in ("gas_create", "gas_step", "gas_step_backward", "gas_set_state", "gas_set_actions", "gas_destroy"):
+        assert n in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(_lib.GAS_EXPORTS) == set(names)
+
+
+def test_gas_host_validation_without_gpu():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    L = _lib.lib()
+    assert L.gas_workspace_bytes(None) == 0
+    src = (ctypes.c_float * 2)(0.0, 1.0)
+    d = _lib.GasDesc()
+    d.nx = d.ny = d.nz = 32
+    d.h, d.dt, d.buoyancy, d.t_amb = 1.0 / 32, 5e-3, 1.0, 1.0
+    d.n_scalars = 2
+    d.src = ctypes.cast(src, ctypes.POINTER(ctypes.c_float))
+    d.emit_sigma, d.emit_kappa, d.emit_speed = 0.05, 0.5, 2.0
+    d.horizon, d.ckpt_every, d.requires_grad, d.mg_cycles = 10, 4, 1, 8
+    ws = L.gas_workspace_bytes(ctypes.byref(d))
+    assert ws > 0 and ws % 256 == 0
+    d.nz = 30            # not a multiple of 4
+    assert L.gas_workspace_bytes(ctypes.byref(d)) == 0
+    d.nz = 32
+    d.emit_kappa = 1.5   # blend weight above 1
+    assert L.gas_workspace_bytes(ctypes.byref(d)) == 0
+    d.emit_kappa = 0.5
+    out = ctypes.c_void_p()
+    assert L.gas_create(ctypes.byref(d), None, 0, None, ctypes.byref(out)) == _lib.MPM_EINVAL
+    assert L.gas_create(ctypes.byref(d), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == _lib.MPM_EWORKSPACE

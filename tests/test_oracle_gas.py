@@ -195,3 +195,19 @@ def test_sensor_loss():
     cells = torch.tensor([0, 5, 63])
     targets = torch.tensor([1.0, 5.0, 60.0], dtype=DT)
     assert G.sensor_loss(s, cells, targets).item() == 1.0 + 0.0 + 3.0
+
+
+def test_cg_pressure_path_equals_direct_path():
+    """The conjugate-gradient solve used for grids too large to factorise
+    gives the direct solve's projection (32^3, both paths forced)."""
+    p = params(n=(32, 32, 32))
+    st = rand_state(p, 14)
+    a = G.project(st, p)
+    old = G.DIRECT_MAX_CELLS
+    try:
+        G.DIRECT_MAX_CELLS = 0
+        b = G.project(st, p)
+    finally:
+        G.DIRECT_MAX_CELLS = old
+    for q in G.COMPS:
+        assert torch.allclose(a[q], b[q], atol=1e-10 * a[q].abs().max().item())
