@@ -244,6 +244,61 @@ def bench_rigid(torch, steps=100, bwd_steps=32):
     return out
 
 
+def bench_gas(torch, n=128, steps=20, bwd_steps=8):
+    """The gas solver (section 3.2's advection-projection) on the 128^3
+    grid of the air-circulation task: forward steps, forward+backward, and
+    the roofline of the finest-level smoother (the dominant kernel: each
+    red-black half-sweep reads f and the other colour's psi and writes its
+    own colour's psi, 6 B per cell)."""
+    from paper_2303_02346_amd import scenes
+    from paper_2303_02346_amd.gas import GasSim
+    sc = scenes.gas_room(n=n, steps=max(steps, bwd_steps) + 2, seed=0)
+    cells = n ** 3
+    sim = GasSim(sc, horizon=steps + 2)
+    sim.step(2)
+    sim.reset()
+    torch.cuda.synchronize()
+    sim.timing(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    adv_ms, adv_n, sm_ms, sm_n = sim.timing_read()
+    sim.timing(False)
+    sim.enable_stats(True)
+    sim.reset()
+    sim.step(1)
+    res = sim.residual()
+    sim.close()
+    simg = GasSim(sc, requires_grad=True, ckpt_every=16, horizon=bwd_steps)
+    w = torch.ones_like(simg.buf)
+    for rep in range(2):
+        simg.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        simg.step(bwd_steps)
+        simg.backward(w)
+        torch.cuda.synchronize()
+        t_fb = time.perf_counter() - t0
+    simg.close()
+    sm_avg = sm_ms / max(sm_n, 1) * 1e-3
+    sm_bytes = 6.0 * cells
+    ach = sm_bytes / sm_avg / 1e9 if sm_n else None
+    out = {"workload": f"gas room {n}^3 (velocity + temperature + smoke), emitter turning about y, dt=5e-3",
+           "cells": cells, "steps": steps, "ms_per_step": t * 1e3 / steps, "cell_steps_per_s": cells * steps / t,
+           "fwd_bwd_steps": bwd_steps, "fwd_bwd_ms_per_step": t_fb * 1e3 / bwd_steps,
+           "mg_cycles": 8, "pressure_rel_residual": res,
+           "advect_avg_us": adv_ms / max(adv_n, 1) * 1e3,
+           "roofline": {"bound": "hbm", "kernel": "k_rbgs (finest level)", "achieved": round(ach, 1) if ach else None,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None,
+                        "avg_us": round(sm_avg * 1e6, 2), "algorithmic_bytes_per_launch": int(sm_bytes),
+                        "traffic": None}}
+    log(f"[bench] gas {n}^3: forward {out['ms_per_step']:.3f} ms/step ({out['cell_steps_per_s']:.3e} cell-steps/s), "
+        f"fwd+bwd {out['fwd_bwd_ms_per_step']:.3f} ms/step; finest smoother {out['roofline']['avg_us']} us "
+        f"({out['roofline']['frac']} of HBM peak); residual {res:.1e}")
+    return out
+
+
 def copy_calibration(torch, mb):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
@@ -273,6 +328,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper-point", action="store_true")
     ap.add_argument("--no-rigid", action="store_true")
+    ap.add_argument("--no-gas", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0, help="first run a device copy of this size (counter scaling)")
     ap.add_argument("--closure", action="store_true", help="also train and time the learned closure (config 5)")
     args = ap.parse_args()
@@ -376,6 +432,7 @@ def main():
     paper = None if args.no_paper_point else bench_paper_point(torch)
 
     rigid = None if args.no_rigid else bench_rigid(torch)
+    gas = None if args.no_gas else bench_gas(torch)
 
     closure = bench_closure(torch) if args.closure else None
 
@@ -399,6 +456,7 @@ def main():
         "batched": batched,
         "paper_point": paper,
         "rigid": rigid,
+        "gas": gas,
         "closure": closure,
         "roofline": roof,
         "cpu_baseline": cpu,
