@@ -47,7 +47,8 @@ extern "C" {
 typedef struct gas_ctx gas_ctx;
 
 typedef struct {
-  int32_t nx, ny, nz;        /* cells per axis: multiples of 4 in [8, 1024] */
+  int32_t nx, ny, nz;        /* cells per axis: multiples of 4 in [8, 1024], such that halving
+                                while every axis is even reaches at most 4096 cells */
   float h;                   /* cell size */
   float dt;
   float buoyancy, t_amb;     /* beta and the ambient temperature */
@@ -58,7 +59,8 @@ typedef struct {
   int32_t horizon;           /* maximum number of steps between gas_set_state calls */
   int32_t ckpt_every;        /* checkpoint period for the backward */
   int32_t requires_grad;     /* record checkpoints during gas_step */
-  int32_t mg_cycles;         /* multigrid V-cycles per pressure solve (1..64; 8) */
+  int32_t mg_cycles;         /* multigrid V-cycles per pressure solve (1..64; 6 reach the FP32
+                                residual floor, about 2e-5, on 128^3) */
 } gas_desc;
 
 typedef struct {

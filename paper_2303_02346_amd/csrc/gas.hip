@@ -36,8 +36,14 @@ constexpr int SLOTS = 128;
 constexpr int POSE_PARTIALS = 6;          // c (3), a = R e_y (3)
 constexpr int BOTTOM_CELLS = 4096;        // levels this small run inside one workgroup, in LDS
 constexpr int BOTTOM_LDS = 4800;          // >= 4096 * 8 / 7
+constexpr int BOTTOM_THREADS = 1024;
 constexpr int MAX_LEVELS = 12;
-constexpr int COARSE_SWEEPS = 16;
+constexpr int COARSE_SWEEPS = 8;
+// smoother tiles: TX x TY x TZ cells per workgroup; psi staged with a 2-cell
+// halo, f with a 1-cell halo
+constexpr int TX = 8, TY = 8, TZ = 16;
+constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4;
+constexpr int FX = TX + 2, FY = TY + 2, FZ = TZ + 2;
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline unsigned nblk(size_t n, unsigned b) {
@@ -294,15 +300,91 @@ __device__ inline float nb_sum(const float* psi, const Dims& D, int i, int j, in
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_rbgs(float* __restrict__ psi, const float* __restrict__ f, Dims D, int color) {
-  const size_t n = D.cells();
-  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n; g += (size_t)gridDim.x * blockDim.x) {
-    int i, j, k;
-    cell_of(D, g, i, j, k);
-    if (((i + j + k) & 1) != color) continue;
-    int cnt;
-    const float s = nb_sum(psi, D, i, j, k, cnt);
-    psi[g] = (s - f[g]) / (float)cnt;
+__device__ inline bool inside(const Dims& D, int i, int j, int k) {
+  return i >= 0 && j >= 0 && k >= 0 && i < D.x && j < D.y && k < D.z;
+}
+__device__ inline float prolong_at(const float* psi_c, const Dims& Dc, int i, int j, int k);
+
+// One full red-black Gauss-Seidel sweep (colour c1, then the other colour)
+// per tile.  The tile's colour-c1 cells are updated on the tile and its
+// 1-cell halo (the halo values are the ones the neighbouring tiles compute
+// from the same old values), then the other colour on the tile itself, so
+// the result equals two separate half-sweeps over the whole grid.  With
+// psi_c, the prolonged coarse correction is added to every staged value
+// first (the correction step fused into the sweep that follows it).
+__global__ __launch_bounds__(256) void k_rb_sweep(float* __restrict__ psi, const float* __restrict__ f, Dims D, int c1,
+                                                  const float* __restrict__ psi_c, Dims Dc) {
+  constexpr int NP = PX * PY * PZ, NF = FX * FY * FZ;
+  constexpr int RP = (NP + 255) / 256, RF = (NF + 255) / 256;
+  __shared__ float sP[NP], sF[NF];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, k0 = blockIdx.z * TZ;
+  // staging: every load of the thread is issued before the first is used
+  // (a loop that stored each value to LDS as it arrived would wait out one
+  // memory latency per iteration)
+  float vp[RP], vf[RF];
+#pragma unroll
+  for (int r = 0; r < RP; r++) {
+    const int q = tid + r * 256;
+    const int a = q / (PY * PZ), b = (q / PZ) % PY, c = q % PZ;
+    const int i = i0 - 2 + a, j = j0 - 2 + b, k = k0 - 2 + c;
+    vp[r] = (q < NP && inside(D, i, j, k)) ? psi[gidx(i, j, k, D.y, D.z)] : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < RF; r++) {
+    const int q = tid + r * 256;
+    const int a = q / (FY * FZ), b = (q / FZ) % FY, c = q % FZ;
+    const int i = i0 - 1 + a, j = j0 - 1 + b, k = k0 - 1 + c;
+    vf[r] = (q < NF && inside(D, i, j, k)) ? f[gidx(i, j, k, D.y, D.z)] : 0.f;
+  }
+  if (psi_c) {
+#pragma unroll
+    for (int r = 0; r < RP; r++) {
+      const int q = tid + r * 256;
+      const int a = q / (PY * PZ), b = (q / PZ) % PY, c = q % PZ;
+      const int i = i0 - 2 + a, j = j0 - 2 + b, k = k0 - 2 + c;
+      if (q < NP && inside(D, i, j, k)) vp[r] += prolong_at(psi_c, Dc, i, j, k);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RP; r++) {
+    const int q = tid + r * 256;
+    if (q < NP) sP[q] = vp[r];
+  }
+#pragma unroll
+  for (int r = 0; r < RF; r++) {
+    const int q = tid + r * 256;
+    if (q < NF) sF[q] = vf[r];
+  }
+  __syncthreads();
+  auto update = [&](int i, int j, int k, int pq, int fq) {
+    float s = 0.f;
+    int cnt = 0;
+    if (i > 0) { s += sP[pq - PY * PZ]; cnt++; }
+    if (i + 1 < D.x) { s += sP[pq + PY * PZ]; cnt++; }
+    if (j > 0) { s += sP[pq - PZ]; cnt++; }
+    if (j + 1 < D.y) { s += sP[pq + PZ]; cnt++; }
+    if (k > 0) { s += sP[pq - 1]; cnt++; }
+    if (k + 1 < D.z) { s += sP[pq + 1]; cnt++; }
+    sP[pq] = (s - sF[fq]) / (float)cnt;
+  };
+  for (int q = tid; q < FX * FY * FZ; q += 256) {
+    const int a = q / (FY * FZ), b = (q / FZ) % FY, c = q % FZ;
+    const int i = i0 - 1 + a, j = j0 - 1 + b, k = k0 - 1 + c;
+    if (inside(D, i, j, k) && ((i + j + k) & 1) == c1) update(i, j, k, ((a + 1) * PY + b + 1) * PZ + c + 1, q);
+  }
+  __syncthreads();
+  for (int q = tid; q < TX * TY * TZ; q += 256) {
+    const int a = q / (TY * TZ), b = (q / TZ) % TY, c = q % TZ;
+    const int i = i0 + a, j = j0 + b, k = k0 + c;
+    if (inside(D, i, j, k) && ((i + j + k) & 1) != c1)
+      update(i, j, k, ((a + 2) * PY + b + 2) * PZ + c + 2, ((a + 1) * FY + b + 1) * FZ + c + 1);
+  }
+  __syncthreads();
+  for (int q = tid; q < TX * TY * TZ; q += 256) {
+    const int a = q / (TY * TZ), b = (q / TZ) % TY, c = q % TZ;
+    const int i = i0 + a, j = j0 + b, k = k0 + c;
+    if (inside(D, i, j, k)) psi[gidx(i, j, k, D.y, D.z)] = sP[((a + 2) * PY + b + 2) * PZ + c + 2];
   }
 }
 
@@ -345,15 +427,6 @@ __device__ inline float prolong_at(const float* psi_c, const Dims& Dc, int i, in
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_prolong(const float* __restrict__ psi_c, Dims Dc, float* __restrict__ psi,
-                                                 Dims Df) {
-  const size_t n = Df.cells();
-  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n; g += (size_t)gridDim.x * blockDim.x) {
-    int i, j, k;
-    cell_of(Df, g, i, j, k);
-    psi[g] += prolong_at(psi_c, Dc, i, j, k);
-  }
-}
 
 struct BottomArgs {
   int n_levels;              // levels handled here (the first is the entry level)
@@ -363,8 +436,9 @@ struct BottomArgs {
 };
 
 // The V-cycle below the entry level, in one workgroup with every level in LDS.
-__global__ __launch_bounds__(1024) void k_bottom(BottomArgs B) {
+__global__ __launch_bounds__(BOTTOM_THREADS) void k_bottom(BottomArgs B) {
   __shared__ float s_psi[BOTTOM_LDS], s_f[BOTTOM_LDS];
+  __shared__ int s_ijk[BOTTOM_LDS];   // packed i | j << 10 | k << 20 of every cell of every level
   const int tid = threadIdx.x, NT = blockDim.x;
   int off[MAX_LEVELS];
   {
@@ -373,14 +447,22 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs B) {
   }
   const int n0 = (int)B.D[0].cells();
   for (int c = tid; c < n0; c += NT) { s_psi[c] = B.psi[c]; s_f[c] = B.f[c]; }
+  // the cell coordinates, decoded once (the phases below only read them)
+  for (int l = 0; l < B.n_levels; l++)
+    for (int c = tid; c < (int)B.D[l].cells(); c += NT) {
+      int i, j, k;
+      cell_of(B.D[l], c, i, j, k);
+      s_ijk[off[l] + c] = i | (j << 10) | (k << 20);
+    }
   __syncthreads();
   auto sweep = [&](int l, int color) {
     const Dims D = B.D[l];
     float* p = s_psi + off[l];
     const float* fl = s_f + off[l];
+    const int* ijk = s_ijk + off[l];
     for (int c = tid; c < (int)D.cells(); c += NT) {
-      int i, j, k;
-      cell_of(D, c, i, j, k);
+      const int e = ijk[c];
+      const int i = e & 1023, j = (e >> 10) & 1023, k = e >> 20;
       if (((i + j + k) & 1) != color) continue;
       int cnt;
       const float s = nb_sum(p, D, i, j, k, cnt);
@@ -393,8 +475,8 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs B) {
     sweep(l, 0); sweep(l, 1); sweep(l, 0); sweep(l, 1);
     const Dims Df = B.D[l], Dc = B.D[l + 1];
     for (int c = tid; c < (int)Dc.cells(); c += NT) {
-      int I, J, K;
-      cell_of(Dc, c, I, J, K);
+      const int e = s_ijk[off[l + 1] + c];
+      const int I = e & 1023, J = (e >> 10) & 1023, K = e >> 20;
       float r = 0.f;
       for (int q = 0; q < 8; q++)
         r += residual_at(s_psi + off[l], s_f + off[l], Df, 2 * I + (q >> 2), 2 * J + ((q >> 1) & 1), 2 * K + (q & 1));
@@ -407,8 +489,8 @@ __global__ __launch_bounds__(1024) void k_bottom(BottomArgs B) {
   for (int l = L - 2; l >= 0; l--) {
     const Dims Df = B.D[l], Dc = B.D[l + 1];
     for (int c = tid; c < (int)Df.cells(); c += NT) {
-      int i, j, k;
-      cell_of(Df, c, i, j, k);
+      const int e = s_ijk[off[l] + c];
+      const int i = e & 1023, j = (e >> 10) & 1023, k = e >> 20;
       s_psi[off[l] + c] += prolong_at(s_psi + off[l + 1], Dc, i, j, k);
     }
     __syncthreads();
@@ -785,27 +867,28 @@ void mg_solve(gas_ctx* c, float* psi0, float* f0) {
   for (int l = 0; l < B.n_levels; l++) B.D[l] = L.D[G + l];
   B.psi = psi(G);
   B.f = fl(G);
+  auto tiles = [&](int l) {
+    const Dims& D = L.D[l];
+    return dim3((D.x + TX - 1) / TX, (D.y + TY - 1) / TY, (D.z + TZ - 1) / TZ);
+  };
+  // V(2,2): red-black sweeps before each restriction, black-red sweeps after
+  // each correction (the first of them adds the correction as it stages)
   for (int cyc = 0; cyc < c->d.mg_cycles; cyc++) {
     for (int l = 0; l < G; l++) {
-      const unsigned nb = nblk(L.D[l].cells(), 256);
-      for (int sw = 0; sw < 2; sw++)
-        for (int color = 0; color < 2; color++) {
-          if (l == 0) c->t_smooth.begin(s);
-          k_rbgs<<<nb, 256, 0, s>>>(psi(l), fl(l), L.D[l], color);
-          if (l == 0) c->t_smooth.end(s);
-        }
+      for (int sw = 0; sw < 2; sw++) {
+        if (l == 0) c->t_smooth.begin(s);
+        k_rb_sweep<<<tiles(l), 256, 0, s>>>(psi(l), fl(l), L.D[l], 0, nullptr, L.D[l]);
+        if (l == 0) c->t_smooth.end(s);
+      }
       k_restrict<<<nblk(L.D[l + 1].cells(), 256), 256, 0, s>>>(psi(l), fl(l), L.D[l], psi(l + 1), fl(l + 1), L.D[l + 1]);
     }
-    k_bottom<<<1, 1024, 0, s>>>(B);
+    k_bottom<<<1, BOTTOM_THREADS, 0, s>>>(B);
     for (int l = G - 1; l >= 0; l--) {
-      const unsigned nb = nblk(L.D[l].cells(), 256);
-      k_prolong<<<nb, 256, 0, s>>>(psi(l + 1), L.D[l + 1], psi(l), L.D[l]);
-      for (int sw = 0; sw < 2; sw++)
-        for (int color = 1; color >= 0; color--) {
-          if (l == 0) c->t_smooth.begin(s);
-          k_rbgs<<<nb, 256, 0, s>>>(psi(l), fl(l), L.D[l], color);
-          if (l == 0) c->t_smooth.end(s);
-        }
+      for (int sw = 0; sw < 2; sw++) {
+        if (l == 0) c->t_smooth.begin(s);
+        k_rb_sweep<<<tiles(l), 256, 0, s>>>(psi(l), fl(l), L.D[l], 1, sw == 0 ? psi(l + 1) : nullptr, L.D[l + 1]);
+        if (l == 0) c->t_smooth.end(s);
+      }
     }
   }
   if (c->stats) {
@@ -893,7 +976,7 @@ int gas_create(const gas_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   c->stats = false;
   c->last_res = 0.0;
   c->t_adv.name = "k_gas_advect";
-  c->t_smooth.name = "k_rbgs";
+  c->t_smooth.name = "k_rb_sweep";
   c->act_set.assign(d->horizon, 0);
   GP& P = c->P;
   P.nx = d->nx; P.ny = d->ny; P.nz = d->nz; P.K = d->n_scalars;

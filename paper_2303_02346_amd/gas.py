@@ -24,7 +24,7 @@ class GasSim:
     are views with the grid shapes."""
 
     def __init__(self, sc: GasScene, requires_grad: bool = False, ckpt_every: int = 16,
-                 horizon: Optional[int] = None, mg_cycles: int = 8, device: str = "cuda"):
+                 horizon: Optional[int] = None, mg_cycles: int = 6, device: str = "cuda"):
         self.sc = sc
         self.device = torch.device(device)
         nx, ny, nz = (int(a) for a in sc.n)
