@@ -36,12 +36,27 @@ constexpr int SLOTS = 128;
 constexpr int POSE_PARTIALS = 6;          // c (3), a = R e_y (3)
 constexpr int BOTTOM_CELLS = 4096;        // levels this small run inside one workgroup, in LDS
 constexpr int BOTTOM_LDS = 4800;          // >= 4096 * 8 / 7
-constexpr int BOTTOM_THREADS = 1024;
+#ifndef GAS_BOTTOM_THREADS
+#define GAS_BOTTOM_THREADS 1024
+#endif
+constexpr int BOTTOM_THREADS = GAS_BOTTOM_THREADS;
 constexpr int MAX_LEVELS = 12;
-constexpr int COARSE_SWEEPS = 8;
+#ifndef GAS_COARSE_SWEEPS
+#define GAS_COARSE_SWEEPS 4
+#endif
+constexpr int COARSE_SWEEPS = GAS_COARSE_SWEEPS;
 // smoother tiles: TX x TY x TZ cells per workgroup; psi staged with a 2-cell
 // halo, f with a 1-cell halo
-constexpr int TX = 8, TY = 8, TZ = 16;
+#ifndef GAS_TILE_X
+#define GAS_TILE_X 8
+#endif
+#ifndef GAS_TILE_Y
+#define GAS_TILE_Y 8
+#endif
+#ifndef GAS_TILE_Z
+#define GAS_TILE_Z 8
+#endif
+constexpr int TX = GAS_TILE_X, TY = GAS_TILE_Y, TZ = GAS_TILE_Z;
 constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4;
 constexpr int FX = TX + 2, FY = TY + 2, FZ = TZ + 2;
 
@@ -366,7 +381,9 @@ __global__ __launch_bounds__(256) void k_rb_sweep(float* __restrict__ psi, const
     if (j + 1 < D.y) { s += sP[pq + PZ]; cnt++; }
     if (k > 0) { s += sP[pq - 1]; cnt++; }
     if (k + 1 < D.z) { s += sP[pq + 1]; cnt++; }
-    sP[pq] = (s - sF[fq]) / (float)cnt;
+    // 1 / cnt for cnt in 1..6 (a division would cost a long sequence)
+    const float inv = cnt == 6 ? (1.f / 6.f) : (cnt == 5 ? 0.2f : (cnt == 4 ? 0.25f : (cnt == 3 ? (1.f / 3.f) : (cnt == 2 ? 0.5f : 1.f))));
+    sP[pq] = (s - sF[fq]) * inv;
   };
   for (int q = tid; q < FX * FY * FZ; q += 256) {
     const int a = q / (FY * FZ), b = (q / FZ) % FY, c = q % FZ;
