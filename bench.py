@@ -39,15 +39,18 @@ KERNEL_BYTES = {
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_g2p2g_config2_traffic.md")
 TRAFFIC_SOURCES = ["mpm_fast.hip", "mpm_fast.h", "mpm_blocks.h", "mpm_phys.h", "mpm_math.h", "mpm_internal.h"]
+GAS_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_rb_sweep_gas128_traffic.md")
+GAS_TRAFFIC_SOURCES = ["gas.hip"]
 
 
-def counted_traffic():
-    """HBM bytes per fused launch from the committed counter summary, or None
-    when the kernel's sources have changed since the counters were taken."""
+def counted_traffic(summary=None, sources=None):
+    """HBM bytes per launch from a committed counter summary (default: the
+    fused MPM kernel's), or None when the kernel's sources have changed
+    since the counters were taken."""
     import hashlib
     import re
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(summary or TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     m_b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
@@ -55,7 +58,7 @@ def counted_traffic():
     if not m_b or not m_h:
         return None
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in (sources or TRAFFIC_SOURCES):
         with open(os.path.join(ROOT, "paper_2303_02346_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return int(m_b.group(1)) if h.hexdigest()[:16] == m_h.group(1) else None
@@ -292,7 +295,7 @@ def bench_gas(torch, n=128, steps=20, bwd_steps=8):
            "roofline": {"bound": "hbm", "kernel": "k_rb_sweep (finest level)", "achieved": round(ach, 1) if ach else None,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None,
                         "avg_us": round(sm_avg * 1e6, 2), "algorithmic_bytes_per_launch": int(sm_bytes),
-                        "traffic": None}}
+                        "traffic": counted_traffic(GAS_TRAFFIC_SUMMARY, GAS_TRAFFIC_SOURCES) if n == 128 else None}}
     log(f"[bench] gas {n}^3: forward {out['ms_per_step']:.3f} ms/step ({out['cell_steps_per_s']:.3e} cell-steps/s), "
         f"fwd+bwd {out['fwd_bwd_ms_per_step']:.3f} ms/step; finest smoother {out['roofline']['avg_us']} us "
         f"({out['roofline']['frac']} of HBM peak); residual {res:.1e}")
