@@ -34,6 +34,8 @@
  * state, actions, gradients and one workspace of gas_workspace_bytes()
  * bytes, 256-byte aligned); the library allocates no device memory; all work
  * goes on the stream given to gas_create; calls return an mpm_status.
+ * Back-traces that leave a grid are clamped, so a gas step never leaves
+ * its domain; non-finite values are reported (gas_last_error_bits).
  */
 #ifndef MPM355_GAS_H
 #define MPM355_GAS_H
@@ -110,6 +112,11 @@ int gas_solver_residual(gas_ctx* c, double* rel_residual);
 int gas_timing_enable(gas_ctx* c, int32_t enable);
 int gas_timing_read(gas_ctx* c, double* advect_ms, int64_t* advect_launches, double* smooth_ms,
                     int64_t* smooth_launches);
+
+/* gas_step and gas_step_backward end with one read of a device error word
+ * and return MPM_EDOMAIN when a kernel wrote a non-finite velocity, scalar
+ * or adjoint velocity (MPM_ERR_NONFINITE); the bits of the last such call: */
+int gas_last_error_bits(const gas_ctx* c, int32_t* bits_out);
 
 int gas_clock(const gas_ctx* c, int32_t* t_out);
 int gas_destroy(gas_ctx* c);

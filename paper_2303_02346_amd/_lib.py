@@ -53,7 +53,7 @@ class GasState(ctypes.Structure):
 
 GAS_EXPORTS = ["gas_workspace_bytes", "gas_create", "gas_set_state", "gas_set_actions", "gas_step",
                "gas_step_backward", "gas_sensor_loss", "gas_enable_stats", "gas_solver_residual", "gas_timing_enable",
-               "gas_timing_read", "gas_clock", "gas_destroy"]
+               "gas_timing_read", "gas_last_error_bits", "gas_clock", "gas_destroy"]
 
 MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS, MPM_OPT_ADJOINT = 1, 2, 3, 4, 5
 
@@ -121,6 +121,7 @@ def lib():
     L.gas_timing_enable.argtypes = [vp, i32]
     L.gas_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(i64)]
+    L.gas_last_error_bits.argtypes = [vp, ctypes.POINTER(i32)]
     L.gas_clock.argtypes = [vp, ctypes.POINTER(i32)]
     L.gas_destroy.argtypes = [vp]
     for name in GAS_EXPORTS:

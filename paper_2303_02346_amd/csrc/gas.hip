@@ -78,6 +78,7 @@ struct GP {
   float kappa, speed;
   float src[MAXK];
   size_t nu, nv, nw, nc;
+  int* err;             // device error word (MPM_ERR_NONFINITE)
 };
 
 // grid q: 0 = u (x-faces), 1 = v, 2 = w, 3 = cells
@@ -267,6 +268,7 @@ __global__ __launch_bounds__(256) void k_gas_final(GP P, const float* __restrict
     const int q = split_points(P, g);
     if (q == 3) {
       s[g] = s1[g];
+      if (!isfinite(s1[g])) atomicOr(P.err, ERR_NONFINITE);
       continue;
     }
     int i, j, k;
@@ -283,6 +285,7 @@ __global__ __launch_bounds__(256) void k_gas_final(GP P, const float* __restrict
       else if (q == 1) val = buoyant_v(P, v1, s1, i, j, k) - gp;
       else val = w1[g] - gp;
     }
+    if (!isfinite(val)) atomicOr(P.err, ERR_NONFINITE);
     float* O = q == 0 ? u : (q == 1 ? v : w);
     O[g] = val;
   }
@@ -588,6 +591,7 @@ __global__ __launch_bounds__(256) void k_gas_adj_sub(GP P, const float* __restri
       const size_t lo = gidx(i - (q == 0), j - (q == 1), k - (q == 2), P.ny, P.nz);
       val = In[g] - (psi[hi] - psi[lo]);
     }
+    if (!isfinite(val)) atomicOr(P.err, ERR_NONFINITE);
     O[g] = val;
   }
 }
@@ -756,7 +760,7 @@ __global__ __launch_bounds__(256) void k_gas_sensors(const float* __restrict__ T
 // host side
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t tmp, pose, act, acc, slots, resp, resout, ckpt, seg, adj0, adj1;
+  size_t tmp, pose, act, acc, slots, resp, resout, err, ckpt, seg, adj0, adj1;
   size_t psi[MAX_LEVELS], f[MAX_LEVELS];
   size_t total;
   size_t state_floats;
@@ -807,6 +811,7 @@ Layout plan(const gas_desc* d) {
   L.slots = take(SLOTS * POSE_PARTIALS * sizeof(double));
   L.resp = take(2 * 4096 * sizeof(double));
   L.resout = take(64);
+  L.err = take(64);
   if (d->requires_grad) {
     const int k = d->ckpt_every;
     L.n_ckpt = (int)((T + k - 1) / k) + 1;
@@ -846,6 +851,7 @@ struct gas_ctx {
   int t;
   bool stats;
   double last_res;
+  int last_err_bits;
   KernelTimer t_adv, t_smooth;
 };
 
@@ -952,7 +958,11 @@ void gas_adjoint_step(gas_ctx* c, const gas_state& st, const gas_state& an, cons
   k_gas_pose_acc<<<1, 64, 0, s>>>((double*)(c->ws + c->L.slots), acc_t);
 }
 
+// Waits for the call's work; reads (and clears) the device error word.
 int sync_ok(gas_ctx* c) {
+  int bits = 0;
+  if (hipMemcpyAsync(&bits, c->ws + c->L.err, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return MPM_EHIP;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return MPM_EHIP;
   if (hipGetLastError() != hipSuccess) return MPM_EHIP;
   c->t_adv.collect();
@@ -961,6 +971,12 @@ int sync_ok(gas_ctx* c) {
     double r = 0.0;
     if (hipMemcpy(&r, c->ws + c->L.resout, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return MPM_EHIP;
     c->last_res = r;
+  }
+  if (bits) {
+    c->last_err_bits = bits;
+    if (hipMemsetAsync(c->ws + c->L.err, 0, sizeof(int), c->stream) != hipSuccess) return MPM_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MPM_EHIP;
+    return MPM_EDOMAIN;
   }
   return MPM_OK;
 }
@@ -992,6 +1008,7 @@ int gas_create(const gas_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   c->t = 0;
   c->stats = false;
   c->last_res = 0.0;
+  c->last_err_bits = 0;
   c->t_adv.name = "k_gas_advect";
   c->t_smooth.name = "k_rb_sweep";
   c->act_set.assign(d->horizon, 0);
@@ -1006,7 +1023,9 @@ int gas_create(const gas_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   P.nv = (size_t)d->nx * (d->ny + 1) * d->nz;
   P.nw = (size_t)d->nx * d->ny * (d->nz + 1);
   P.nc = (size_t)d->nx * d->ny * d->nz;
+  P.err = (int*)(c->ws + L.err);
   launch_zero(c->ws + L.slots, SLOTS * POSE_PARTIALS * sizeof(double), c->stream);
+  launch_zero(c->ws + L.err, 64, c->stream);
   if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) { delete c; return MPM_EHIP; }
   *out = c;
   return MPM_OK;
@@ -1139,6 +1158,12 @@ int gas_timing_read(gas_ctx* c, double* advect_ms, int64_t* advect_launches, dou
   *smooth_launches = c->t_smooth.launches;
   c->t_adv.total_ms = c->t_smooth.total_ms = 0.0;
   c->t_adv.launches = c->t_smooth.launches = 0;
+  return MPM_OK;
+}
+
+int gas_last_error_bits(const gas_ctx* c, int32_t* bits_out) {
+  if (!c || !bits_out) return MPM_EINVAL;
+  *bits_out = c->last_err_bits;
   return MPM_OK;
 }
 

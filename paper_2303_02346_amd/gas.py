@@ -86,6 +86,13 @@ class GasSim:
     def _sync_in(self):
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
 
+    def _check(self, status: int, where: str):
+        if status != _lib.MPM_OK:
+            bits = ctypes.c_int32(0)
+            if status == _lib.MPM_EDOMAIN:
+                _lib.lib().gas_last_error_bits(self.ctx, ctypes.byref(bits))
+            raise _lib.MpmError(status, where, bits.value)
+
     # calls ------------------------------------------------------------------
     def load(self, u=None, v=None, w=None, s=None):
         sc = self.sc
@@ -96,7 +103,7 @@ class GasSim:
         self.load()
         self._sync_in()
         self._state = self.struct(self.buf)
-        _lib.check(_lib.lib().gas_set_state(self.ctx, ctypes.byref(self._state)), "gas_set_state")
+        self._check(_lib.lib().gas_set_state(self.ctx, ctypes.byref(self._state)), "gas_set_state")
         self.set_actions(self.actions)
 
     def set_actions(self, actions: torch.Tensor, t0: int = 0):
@@ -108,7 +115,7 @@ class GasSim:
 
     def step(self, n: int):
         self._sync_in()
-        _lib.check(_lib.lib().gas_step(self.ctx, int(n)), "gas_step")
+        self._check(_lib.lib().gas_step(self.ctx, int(n)), "gas_step")
 
     def clock(self) -> int:
         t = ctypes.c_int32(0)
@@ -125,7 +132,7 @@ class GasSim:
         g0 = torch.zeros_like(self.buf) if want_grad0 else None
         g0s = self.struct(g0) if want_grad0 else None
         self._sync_in()
-        _lib.check(_lib.lib().gas_step_backward(self.ctx, ctypes.byref(gs), ctypes.c_void_p(ga.data_ptr()),
+        self._check(_lib.lib().gas_step_backward(self.ctx, ctypes.byref(gs), ctypes.c_void_p(ga.data_ptr()),
                                                 ctypes.byref(g0s) if g0s is not None else None), "gas_step_backward")
         return (ga, g0) if want_grad0 else ga
 
@@ -136,7 +143,7 @@ class GasSim:
         g = torch.zeros_like(self.buf) if want_grad else None
         gs = self.struct(g) if want_grad else None
         self._sync_in()
-        _lib.check(_lib.lib().gas_sensor_loss(self.ctx, int(cells.numel()), ctypes.c_void_p(cells.data_ptr()),
+        self._check(_lib.lib().gas_sensor_loss(self.ctx, int(cells.numel()), ctypes.c_void_p(cells.data_ptr()),
                                               ctypes.c_void_p(targets.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
                                               ctypes.byref(gs) if gs is not None else None), "gas_sensor_loss")
         return (loss, g) if want_grad else loss

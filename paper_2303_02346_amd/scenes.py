@@ -400,18 +400,22 @@ class GasScene:
         return self.actions.shape[0]
 
 
-def gas_room(n: int = 128, steps: int = 100, seed: int = 0, dt: float = 5e-3, velocity: float = 0.5,
-             n_scalars: int = 2, translate: bool = False) -> GasScene:
+def gas_room(n=128, steps: int = 100, seed: int = 0, dt: float = 5e-3, velocity: float = 0.5,
+             n_scalars: int = 2, translate: bool = False, **kw) -> GasScene:
     """A closed room of warm air (T = 1 with seeded smooth variations) and a
     cool-air emitter near the -x wall that swings about the vertical axis
     (the air-circulation task of section 4.1 on the 128^3 gas grid of
     section 4.2).  The initial velocity is a seeded smooth field (not
     divergence-free: the first projection removes its divergent part).  27
     temperature sensors sit on a 3x3x3 lattice with seeded cool/warm targets.
-    translate: also move the emitter (small seeded translational velocities)."""
-    rng = np.random.default_rng(np.random.SeedSequence([20230302, 77, n, seed]))
-    h = 1.0 / n
-    dims = (n, n, n)
+    translate: also move the emitter (small seeded translational velocities).
+    n: cells per axis, or (nx, ny, nz) for a box of cell size 1 / max(n);
+    other keyword arguments override GasScene fields (emitter, buoyancy)."""
+    dims = tuple(int(a) for a in n) if hasattr(n, "__len__") else (int(n),) * 3
+    cube = dims[0] == dims[1] == dims[2]
+    rng = np.random.default_rng(np.random.SeedSequence([20230302, 77, dims[0], seed] if cube else
+                                                       [20230302, 77, *dims, seed]))
+    h = 1.0 / max(dims)
 
     def smooth(shape, amp):
         # sum of a few seeded low-frequency modes sampled on the grid points
@@ -425,9 +429,10 @@ def gas_room(n: int = 128, steps: int = 100, seed: int = 0, dt: float = 5e-3, ve
                 np.sin(math.pi * k[1] * idx[1] / shape[1] + ph[1]) * np.sin(math.pi * k[2] * idx[2] / shape[2] + ph[2])
         return out
 
-    u = smooth((n + 1, n, n), velocity)
-    v = smooth((n, n + 1, n), velocity)
-    w = smooth((n, n, n + 1), velocity)
+    nx, ny, nz = dims
+    u = smooth((nx + 1, ny, nz), velocity)
+    v = smooth((nx, ny + 1, nz), velocity)
+    w = smooth((nx, ny, nz + 1), velocity)
     u[0] = u[-1] = 0.0
     v[:, 0] = v[:, -1] = 0.0
     w[:, :, 0] = w[:, :, -1] = 0.0
@@ -438,9 +443,14 @@ def gas_room(n: int = 128, steps: int = 100, seed: int = 0, dt: float = 5e-3, ve
     acts[:, 5] = 0.0                       # the air conditioner turns about y only
     if not translate:
         acts[:, :3] = 0.0
-    lat = [int(round(f * n)) for f in (0.2, 0.5, 0.8)]
-    sensors = np.array([(i * n + j) * n + k for i in lat for j in lat for k in lat], np.int64)
+    lat = [[int(round(f * d)) for f in (0.2, 0.5, 0.8)] for d in dims]
+    sensors = np.array([(i * ny + j) * nz + k for i in lat[0] for j in lat[1] for k in lat[2]], np.int64)
     targets = np.where(rng.random(sensors.size) < 0.5, 0.0, 1.0)
-    return GasScene(n=dims, h=h, dt=dt, u=u, v=v, w=w, s=s, actions=acts, sensors=sensors, targets=targets,
-                    src=(0.0, 1.0)[:n_scalars] if n_scalars <= 2 else tuple([0.0, 1.0] + [0.5] * (n_scalars - 2)),
-                    name=f"gas{n}_{seed}")
+    sc = GasScene(n=dims, h=h, dt=dt, u=u, v=v, w=w, s=s, actions=acts, sensors=sensors, targets=targets,
+                  src=(0.0, 1.0)[:n_scalars] if n_scalars <= 2 else tuple([0.0, 1.0] + [0.5] * (n_scalars - 2)),
+                  name=f"gas{nx}x{ny}x{nz}_{seed}")
+    for k, val in kw.items():
+        if not hasattr(sc, k):
+            raise TypeError(f"unknown GasScene field {k}")
+        setattr(sc, k, val)
+    return sc

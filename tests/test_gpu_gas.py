@@ -2,9 +2,10 @@
 1999; the air-circulation setting of section 4.1) through the C ABI, against
 the FP64 oracle on the same seeded scenes.
 
-Tolerances: FP32 advection and a multigrid pressure solve of 8 V-cycles
-(relative residual about 1e-6) against the oracle's exact projection:
-fields 2e-4 relative after several steps; gradients 2e-3 relative.
+Tolerances: FP32 advection and a multigrid pressure solve of 6 V-cycles
+(relative residual at the FP32 floor, 1e-6 to 3e-5 depending on the grid)
+against the oracle's exact projection: fields 2e-4 relative after several
+steps; gradients 2e-3 relative.
 """
 import sys
 
@@ -18,6 +19,7 @@ from paper_2303_02346_amd import scenes
 pytestmark = pytest.mark.gpu
 
 DT = torch.float64
+MPM_ERR_NONFINITE = 2
 
 
 def say(msg):
@@ -129,3 +131,38 @@ def test_gas_sensor_loss_and_its_gradient():
     say(f"  loss gpu {loss.item():.6f} ref {L.item():.6f}; actions rel {ea:.2e}")
     assert abs(loss.item() - L.item()) <= 1e-4 * abs(L.item())
     assert ea <= 2e-3
+
+
+def test_gas_box_grid_one_scalar_vs_oracle():
+    """A non-cubic box (24 x 16 x 32 cells: its multigrid stops at an odd
+    3 x 2 x 4 level) with one scalar, against the oracle."""
+    sc = scenes.gas_room(n=(24, 16, 32), steps=4, seed=5, n_scalars=1, translate=True)
+    say("gas 24x16x32, one scalar, 4 steps")
+    sim = gas_sim(sc)
+    sim.step(4)
+    compare(sim.state_numpy(), G.rollout_scene(sc, steps=4))
+
+
+def test_gas_four_scalars_no_emitter_long_backtraces_vs_oracle():
+    """Four scalars, the emitter switched off (kappa = 0), no buoyancy, and a
+    step long enough that back-traces cross several cells (and leave the
+    grid near the walls)."""
+    sc = scenes.gas_room(n=16, steps=3, seed=6, n_scalars=4, velocity=3.0, dt=0.05, emit_kappa=0.0, buoyancy=0.0)
+    say("gas 16^3, 4 scalars, kappa 0, CFL > 1")
+    u = np.abs(sc.u).max()
+    say(f"  max |u| dt / h = {u * sc.dt / sc.h:.2f}")
+    sim = gas_sim(sc)
+    sim.step(3)
+    compare(sim.state_numpy(), G.rollout_scene(sc, steps=3))
+
+
+def test_gas_nonfinite_is_reported():
+    """A NaN temperature spreads through buoyancy; the step reports it as
+    MPM_EDOMAIN with the non-finite bit (nothing is clamped or hidden)."""
+    from paper_2303_02346_amd import _lib
+    sc = scenes.gas_room(n=16, steps=2, seed=7)
+    sc.s[0, 8, 8, 8] = np.nan
+    sim = gas_sim(sc)
+    with pytest.raises(_lib.MpmError) as e:
+        sim.step(1)
+    assert e.value.status == _lib.MPM_EDOMAIN and (e.value.bits & MPM_ERR_NONFINITE) != 0
