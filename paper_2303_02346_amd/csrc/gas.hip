@@ -45,6 +45,21 @@ constexpr int MAX_LEVELS = 12;
 #define GAS_COARSE_SWEEPS 4
 #endif
 constexpr int COARSE_SWEEPS = GAS_COARSE_SWEEPS;
+#ifndef GAS_NU0_PRE
+#define GAS_NU0_PRE 2
+#endif
+#ifndef GAS_NU0_POST
+#define GAS_NU0_POST 1
+#endif
+#ifndef GAS_NU_POST
+#define GAS_NU_POST 2
+#endif
+#ifndef GAS_NU_BOTTOM
+#define GAS_NU_BOTTOM 2
+#endif
+// sweeps before / after the coarse correction on the finest level, after it
+// on the coarser grid levels, and before and after it inside the bottom solve
+constexpr int NU0_PRE = GAS_NU0_PRE, NU0_POST = GAS_NU0_POST, NU_POST = GAS_NU_POST, NU_BOTTOM = GAS_NU_BOTTOM;
 // smoother tiles: TX x TY x TZ cells per workgroup; psi staged with a 2-cell
 // halo, f with a 1-cell halo
 #ifndef GAS_TILE_X
@@ -116,6 +131,13 @@ __device__ inline Lerp lerp_setup(const GP& P, int q, const float* x) {
 
 __device__ inline size_t gidx(int i, int j, int k, int d1, int d2) { return ((size_t)i * d1 + j) * d2 + k; }
 
+__device__ inline void cell_of(const Dims& D, size_t g, int& i, int& j, int& k) {
+  const uint32_t g32 = (uint32_t)g, r = g32 / (uint32_t)D.z;
+  k = (int)(g32 - r * (uint32_t)D.z);
+  i = (int)(r / (uint32_t)D.y);
+  j = (int)(r - (uint32_t)i * (uint32_t)D.y);
+}
+
 // the 8 corner values
 __device__ inline void lerp_load(const float* __restrict__ F, const Lerp& L, int d1, int d2, float* c) {
 #pragma unroll
@@ -160,10 +182,11 @@ __device__ inline float sample(const GP& P, int q, const float* F, const float* 
 __device__ inline void point_of(const GP& P, int q, size_t g, int& i, int& j, int& k, float* x) {
   int d0, d1, d2;
   gdims(P, q, d0, d1, d2);
-  k = (int)(g % d2);
-  const size_t r = g / d2;
-  j = (int)(r % d1);
-  i = (int)(r / d1);
+  // (every grid has fewer than 2^32 points: 32-bit divisions)
+  const uint32_t g32 = (uint32_t)g, r = g32 / (uint32_t)d2;
+  k = (int)(g32 - r * (uint32_t)d2);
+  i = (int)(r / (uint32_t)d1);
+  j = (int)(r - (uint32_t)i * (uint32_t)d1);
   x[0] = ((float)i + gorigin(q, 0)) * P.h;
   x[1] = ((float)j + gorigin(q, 1)) * P.h;
   x[2] = ((float)k + gorigin(q, 2)) * P.h;
@@ -244,7 +267,8 @@ __global__ __launch_bounds__(256) void k_gas_div(GP P, const float* __restrict__
                                                  const float* __restrict__ w1, const float* __restrict__ T1,
                                                  float* __restrict__ f, float* __restrict__ psi) {
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < P.nc; g += (size_t)gridDim.x * blockDim.x) {
-    const int k = (int)(g % P.nz), j = (int)((g / P.nz) % P.ny), i = (int)(g / ((size_t)P.nz * P.ny));
+    int i, j, k;
+    cell_of(Dims{P.nx, P.ny, P.nz}, g, i, j, k);
     const float ur = (i + 1 < P.nx) ? u1[gidx(i + 1, j, k, P.ny, P.nz)] : 0.f;
     const float ul = (i > 0) ? u1[gidx(i, j, k, P.ny, P.nz)] : 0.f;
     const float vt = (j + 1 < P.ny) ? buoyant_v(P, v1, T1, i, j + 1, k) : 0.f;
@@ -298,11 +322,6 @@ __global__ __launch_bounds__(256) void k_gas_final(GP P, const float* __restrict
 // children's residuals (the coarse operator is A again at twice the
 // spacing), cell-centred trilinear prolongation.
 // ---------------------------------------------------------------------------
-__device__ inline void cell_of(const Dims& D, size_t g, int& i, int& j, int& k) {
-  k = (int)(g % D.z);
-  j = (int)((g / D.z) % D.y);
-  i = (int)(g / ((size_t)D.z * D.y));
-}
 
 // sum of the in-domain neighbours and their number
 __device__ inline float nb_sum(const float* psi, const Dims& D, int i, int j, int k, int& cnt) {
@@ -492,7 +511,7 @@ __global__ __launch_bounds__(BOTTOM_THREADS) void k_bottom(BottomArgs B) {
   };
   const int L = B.n_levels;
   for (int l = 0; l + 1 < L; l++) {
-    sweep(l, 0); sweep(l, 1); sweep(l, 0); sweep(l, 1);
+    for (int sw = 0; sw < NU_BOTTOM; sw++) { sweep(l, 0); sweep(l, 1); }
     const Dims Df = B.D[l], Dc = B.D[l + 1];
     for (int c = tid; c < (int)Dc.cells(); c += NT) {
       const int e = s_ijk[off[l + 1] + c];
@@ -514,7 +533,7 @@ __global__ __launch_bounds__(BOTTOM_THREADS) void k_bottom(BottomArgs B) {
       s_psi[off[l] + c] += prolong_at(s_psi + off[l + 1], Dc, i, j, k);
     }
     __syncthreads();
-    sweep(l, 1); sweep(l, 0); sweep(l, 1); sweep(l, 0);
+    for (int sw = 0; sw < NU_BOTTOM; sw++) { sweep(l, 1); sweep(l, 0); }
   }
   for (int c = tid; c < n0; c += NT) B.psi[c] = s_psi[c];
 }
@@ -557,7 +576,8 @@ __global__ __launch_bounds__(256) void k_gas_adj_div(GP P, const float* __restri
                                                      const float* __restrict__ wb, float* __restrict__ f,
                                                      float* __restrict__ psi) {
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < P.nc; g += (size_t)gridDim.x * blockDim.x) {
-    const int k = (int)(g % P.nz), j = (int)((g / P.nz) % P.ny), i = (int)(g / ((size_t)P.nz * P.ny));
+    int i, j, k;
+    cell_of(Dims{P.nx, P.ny, P.nz}, g, i, j, k);
     const float ur = (i + 1 < P.nx) ? ub[gidx(i + 1, j, k, P.ny, P.nz)] : 0.f;
     const float ul = (i > 0) ? ub[gidx(i, j, k, P.ny, P.nz)] : 0.f;
     const float vt = (j + 1 < P.ny) ? vb[gidx(i, j + 1, k, P.ny + 1, P.nz)] : 0.f;
@@ -898,7 +918,7 @@ void mg_solve(gas_ctx* c, float* psi0, float* f0) {
   // each correction (the first of them adds the correction as it stages)
   for (int cyc = 0; cyc < c->d.mg_cycles; cyc++) {
     for (int l = 0; l < G; l++) {
-      for (int sw = 0; sw < 2; sw++) {
+      for (int sw = 0; sw < (l == 0 ? NU0_PRE : 2); sw++) {
         if (l == 0) c->t_smooth.begin(s);
         k_rb_sweep<<<tiles(l), 256, 0, s>>>(psi(l), fl(l), L.D[l], 0, nullptr, L.D[l]);
         if (l == 0) c->t_smooth.end(s);
@@ -907,7 +927,7 @@ void mg_solve(gas_ctx* c, float* psi0, float* f0) {
     }
     k_bottom<<<1, BOTTOM_THREADS, 0, s>>>(B);
     for (int l = G - 1; l >= 0; l--) {
-      for (int sw = 0; sw < 2; sw++) {
+      for (int sw = 0; sw < (l == 0 ? NU0_POST : NU_POST); sw++) {
         if (l == 0) c->t_smooth.begin(s);
         k_rb_sweep<<<tiles(l), 256, 0, s>>>(psi(l), fl(l), L.D[l], 1, sw == 0 ? psi(l + 1) : nullptr, L.D[l + 1]);
         if (l == 0) c->t_smooth.end(s);
