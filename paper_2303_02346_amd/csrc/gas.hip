@@ -640,7 +640,7 @@ __global__ __launch_bounds__(256) void k_gas_adj_advect(GP P, VelPtrs vel, const
                                                         const float* __restrict__ ub1, const float* __restrict__ vb1,
                                                         const float* __restrict__ wb1, const float* __restrict__ sb,
                                                         AdjOut out, const double* __restrict__ pose,
-                                                        double* __restrict__ slots) {
+                                                        double* __restrict__ slots, float* __restrict__ ub) {
   const size_t total = P.nu + P.nv + P.nw + P.nc;
   const Pose E = load_pose(pose);
   double part[POSE_PARTIALS] = {0, 0, 0, 0, 0, 0};
@@ -707,18 +707,10 @@ __global__ __launch_bounds__(256) void k_gas_adj_advect(GP P, VelPtrs vel, const
         for (int a = 0; a < 3; a++) xbb[a] += L.cl[a] ? 0.f : sbar * gr[a] * P.inv_h;
       }
     }
-    // back-trace xb = x - dt U(x): U's adjoint is -dt xbb, spread over the
-    // velocity grids at the grid point x
-    if (xbb[0] != 0.f || xbb[1] != 0.f || xbb[2] != 0.f) {
+    // back-trace xb = x - dt U(x): U's adjoint -dt xbb is kept per point;
+    // k_gas_adj_ugather spreads it over the velocity grids
 #pragma unroll
-      for (int a = 0; a < 3; a++) {
-        int d0, d1, d2;
-        gdims(P, a, d0, d1, d2);
-        const Lerp L = lerp_setup(P, a, x);
-        float* O = a == 0 ? out.u : (a == 1 ? out.v : out.w);
-        scatter_lerp(O, L, d1, d2, -P.dt * xbb[a]);
-      }
-    }
+    for (int a = 0; a < 3; a++) ub[(size_t)a * total + g0] = -P.dt * xbb[a];
   }
   // pose partials: wave sums, one FP64 atomic per component into the
   // wavefront's accumulator copy
@@ -730,6 +722,55 @@ __global__ __launch_bounds__(256) void k_gas_adj_advect(GP P, VelPtrs vel, const
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if (__lane_id() == 0 && v != 0.0) atomicAdd(dst + qn, v);
+  }
+}
+
+// Adjoint of the velocity sampled at every grid point (U(x) of the
+// back-traces) as a gather: each velocity-grid node sums, over the grid
+// points whose trilinear sample of its grid touches it, the weight times the
+// point's U adjoint (ub, from k_gas_adj_advect).  A point of grid q touches
+// node n of grid a only from index n on an axis where q and a share their
+// staggering and from n - 1 .. n + 1 where they differ; the weights are those
+// of the same sampling routine as the forward.
+__global__ __launch_bounds__(256) void k_gas_adj_ugather(GP P, const float* __restrict__ ub, AdjOut out) {
+  const size_t total = P.nu + P.nv + P.nw + P.nc;
+  const size_t nvel = P.nu + P.nv + P.nw;
+  for (size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g0 < nvel; g0 += (size_t)gridDim.x * blockDim.x) {
+    size_t g = g0;
+    const int a = split_points(P, g);
+    int n[3];
+    float xn[3];
+    point_of(P, a, g, n[0], n[1], n[2], xn);
+    const float* U = ub + (size_t)a * total;
+    float acc = 0.f;
+    size_t qoff = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      int dq[3];
+      gdims(P, q, dq[0], dq[1], dq[2]);
+      int lo[3], hi[3];
+#pragma unroll
+      for (int e = 0; e < 3; e++) {
+        const bool same = gorigin(q, e) == gorigin(a, e);
+        lo[e] = same ? n[e] : max(n[e] - 1, 0);
+        hi[e] = same ? n[e] : min(n[e] + 1, dq[e] - 1);
+      }
+      for (int pi = lo[0]; pi <= hi[0]; pi++)
+        for (int pj = lo[1]; pj <= hi[1]; pj++)
+          for (int pk = lo[2]; pk <= hi[2]; pk++) {
+            const float xp[3] = {((float)pi + gorigin(q, 0)) * P.h, ((float)pj + gorigin(q, 1)) * P.h,
+                                 ((float)pk + gorigin(q, 2)) * P.h};
+            const Lerp L = lerp_setup(P, a, xp);
+            const int b[3] = {L.i0, L.j0, L.k0};
+            float w = 1.f;
+#pragma unroll
+            for (int e = 0; e < 3; e++) w *= (n[e] == b[e]) ? 1.f - L.f[e] : ((n[e] == b[e] + 1) ? L.f[e] : 0.f);
+            if (w != 0.f) acc += w * U[qoff + gidx(pi, pj, pk, dq[1], dq[2])];
+          }
+      qoff += (size_t)dq[0] * dq[1] * dq[2];
+    }
+    float* O = a == 0 ? out.u : (a == 1 ? out.v : out.w);
+    O[g] += acc;
   }
 }
 
@@ -780,7 +821,7 @@ __global__ __launch_bounds__(256) void k_gas_sensors(const float* __restrict__ T
 // host side
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t tmp, pose, act, acc, slots, resp, resout, err, ckpt, seg, adj0, adj1;
+  size_t tmp, pose, act, acc, slots, resp, resout, err, ckpt, seg, adj0, adj1, ub;
   size_t psi[MAX_LEVELS], f[MAX_LEVELS];
   size_t total;
   size_t state_floats;
@@ -840,9 +881,10 @@ Layout plan(const gas_desc* d) {
     L.seg = take(al256(L.state_floats * 4) * (size_t)k);
     L.adj0 = take(L.state_floats * 4);
     L.adj1 = take(L.state_floats * 4);
+    L.ub = take(3 * (nc + (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)) * 4);
   } else {
     L.n_ckpt = 0;
-    L.acc = L.ckpt = L.seg = L.adj0 = L.adj1 = 0;
+    L.acc = L.ckpt = L.seg = L.adj0 = L.adj1 = L.ub = 0;
   }
   L.total = o;
   return L;
@@ -974,7 +1016,9 @@ void gas_adjoint_step(gas_ctx* c, const gas_state& st, const gas_state& an, cons
   const size_t pts = P.nu + P.nv + P.nw + P.nc;
   k_gas_adj_advect<<<nblk(pts, 256), 256, 0, s>>>(P, VelPtrs{st.u, st.v, st.w}, st.s, tmp.u, tmp.v, tmp.w, an.s,
                                                  AdjOut{ab.u, ab.v, ab.w, ab.s}, pose_at(c, t),
-                                                 (double*)(c->ws + c->L.slots));
+                                                 (double*)(c->ws + c->L.slots), (float*)(c->ws + c->L.ub));
+  k_gas_adj_ugather<<<nblk(P.nu + P.nv + P.nw, 256), 256, 0, s>>>(P, (const float*)(c->ws + c->L.ub),
+                                                                  AdjOut{ab.u, ab.v, ab.w, ab.s});
   k_gas_pose_acc<<<1, 64, 0, s>>>((double*)(c->ws + c->L.slots), acc_t);
 }
 
