@@ -166,3 +166,21 @@ def test_gas_nonfinite_is_reported():
     with pytest.raises(_lib.MpmError) as e:
         sim.step(1)
     assert e.value.status == _lib.MPM_EDOMAIN and (e.value.bits & MPM_ERR_NONFINITE) != 0
+
+
+def test_gas_rollout_autograd_function_matches_direct_backward():
+    """GasRollout (torch.autograd.Function over gas_step / gas_step_backward)
+    gives the direct backward's action gradient."""
+    from paper_2303_02346_amd.gas import GasRollout
+    sc = scenes.gas_room(n=16, steps=4, seed=8, translate=True)
+    sim = gas_sim(sc, requires_grad=True, ckpt_every=2)
+    w = _seeds(sim, 31).to(sim.device)
+    acts = torch.tensor(sc.actions, dtype=torch.float32, device=sim.device, requires_grad=True)
+    out = GasRollout.apply(acts, sim)
+    (out * w).sum().backward()
+    sim.reset()
+    sim.step(4)
+    ga = sim.backward(w)
+    e = rel(acts.grad.double().cpu().numpy(), ga.double().cpu().numpy())
+    say(f"  autograd vs direct backward rel {e:.2e}")
+    assert e <= 1e-6
