@@ -39,7 +39,7 @@ KERNEL_BYTES = {
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_g2p2g_config2_traffic.md")
 TRAFFIC_SOURCES = ["mpm_fast.hip", "mpm_fast.h", "mpm_blocks.h", "mpm_phys.h", "mpm_math.h", "mpm_internal.h"]
-GAS_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_rb_sweep_gas128_traffic.md")
+GAS_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_rb_half_gas128_traffic.md")
 GAS_TRAFFIC_SOURCES = ["gas.hip"]
 
 
@@ -251,8 +251,8 @@ def bench_gas(torch, n=128, steps=20, bwd_steps=8):
     """The gas solver (section 3.2's advection-projection) on the 128^3
     grid of the air-circulation task: forward steps, forward+backward, and
     the roofline of the finest-level smoother (the dominant kernel: one
-    launch is a full red-black sweep, which reads f and psi and writes psi
-    once per cell, 12 B per cell)."""
+    launch is a red-black half-sweep, which reads f and writes psi for the
+    cells of one colour and reads psi of the other, 6 B per cell)."""
     from paper_2303_02346_amd import scenes
     from paper_2303_02346_amd.gas import GasSim
     sc = scenes.gas_room(n=n, steps=max(steps, bwd_steps) + 2, seed=0)
@@ -285,14 +285,14 @@ def bench_gas(torch, n=128, steps=20, bwd_steps=8):
         t_fb = time.perf_counter() - t0
     simg.close()
     sm_avg = sm_ms / max(sm_n, 1) * 1e-3
-    sm_bytes = 12.0 * cells
+    sm_bytes = 6.0 * cells
     ach = sm_bytes / sm_avg / 1e9 if sm_n else None
     out = {"workload": f"gas room {n}^3 (velocity + temperature + smoke), emitter turning about y, dt=5e-3",
            "cells": cells, "steps": steps, "ms_per_step": t * 1e3 / steps, "cell_steps_per_s": cells * steps / t,
            "fwd_bwd_steps": bwd_steps, "fwd_bwd_ms_per_step": t_fb * 1e3 / bwd_steps,
            "mg_cycles": 6, "pressure_rel_residual": res,
            "advect_avg_us": adv_ms / max(adv_n, 1) * 1e3,
-           "roofline": {"bound": "hbm", "kernel": "k_rb_sweep (finest level)", "achieved": round(ach, 1) if ach else None,
+           "roofline": {"bound": "hbm", "kernel": "k_rb_half (finest level)", "achieved": round(ach, 1) if ach else None,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None,
                         "avg_us": round(sm_avg * 1e6, 2), "algorithmic_bytes_per_launch": int(sm_bytes),
                         "traffic": counted_traffic(GAS_TRAFFIC_SUMMARY, GAS_TRAFFIC_SOURCES) if n == 128 else None}}

@@ -9,7 +9,10 @@
 //                  buoyancy of the y-faces added on the fly and the walls
 //                  closed; right-hand side of the pressure equation
 //   mg_solve       multigrid V-cycles for A psi = div (A: 7-point Neumann
-//                  Laplacian in cell units; psi = pressure * dt / h)
+//                  Laplacian in cell units; psi = pressure * dt / h):
+//                  red-black half-sweeps on the finest level, tiled full
+//                  sweeps on the coarser grid levels, the levels of at most
+//                  4096 cells in one workgroup
 //   k_gas_final    u = u* - grad psi on the interior faces, walls zero,
 //                  scalars copied
 // Adjoint step: the projection of the adjoint (k_gas_adj_div, mg_solve,
@@ -45,6 +48,10 @@ constexpr int MAX_LEVELS = 12;
 #define GAS_COARSE_SWEEPS 4
 #endif
 constexpr int COARSE_SWEEPS = GAS_COARSE_SWEEPS;
+#ifndef GAS_HALF_LEVELS
+#define GAS_HALF_LEVELS 1
+#endif
+constexpr int HALF_LEVELS = GAS_HALF_LEVELS;   // finest levels smoothed by separate half-sweeps
 #ifndef GAS_NU0_PRE
 #define GAS_NU0_PRE 2
 #endif
@@ -337,6 +344,11 @@ __device__ inline float nb_sum(const float* psi, const Dims& D, int i, int j, in
   return s;
 }
 
+// 1 / cnt for a neighbour count of 1..6 (a division would cost a long sequence)
+__device__ inline float inv_count(int cnt) {
+  return cnt == 6 ? (1.f / 6.f) : (cnt == 5 ? 0.2f : (cnt == 4 ? 0.25f : (cnt == 3 ? (1.f / 3.f) : (cnt == 2 ? 0.5f : 1.f))));
+}
+
 __device__ inline bool inside(const Dims& D, int i, int j, int k) {
   return i >= 0 && j >= 0 && k >= 0 && i < D.x && j < D.y && k < D.z;
 }
@@ -403,9 +415,7 @@ __global__ __launch_bounds__(256) void k_rb_sweep(float* __restrict__ psi, const
     if (j + 1 < D.y) { s += sP[pq + PZ]; cnt++; }
     if (k > 0) { s += sP[pq - 1]; cnt++; }
     if (k + 1 < D.z) { s += sP[pq + 1]; cnt++; }
-    // 1 / cnt for cnt in 1..6 (a division would cost a long sequence)
-    const float inv = cnt == 6 ? (1.f / 6.f) : (cnt == 5 ? 0.2f : (cnt == 4 ? 0.25f : (cnt == 3 ? (1.f / 3.f) : (cnt == 2 ? 0.5f : 1.f))));
-    sP[pq] = (s - sF[fq]) * inv;
+    sP[pq] = (s - sF[fq]) * inv_count(cnt);
   };
   for (int q = tid; q < FX * FY * FZ; q += 256) {
     const int a = q / (FY * FZ), b = (q / FZ) % FY, c = q % FZ;
@@ -432,6 +442,33 @@ __device__ inline float residual_at(const float* psi, const float* f, const Dims
   const float s = nb_sum(psi, D, i, j, k, cnt);
   const size_t c = gidx(i, j, k, D.y, D.z);
   return f[c] - (s - (float)cnt * psi[c]);
+}
+
+// One red-black half-sweep (the cells of one colour), one thread per pair of
+// z-neighbours (one cell of each colour), for the finest levels.
+__global__ __launch_bounds__(256) void k_rb_half(float* __restrict__ psi, const float* __restrict__ f, Dims D,
+                                                 int color) {
+  const uint32_t nzp = (uint32_t)D.z >> 1;
+  const uint32_t n = (uint32_t)D.x * (uint32_t)D.y * nzp;
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+    const uint32_t r = g / nzp, kp = g - r * nzp;
+    const int i = (int)(r / (uint32_t)D.y), j = (int)(r - (uint32_t)i * (uint32_t)D.y);
+    const int k = 2 * (int)kp + ((color + i + j) & 1);
+    int cnt;
+    const float sn = nb_sum(psi, D, i, j, k, cnt);
+    const size_t c = gidx(i, j, k, D.y, D.z);
+    psi[c] = (sn - f[c]) * inv_count(cnt);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_prolong(const float* __restrict__ psi_c, Dims Dc, float* __restrict__ psi,
+                                                 Dims Df) {
+  const size_t n = Df.cells();
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n; g += (size_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_of(Df, g, i, j, k);
+    psi[g] += prolong_at(psi_c, Dc, i, j, k);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_restrict(const float* __restrict__ psi, const float* __restrict__ f, Dims Df,
@@ -961,6 +998,14 @@ void mg_solve(gas_ctx* c, float* psi0, float* f0) {
   for (int cyc = 0; cyc < c->d.mg_cycles; cyc++) {
     for (int l = 0; l < G; l++) {
       for (int sw = 0; sw < (l == 0 ? NU0_PRE : 2); sw++) {
+        if (l < HALF_LEVELS) {
+          for (int color = 0; color < 2; color++) {
+            if (l == 0) c->t_smooth.begin(s);
+            k_rb_half<<<nblk(L.D[l].cells() / 2, 256), 256, 0, s>>>(psi(l), fl(l), L.D[l], color);
+            if (l == 0) c->t_smooth.end(s);
+          }
+          continue;
+        }
         if (l == 0) c->t_smooth.begin(s);
         k_rb_sweep<<<tiles(l), 256, 0, s>>>(psi(l), fl(l), L.D[l], 0, nullptr, L.D[l]);
         if (l == 0) c->t_smooth.end(s);
@@ -969,7 +1014,17 @@ void mg_solve(gas_ctx* c, float* psi0, float* f0) {
     }
     k_bottom<<<1, BOTTOM_THREADS, 0, s>>>(B);
     for (int l = G - 1; l >= 0; l--) {
+      if (l < HALF_LEVELS)
+        k_prolong<<<nblk(L.D[l].cells(), 256), 256, 0, s>>>(psi(l + 1), L.D[l + 1], psi(l), L.D[l]);
       for (int sw = 0; sw < (l == 0 ? NU0_POST : NU_POST); sw++) {
+        if (l < HALF_LEVELS) {
+          for (int color = 1; color >= 0; color--) {
+            if (l == 0) c->t_smooth.begin(s);
+            k_rb_half<<<nblk(L.D[l].cells() / 2, 256), 256, 0, s>>>(psi(l), fl(l), L.D[l], color);
+            if (l == 0) c->t_smooth.end(s);
+          }
+          continue;
+        }
         if (l == 0) c->t_smooth.begin(s);
         k_rb_sweep<<<tiles(l), 256, 0, s>>>(psi(l), fl(l), L.D[l], 1, sw == 0 ? psi(l + 1) : nullptr, L.D[l + 1]);
         if (l == 0) c->t_smooth.end(s);
@@ -1074,7 +1129,7 @@ int gas_create(const gas_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   c->last_res = 0.0;
   c->last_err_bits = 0;
   c->t_adv.name = "k_gas_advect";
-  c->t_smooth.name = "k_rb_sweep";
+  c->t_smooth.name = "k_rb_half";
   c->act_set.assign(d->horizon, 0);
   GP& P = c->P;
   P.nx = d->nx; P.ny = d->ny; P.nz = d->nz; P.K = d->n_scalars;
