@@ -19,7 +19,8 @@
  *      0) averaged over the two cells the face separates;
  *   4. closed walls: zero normal velocity on the domain's boundary faces;
  *   5. the exact projection onto divergence-free fields (pressure Poisson
- *      equation with Neumann walls, solved by multigrid V-cycles).
+ *      equation with Neumann walls, solved spectrally by DCT-II transforms
+ *      along the three axes, or by multigrid V-cycles).
  * The emitter pose follows the 6-vector action of section 4.2 like the MPM
  * manipulator: c_{t+1} = c_t + dt u_t, R_{t+1} = exp(dt [w_t]x) R_t.
  *
@@ -49,8 +50,9 @@ extern "C" {
 typedef struct gas_ctx gas_ctx;
 
 typedef struct {
-  int32_t nx, ny, nz;        /* cells per axis: multiples of 4 in [8, 1024], such that halving
-                                while every axis is even reaches at most 4096 cells */
+  int32_t nx, ny, nz;        /* cells per axis: multiples of 4 in [8, 1024]; for the multigrid
+                                solver, halving while every axis is even must reach at most
+                                4096 cells */
   float h;                   /* cell size */
   float dt;
   float buoyancy, t_amb;     /* beta and the ambient temperature */
@@ -62,7 +64,10 @@ typedef struct {
   int32_t ckpt_every;        /* checkpoint period for the backward */
   int32_t requires_grad;     /* record checkpoints during gas_step */
   int32_t mg_cycles;         /* multigrid V-cycles per pressure solve (1..64; 6 reach the FP32
-                                residual floor, about 2e-5, on 128^3) */
+                                residual floor, about 3e-5, on 128^3) */
+  int32_t pressure_solver;   /* 0: spectral (exact: DCT-II axis transforms diagonalise the
+                                Neumann Laplacian of the closed box; default);
+                                1: multigrid V-cycles */
 } gas_desc;
 
 typedef struct {

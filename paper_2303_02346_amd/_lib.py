@@ -44,7 +44,8 @@ class GasDesc(ctypes.Structure):
                 ("n_scalars", ctypes.c_int32), ("src", ctypes.POINTER(ctypes.c_float)),
                 ("emit_sigma", ctypes.c_float), ("emit_kappa", ctypes.c_float), ("emit_speed", ctypes.c_float),
                 ("emit_pos0", ctypes.c_float * 3), ("emit_rot0", ctypes.c_float * 9), ("horizon", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("requires_grad", ctypes.c_int32), ("mg_cycles", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("requires_grad", ctypes.c_int32), ("mg_cycles", ctypes.c_int32),
+                ("pressure_solver", ctypes.c_int32)]
 
 
 class GasState(ctypes.Structure):

@@ -575,6 +575,115 @@ __global__ __launch_bounds__(BOTTOM_THREADS) void k_bottom(BottomArgs B) {
   for (int c = tid; c < n0; c += NT) B.psi[c] = s_psi[c];
 }
 
+// ---------------------------------------------------------------------------
+// Spectral pressure solve.  With closed walls on a box of uniform cells the
+// 7-point Neumann Laplacian is the Kronecker sum of 1-D Neumann Laplacians,
+// each diagonalised by the DCT-II basis cos(pi k (i + 1/2) / n) with
+// eigenvalues -4 sin^2(pi k / 2n).  So A psi = f is solved exactly by three
+// axis transforms, a division by lambda_x + lambda_y + lambda_z (the
+// constant mode, lambda = 0, set to zero: the gauge), and three inverse
+// transforms.  Each axis transform is a dense contraction with an n x n
+// matrix: out[k] = sum_i M[i][k] in[i] along the axis.
+// ---------------------------------------------------------------------------
+constexpr int XB = 64, XI = 64, XK = 128;    // lines per workgroup, input / output chunk along the axis
+static_assert(XK * XB <= XI * (XK + 1), "the output tile reuses the matrix chunk's LDS");
+
+struct AxisArgs {
+  const float* in;
+  float* out;
+  const float* M;        // n x n, row = input index
+  int n;                 // length of the transformed axis
+  int A, B;              // layout [A][n][B]; inner transform (B == 1): A lines of n contiguous values
+  // optional division by the 3-D eigenvalue (the last forward pass, along x):
+  // out index k = kx, line index b = ky * nz + kz
+  const float* lx;
+  const float* ly;
+  const float* lz;
+  int nz;
+};
+
+template <bool INNER>
+__global__ __launch_bounds__(256) void k_axis(AxisArgs X) {
+  __shared__ float sS[XI][XB + 1];       // input chunk, [i][line]
+  __shared__ float sM[XI][XK + 1];       // matrix chunk, [i][k]; reused for the output tile [k][line]
+  float* sO = &sM[0][0];                 // output tile: k * XB + line (49.7 KB of LDS in all)
+  const int tid = threadIdx.x;
+  const int tb = tid >> 4, tk = tid & 15;   // 4 lines x 8 outputs per thread
+  const int n = X.n;
+  const int a = INNER ? 0 : (int)blockIdx.y;
+  const int line0 = blockIdx.x * XB;        // first line (INNER: row; OUTER: b)
+  const int nlines = INNER ? X.A : X.B;
+  for (int k0 = 0; k0 < n; k0 += XK) {
+    float acc[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int m = 0; m < 8; m++) acc[u][m] = 0.f;
+    for (int i0 = 0; i0 < n; i0 += XI) {
+      __syncthreads();
+      // stage the input chunk (coalesced along the contiguous index)
+      if (INNER) {
+        for (int q = tid; q < XB * XI; q += 256) {
+          const int b = q / XI, i = q % XI;
+          const int line = line0 + b, ii = i0 + i;
+          sS[i][b] = (line < nlines && ii < n) ? X.in[(size_t)line * n + ii] : 0.f;
+        }
+      } else {
+        for (int q = tid; q < XB * XI; q += 256) {
+          const int i = q / XB, b = q % XB;
+          const int line = line0 + b, ii = i0 + i;
+          sS[i][b] = (line < nlines && ii < n) ? X.in[((size_t)a * n + ii) * X.B + line] : 0.f;
+        }
+      }
+      for (int q = tid; q < XI * XK; q += 256) {
+        const int i = q / XK, k = q % XK;
+        const int ii = i0 + i, kk = k0 + k;
+        sM[i][k] = (ii < n && kk < n) ? X.M[(size_t)ii * n + kk] : 0.f;
+      }
+      __syncthreads();
+      for (int i = 0; i < XI; i++) {
+        float sv[4], mv[8];
+#pragma unroll
+        for (int u = 0; u < 4; u++) sv[u] = sS[i][tb * 4 + u];
+#pragma unroll
+        for (int m = 0; m < 8; m++) mv[m] = sM[i][tk + 16 * m];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+          for (int m = 0; m < 8; m++) acc[u][m] += sv[u] * mv[m];
+      }
+    }
+    __syncthreads();
+    // output tile through LDS ([k][line] in sM), then coalesced stores
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int m = 0; m < 8; m++) sO[(tk + 16 * m) * XB + tb * 4 + u] = acc[u][m];
+    __syncthreads();
+    if (INNER) {
+      for (int q = tid; q < XB * XK; q += 256) {
+        const int b = q / XK, k = q % XK;
+        const int line = line0 + b, kk = k0 + k;
+        if (line < nlines && kk < n) X.out[(size_t)line * n + kk] = sO[k * XB + b];
+      }
+    } else {
+      for (int q = tid; q < XB * XK; q += 256) {
+        const int k = q / XB, b = q % XB;
+        const int line = line0 + b, kk = k0 + k;
+        if (line < nlines && kk < n) {
+          float v = sO[k * XB + b];
+          if (X.lx) {
+            const int ky = line / X.nz, kz = line - ky * X.nz;
+            const float lam = X.lx[kk] + X.ly[ky] + X.lz[kz];
+            v = lam != 0.f ? v / lam : 0.f;
+          }
+          X.out[((size_t)a * n + kk) * X.B + line] = v;
+        }
+      }
+    }
+  }
+}
+
 // |f - A psi|^2 and |f|^2 per block into part[2 * block]; the last step sums
 __global__ __launch_bounds__(256) void k_resnorm(const float* __restrict__ psi, const float* __restrict__ f, Dims D,
                                                  double* __restrict__ part) {
@@ -859,6 +968,7 @@ __global__ __launch_bounds__(256) void k_gas_sensors(const float* __restrict__ T
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t tmp, pose, act, acc, slots, resp, resout, err, ckpt, seg, adj0, adj1, ub;
+  size_t spec_tmp, dct[3], idct[3], lam[3];   // spectral solve: a cell array, per-axis matrices and eigenvalues
   size_t psi[MAX_LEVELS], f[MAX_LEVELS];
   size_t total;
   size_t state_floats;
@@ -875,6 +985,7 @@ bool desc_ok(const gas_desc* d) {
   if (d->n_scalars < 1 || d->n_scalars > MAXK || !d->src) return false;
   if (!(d->emit_sigma > 0.f) || !(d->emit_kappa >= 0.f && d->emit_kappa <= 1.f)) return false;
   if (d->horizon < 1 || d->mg_cycles < 1 || d->mg_cycles > 64) return false;
+  if (d->pressure_solver != 0 && d->pressure_solver != 1) return false;
   if (d->requires_grad && (d->ckpt_every < 1 || d->ckpt_every > 4096)) return false;
   return true;
 }
@@ -903,6 +1014,15 @@ Layout plan(const gas_desc* d) {
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o += al256(b); return r; };
   L.tmp = take(L.state_floats * 4);
+  {
+    const int nn[3] = {d->nx, d->ny, d->nz};
+    L.spec_tmp = take(nc * 4);
+    for (int a = 0; a < 3; a++) {
+      L.dct[a] = take((size_t)nn[a] * nn[a] * 4);
+      L.idct[a] = take((size_t)nn[a] * nn[a] * 4);
+      L.lam[a] = take((size_t)nn[a] * 4);
+    }
+  }
   for (int l = 0; l < L.n_levels; l++) { L.psi[l] = take(L.D[l].cells() * 4); L.f[l] = take(L.D[l].cells() * 4); }
   L.pose = take((T + 1) * POSE_DOUBLES * sizeof(double));
   L.act = take(T * 6 * sizeof(float));
@@ -928,6 +1048,7 @@ Layout plan(const gas_desc* d) {
 }
 
 bool levels_ok(const gas_desc* d) {
+  if (d->pressure_solver == 0) return true;   // (the spectral solve has no hierarchy)
   const Layout L = plan(d);
   return L.n_grid_levels < L.n_levels;
 }
@@ -1038,6 +1159,57 @@ void mg_solve(gas_ctx* c, float* psi0, float* f0) {
   }
 }
 
+// A psi = f exactly by the axis transforms (psi0 receives the solution with
+// zero mean; f0 is left unchanged)
+void spectral_solve(gas_ctx* c, float* psi0, const float* f0) {
+  const GP& P = c->P;
+  hipStream_t s = c->stream;
+  float* T = (float*)(c->ws + c->L.spec_tmp);
+  const float* Mf[3] = {(const float*)(c->ws + c->L.dct[0]), (const float*)(c->ws + c->L.dct[1]),
+                        (const float*)(c->ws + c->L.dct[2])};
+  const float* Mi[3] = {(const float*)(c->ws + c->L.idct[0]), (const float*)(c->ws + c->L.idct[1]),
+                        (const float*)(c->ws + c->L.idct[2])};
+  const float* lam[3] = {(const float*)(c->ws + c->L.lam[0]), (const float*)(c->ws + c->L.lam[1]),
+                         (const float*)(c->ws + c->L.lam[2])};
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  auto pass = [&](int axis, const float* in, float* out, const float* M, bool divide) {
+    AxisArgs X = {};
+    X.in = in; X.out = out; X.M = M;
+    if (axis == 2) {
+      X.n = nz; X.A = nx * ny; X.B = 1;
+      k_axis<true><<<dim3((X.A + XB - 1) / XB, 1, 1), 256, 0, s>>>(X);
+      return;
+    }
+    X.n = axis == 0 ? nx : ny;
+    X.A = axis == 0 ? 1 : nx;
+    X.B = axis == 0 ? ny * nz : nz;
+    if (divide) { X.lx = lam[0]; X.ly = lam[1]; X.lz = lam[2]; X.nz = nz; }
+    k_axis<false><<<dim3((X.B + XB - 1) / XB, X.A, 1), 256, 0, s>>>(X);
+  };
+  c->t_smooth.begin(s);
+  pass(2, f0, T, Mf[2], false);
+  c->t_smooth.end(s);
+  pass(1, T, psi0, Mf[1], false);
+  pass(0, psi0, T, Mf[0], true);
+  pass(0, T, psi0, Mi[0], false);
+  pass(1, psi0, T, Mi[1], false);
+  pass(2, T, psi0, Mi[2], false);
+}
+
+void pressure_solve(gas_ctx* c, float* psi0, float* f0) {
+  if (c->d.pressure_solver != 0) {
+    mg_solve(c, psi0, f0);
+    return;
+  }
+  spectral_solve(c, psi0, f0);
+  if (c->stats) {
+    const Layout& L = c->L;
+    const unsigned nb = min(nblk(L.D[0].cells(), 256), 4096u);
+    k_resnorm<<<nb, 256, 0, c->stream>>>(psi0, f0, L.D[0], (double*)(c->ws + L.resp));
+    k_resnorm_final<<<1, 64, 0, c->stream>>>((const double*)(c->ws + L.resp), (int)nb, (double*)(c->ws + L.resout));
+  }
+}
+
 // one forward step from `in` to `out` (distinct), emitter at pose t
 void gas_forward_step(gas_ctx* c, const gas_state& in, const gas_state& out, int t) {
   const GP& P = c->P;
@@ -1051,7 +1223,7 @@ void gas_forward_step(gas_ctx* c, const gas_state& in, const gas_state& out, int
                                              pose_at(c, t));
   c->t_adv.end(s);
   k_gas_div<<<nblk(P.nc, 256), 256, 0, s>>>(P, tmp.u, tmp.v, tmp.w, tmp.s, f0, psi0);
-  mg_solve(c, psi0, f0);
+  pressure_solve(c, psi0, f0);
   const size_t tot = P.nu + P.nv + P.nw + (size_t)P.K * P.nc;
   k_gas_final<<<nblk(tot, 256), 256, 0, s>>>(P, tmp.u, tmp.v, tmp.w, tmp.s, psi0, out.u, out.v, out.w, out.s);
 }
@@ -1065,7 +1237,7 @@ void gas_adjoint_step(gas_ctx* c, const gas_state& st, const gas_state& an, cons
   float* psi0 = (float*)(c->ws + c->L.psi[0]);
   float* f0 = (float*)(c->ws + c->L.f[0]);
   k_gas_adj_div<<<nblk(P.nc, 256), 256, 0, s>>>(P, an.u, an.v, an.w, f0, psi0);
-  mg_solve(c, psi0, f0);
+  pressure_solve(c, psi0, f0);
   k_gas_adj_sub<<<nblk(P.nu + P.nv + P.nw, 256), 256, 0, s>>>(P, an.u, an.v, an.w, psi0, tmp.u, tmp.v, tmp.w);
   launch_zero(ab.u, c->L.state_floats * 4, s);
   const size_t pts = P.nu + P.nv + P.nw + P.nc;
@@ -1145,6 +1317,32 @@ int gas_create(const gas_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   P.err = (int*)(c->ws + L.err);
   launch_zero(c->ws + L.slots, SLOTS * POSE_PARTIALS * sizeof(double), c->stream);
   launch_zero(c->ws + L.err, 64, c->stream);
+  // spectral tables: per axis the DCT-II matrix C[i][k] = cos(pi k (i + 1/2) / n),
+  // its inverse Ci[k][i] = w_k C[i][k] (w_0 = 1/n, w_k = 2/n) and the 1-D
+  // Neumann eigenvalues -4 sin^2(pi k / 2n), computed in FP64
+  {
+    const int nn[3] = {d->nx, d->ny, d->nz};
+    for (int a = 0; a < 3; a++) {
+      const int n = nn[a];
+      std::vector<float> C((size_t)n * n), Ci((size_t)n * n), lam(n);
+      for (int i = 0; i < n; i++)
+        for (int k = 0; k < n; k++) {
+          const double v = cos(M_PI * k * (i + 0.5) / n);
+          C[(size_t)i * n + k] = (float)v;
+          Ci[(size_t)k * n + i] = (float)(v * (k == 0 ? 1.0 / n : 2.0 / n));
+        }
+      for (int k = 0; k < n; k++) {
+        const double sk = sin(M_PI * k / (2.0 * n));
+        lam[k] = (float)(-4.0 * sk * sk);
+      }
+      if (hipMemcpy(c->ws + L.dct[a], C.data(), C.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->ws + L.idct[a], Ci.data(), Ci.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->ws + L.lam[a], lam.data(), lam.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        delete c;
+        return MPM_EHIP;
+      }
+    }
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) { delete c; return MPM_EHIP; }
   *out = c;
   return MPM_OK;

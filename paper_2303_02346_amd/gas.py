@@ -24,7 +24,8 @@ class GasSim:
     are views with the grid shapes."""
 
     def __init__(self, sc: GasScene, requires_grad: bool = False, ckpt_every: int = 16,
-                 horizon: Optional[int] = None, mg_cycles: int = 6, device: str = "cuda"):
+                 horizon: Optional[int] = None, mg_cycles: int = 6, solver: str = "spectral",
+                 device: str = "cuda"):
         self.sc = sc
         self.device = torch.device(device)
         nx, ny, nz = (int(a) for a in sc.n)
@@ -47,6 +48,9 @@ class GasSim:
         d.ckpt_every = ckpt_every
         d.requires_grad = 1 if requires_grad else 0
         d.mg_cycles = mg_cycles
+        if solver not in ("spectral", "multigrid"):
+            raise ValueError("solver must be 'spectral' or 'multigrid'")
+        d.pressure_solver = 0 if solver == "spectral" else 1
         self.desc = d
         L = _lib.lib()
         ws = L.gas_workspace_bytes(ctypes.byref(d))

@@ -184,3 +184,24 @@ def test_gas_rollout_autograd_function_matches_direct_backward():
     e = rel(acts.grad.double().cpu().numpy(), ga.double().cpu().numpy())
     say(f"  autograd vs direct backward rel {e:.2e}")
     assert e <= 1e-6
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 16, 32)], ids=["cube", "box"])
+def test_gas_spectral_and_multigrid_solvers_agree(n):
+    """The exact spectral pressure solve (default) and the multigrid solver
+    give the same steps, forward and backward."""
+    sc = scenes.gas_room(n=n, steps=4, seed=9, translate=True)
+    say(f"gas {n}: spectral vs multigrid, 4 steps with gradients")
+    out = {}
+    for solver in ("spectral", "multigrid"):
+        sim = gas_sim(sc, requires_grad=True, ckpt_every=2, solver=solver)
+        sim.enable_stats(True)
+        sim.step(4)
+        res = sim.residual()
+        ga = sim.backward(_seeds(sim, 32).to(sim.device))
+        out[solver] = (sim.buf.double().cpu().numpy(), ga.double().cpu().numpy(), res)
+    e = rel(out["spectral"][0], out["multigrid"][0])
+    eg = rel(out["spectral"][1], out["multigrid"][1])
+    say(f"  residual spectral {out['spectral'][2]:.1e} multigrid {out['multigrid'][2]:.1e}; "
+        f"state rel {e:.2e}, action gradient rel {eg:.2e}")
+    assert out["spectral"][2] <= 1e-5 and e <= 1e-4 and eg <= 1e-3
