@@ -185,6 +185,40 @@ __device__ inline float sample(const GP& P, int q, const float* F, const float* 
   return lerp_eval(c, L);
 }
 
+// The velocity at a grid point of grid q: the trilinear sample of each
+// component grid there reduces to the point's own value on its own grid and
+// to averages of 2 or 4 neighbours on the others (sample fractions 0 or 1/2,
+// clamped at the walls like every sample).
+__device__ inline void node_velocity(const GP& P, const VelPtrs& vel, int q, int i, int j, int k, float* U) {
+  const int ny = P.ny, nz = P.nz;
+  if (q == 3) {
+    U[0] = 0.5f * (vel.u[gidx(i, j, k, ny, nz)] + vel.u[gidx(i + 1, j, k, ny, nz)]);
+    U[1] = 0.5f * (vel.v[gidx(i, j, k, ny + 1, nz)] + vel.v[gidx(i, j + 1, k, ny + 1, nz)]);
+    U[2] = 0.5f * (vel.w[gidx(i, j, k, ny, nz + 1)] + vel.w[gidx(i, j, k + 1, ny, nz + 1)]);
+  } else if (q == 0) {
+    const int ia = max(i - 1, 0), ib = min(i, P.nx - 1);
+    U[0] = vel.u[gidx(i, j, k, ny, nz)];
+    U[1] = 0.25f * ((vel.v[gidx(ia, j, k, ny + 1, nz)] + vel.v[gidx(ib, j, k, ny + 1, nz)]) +
+                    (vel.v[gidx(ia, j + 1, k, ny + 1, nz)] + vel.v[gidx(ib, j + 1, k, ny + 1, nz)]));
+    U[2] = 0.25f * ((vel.w[gidx(ia, j, k, ny, nz + 1)] + vel.w[gidx(ib, j, k, ny, nz + 1)]) +
+                    (vel.w[gidx(ia, j, k + 1, ny, nz + 1)] + vel.w[gidx(ib, j, k + 1, ny, nz + 1)]));
+  } else if (q == 1) {
+    const int ja = max(j - 1, 0), jb = min(j, ny - 1);
+    U[0] = 0.25f * ((vel.u[gidx(i, ja, k, ny, nz)] + vel.u[gidx(i, jb, k, ny, nz)]) +
+                    (vel.u[gidx(i + 1, ja, k, ny, nz)] + vel.u[gidx(i + 1, jb, k, ny, nz)]));
+    U[1] = vel.v[gidx(i, j, k, ny + 1, nz)];
+    U[2] = 0.25f * ((vel.w[gidx(i, ja, k, ny, nz + 1)] + vel.w[gidx(i, jb, k, ny, nz + 1)]) +
+                    (vel.w[gidx(i, ja, k + 1, ny, nz + 1)] + vel.w[gidx(i, jb, k + 1, ny, nz + 1)]));
+  } else {
+    const int ka = max(k - 1, 0), kb = min(k, nz - 1);
+    U[0] = 0.25f * ((vel.u[gidx(i, j, ka, ny, nz)] + vel.u[gidx(i, j, kb, ny, nz)]) +
+                    (vel.u[gidx(i + 1, j, ka, ny, nz)] + vel.u[gidx(i + 1, j, kb, ny, nz)]));
+    U[1] = 0.25f * ((vel.v[gidx(i, j, ka, ny + 1, nz)] + vel.v[gidx(i, j, kb, ny + 1, nz)]) +
+                    (vel.v[gidx(i, j + 1, ka, ny + 1, nz)] + vel.v[gidx(i, j + 1, kb, ny + 1, nz)]));
+    U[2] = vel.w[gidx(i, j, k, ny, nz + 1)];
+  }
+}
+
 // grid point of flat index g of grid q, and its position
 __device__ inline void point_of(const GP& P, int q, size_t g, int& i, int& j, int& k, float* x) {
   int d0, d1, d2;
@@ -239,7 +273,8 @@ __global__ __launch_bounds__(256) void k_gas_advect(GP P, VelPtrs vel, const flo
     int i, j, k;
     float x[3];
     point_of(P, q, g, i, j, k, x);
-    const float U[3] = {sample(P, 0, vel.u, x), sample(P, 1, vel.v, x), sample(P, 2, vel.w, x)};
+    float U[3];
+    node_velocity(P, vel, q, i, j, k, U);
     const float xb[3] = {x[0] - P.dt * U[0], x[1] - P.dt * U[1], x[2] - P.dt * U[2]};
     const float chi = emitter_chi(P, E, x);
     if (q < 3) {
@@ -585,8 +620,15 @@ __global__ __launch_bounds__(BOTTOM_THREADS) void k_bottom(BottomArgs B) {
 // transforms.  Each axis transform is a dense contraction with an n x n
 // matrix: out[k] = sum_i M[i][k] in[i] along the axis.
 // ---------------------------------------------------------------------------
-constexpr int XB = 64, XI = 64, XK = 128;    // lines per workgroup, input / output chunk along the axis
-static_assert(XK * XB <= XI * (XK + 1), "the output tile reuses the matrix chunk's LDS");
+// The contraction runs on the matrix cores in FP32 (v_mfma_f32_16x16x4f32):
+// a workgroup of four wavefronts takes XB = 64 lines and XK outputs along the
+// axis, each wavefront 16 lines x XK outputs as XK / 16 tiles of 16 x 16;
+// input chunks of XI values and the matching XI x XK block of the matrix are
+// staged in LDS with every global load of a chunk issued before the first
+// LDS write (float4 loads: every axis length and line count is a multiple
+// of 4).
+constexpr int XB = 64;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct AxisArgs {
   const float* in;
@@ -602,83 +644,101 @@ struct AxisArgs {
   int nz;
 };
 
-template <bool INNER>
+template <bool INNER, int XK, int XI>
 __global__ __launch_bounds__(256) void k_axis(AxisArgs X) {
+  constexpr int XM = XK / 16;
+  constexpr int NS = XB * XI / 1024;      // float4 loads of the input chunk per thread
+  constexpr int NMAT = XI * XK / 1024;    // float4 loads of the matrix block per thread
+  static_assert(XK % 16 == 0 && XI % 16 == 0 && NS >= 1 && NMAT >= 1, "tile shape");
+  static_assert(XK * XB <= XI * (XK + 1), "the output tile reuses the matrix chunk's LDS");
   __shared__ float sS[XI][XB + 1];       // input chunk, [i][line]
   __shared__ float sM[XI][XK + 1];       // matrix chunk, [i][k]; reused for the output tile [k][line]
-  float* sO = &sM[0][0];                 // output tile: k * XB + line (49.7 KB of LDS in all)
+  float* sO = &sM[0][0];                 // output tile: k * XB + line
   const int tid = threadIdx.x;
-  const int tb = tid >> 4, tk = tid & 15;   // 4 lines x 8 outputs per thread
+  // wavefront wv: lines 16 wv .. 16 wv + 15; lane (lr, lc)
+  const int wv = tid >> 6, ln = tid & 63, lr = ln >> 4, lc = ln & 15;
   const int n = X.n;
   const int a = INNER ? 0 : (int)blockIdx.y;
   const int line0 = blockIdx.x * XB;        // first line (INNER: row; OUTER: b)
   const int nlines = INNER ? X.A : X.B;
-  for (int k0 = 0; k0 < n; k0 += XK) {
-    float acc[4][8];
+  const int k0 = blockIdx.z * XK;
+  floatx4 acc[XM];
 #pragma unroll
-    for (int u = 0; u < 4; u++)
+  for (int m = 0; m < XM; m++) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int i0 = 0; i0 < n; i0 += XI) {
+    float4 rs[NS], rm[NMAT];
 #pragma unroll
-      for (int m = 0; m < 8; m++) acc[u][m] = 0.f;
-    for (int i0 = 0; i0 < n; i0 += XI) {
-      __syncthreads();
-      // stage the input chunk (coalesced along the contiguous index)
+    for (int r = 0; r < NS; r++) {
+      const int q = tid + 256 * r;
+      int line, ii;
+      if (INNER) { line = line0 + q / (XI / 4); ii = i0 + 4 * (q % (XI / 4)); }
+      else { ii = i0 + q / (XB / 4); line = line0 + 4 * (q % (XB / 4)); }
+      rs[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (line < nlines && ii < n)
+        rs[r] = INNER ? *(const float4*)(X.in + (size_t)line * n + ii)
+                      : *(const float4*)(X.in + ((size_t)a * n + ii) * X.B + line);
+    }
+#pragma unroll
+    for (int r = 0; r < NMAT; r++) {
+      const int q = tid + 256 * r;
+      const int ii = i0 + q / (XK / 4), kk = k0 + 4 * (q % (XK / 4));
+      rm[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ii < n && kk < n) rm[r] = *(const float4*)(X.M + (size_t)ii * n + kk);
+    }
+    __syncthreads();    // the previous chunk's reads are done
+#pragma unroll
+    for (int r = 0; r < NS; r++) {
+      const int q = tid + 256 * r;
       if (INNER) {
-        for (int q = tid; q < XB * XI; q += 256) {
-          const int b = q / XI, i = q % XI;
-          const int line = line0 + b, ii = i0 + i;
-          sS[i][b] = (line < nlines && ii < n) ? X.in[(size_t)line * n + ii] : 0.f;
-        }
+        const int b = q / (XI / 4), i = 4 * (q % (XI / 4));
+        sS[i][b] = rs[r].x; sS[i + 1][b] = rs[r].y; sS[i + 2][b] = rs[r].z; sS[i + 3][b] = rs[r].w;
       } else {
-        for (int q = tid; q < XB * XI; q += 256) {
-          const int i = q / XB, b = q % XB;
-          const int line = line0 + b, ii = i0 + i;
-          sS[i][b] = (line < nlines && ii < n) ? X.in[((size_t)a * n + ii) * X.B + line] : 0.f;
-        }
-      }
-      for (int q = tid; q < XI * XK; q += 256) {
-        const int i = q / XK, k = q % XK;
-        const int ii = i0 + i, kk = k0 + k;
-        sM[i][k] = (ii < n && kk < n) ? X.M[(size_t)ii * n + kk] : 0.f;
-      }
-      __syncthreads();
-      for (int i = 0; i < XI; i++) {
-        float sv[4], mv[8];
-#pragma unroll
-        for (int u = 0; u < 4; u++) sv[u] = sS[i][tb * 4 + u];
-#pragma unroll
-        for (int m = 0; m < 8; m++) mv[m] = sM[i][tk + 16 * m];
-#pragma unroll
-        for (int u = 0; u < 4; u++)
-#pragma unroll
-          for (int m = 0; m < 8; m++) acc[u][m] += sv[u] * mv[m];
+        const int i = q / (XB / 4), b = 4 * (q % (XB / 4));
+        sS[i][b] = rs[r].x; sS[i][b + 1] = rs[r].y; sS[i][b + 2] = rs[r].z; sS[i][b + 3] = rs[r].w;
       }
     }
-    __syncthreads();
-    // output tile through LDS ([k][line] in sM), then coalesced stores
 #pragma unroll
-    for (int u = 0; u < 4; u++)
-#pragma unroll
-      for (int m = 0; m < 8; m++) sO[(tk + 16 * m) * XB + tb * 4 + u] = acc[u][m];
+    for (int r = 0; r < NMAT; r++) {
+      const int q = tid + 256 * r;
+      const int i = q / (XK / 4), k = 4 * (q % (XK / 4));
+      sM[i][k] = rm[r].x; sM[i][k + 1] = rm[r].y; sM[i][k + 2] = rm[r].z; sM[i][k + 3] = rm[r].w;
+    }
     __syncthreads();
-    if (INNER) {
-      for (int q = tid; q < XB * XK; q += 256) {
-        const int b = q / XK, k = q % XK;
-        const int line = line0 + b, kk = k0 + k;
-        if (line < nlines && kk < n) X.out[(size_t)line * n + kk] = sO[k * XB + b];
-      }
-    } else {
-      for (int q = tid; q < XB * XK; q += 256) {
-        const int k = q / XB, b = q % XB;
-        const int line = line0 + b, kk = k0 + k;
-        if (line < nlines && kk < n) {
-          float v = sO[k * XB + b];
-          if (X.lx) {
-            const int ky = line / X.nz, kz = line - ky * X.nz;
-            const float lam = X.lx[kk] + X.ly[ky] + X.lz[kz];
-            v = lam != 0.f ? v / lam : 0.f;
-          }
-          X.out[((size_t)a * n + kk) * X.B + line] = v;
+    // D(16 lines x 16 outputs) += A(16 x 4) B(4 x 16): lane (lr, lc) holds
+    // A[lc][lr] = in[line 16 wv + lc][i + lr] and B[lr][lc] = M[i + lr][16 m + lc]
+#pragma unroll 4
+    for (int i = 0; i < XI; i += 4) {
+      const float av = sS[i + lr][16 * wv + lc];
+#pragma unroll
+      for (int m = 0; m < XM; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sM[i + lr][16 * m + lc], acc[m], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  // output tile through LDS ([k][line] in sM), then coalesced stores; lane
+  // (lr, lc) holds D[4 lr + r][lc], r < 4
+#pragma unroll
+  for (int m = 0; m < XM; m++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) sO[(16 * m + lc) * XB + 16 * wv + 4 * lr + r] = acc[m][r];
+  __syncthreads();
+  if (INNER) {
+    for (int q = tid; q < XB * XK; q += 256) {
+      const int b = q / XK, k = q % XK;
+      const int line = line0 + b, kk = k0 + k;
+      if (line < nlines && kk < n) X.out[(size_t)line * n + kk] = sO[k * XB + b];
+    }
+  } else {
+    for (int q = tid; q < XB * XK; q += 256) {
+      const int k = q / XB, b = q % XB;
+      const int line = line0 + b, kk = k0 + k;
+      if (line < nlines && kk < n) {
+        float v = sO[k * XB + b];
+        if (X.lx) {
+          const int ky = line / X.nz, kz = line - ky * X.nz;
+          const float lam = X.lx[kk] + X.ly[ky] + X.lz[kz];
+          v = lam != 0.f ? v / lam : 0.f;
         }
+        X.out[((size_t)a * n + kk) * X.B + line] = v;
       }
     }
   }
@@ -796,7 +856,8 @@ __global__ __launch_bounds__(256) void k_gas_adj_advect(GP P, VelPtrs vel, const
     int i, j, k;
     float x[3];
     point_of(P, q, g, i, j, k, x);
-    const float U[3] = {sample(P, 0, vel.u, x), sample(P, 1, vel.v, x), sample(P, 2, vel.w, x)};
+    float U[3];
+    node_velocity(P, vel, q, i, j, k, U);
     const float xb[3] = {x[0] - P.dt * U[0], x[1] - P.dt * U[1], x[2] - P.dt * U[2]};
     const float chi = emitter_chi(P, E, x);
     const float dchi[3] = {chi * (x[0] - E.c[0]) * 2.f * P.s2inv, chi * (x[1] - E.c[1]) * 2.f * P.s2inv,
@@ -1159,6 +1220,19 @@ void mg_solve(gas_ctx* c, float* psi0, float* f0) {
   }
 }
 
+// one transform pass; grid.z splits the n outputs into chunks of XK (16 up to
+// n = 128, 64 above: measured fastest at 64^3, 128^3 and 256^3)
+template <bool INNER>
+void launch_axis(const AxisArgs& X, dim3 grid, hipStream_t s) {
+  if (X.n <= 128) {
+    grid.z = (X.n + 15) / 16;
+    k_axis<INNER, 16, 64><<<grid, 256, 0, s>>>(X);
+  } else {
+    grid.z = (X.n + 63) / 64;
+    k_axis<INNER, 64, 64><<<grid, 256, 0, s>>>(X);
+  }
+}
+
 // A psi = f exactly by the axis transforms (psi0 receives the solution with
 // zero mean; f0 is left unchanged)
 void spectral_solve(gas_ctx* c, float* psi0, const float* f0) {
@@ -1177,14 +1251,14 @@ void spectral_solve(gas_ctx* c, float* psi0, const float* f0) {
     X.in = in; X.out = out; X.M = M;
     if (axis == 2) {
       X.n = nz; X.A = nx * ny; X.B = 1;
-      k_axis<true><<<dim3((X.A + XB - 1) / XB, 1, 1), 256, 0, s>>>(X);
+      launch_axis<true>(X, dim3((X.A + XB - 1) / XB, 1, 1), s);
       return;
     }
     X.n = axis == 0 ? nx : ny;
     X.A = axis == 0 ? 1 : nx;
     X.B = axis == 0 ? ny * nz : nz;
     if (divide) { X.lx = lam[0]; X.ly = lam[1]; X.lz = lam[2]; X.nz = nz; }
-    k_axis<false><<<dim3((X.B + XB - 1) / XB, X.A, 1), 256, 0, s>>>(X);
+    launch_axis<false>(X, dim3((X.B + XB - 1) / XB, X.A, 1), s);
   };
   c->t_smooth.begin(s);
   pass(2, f0, T, Mf[2], false);

@@ -2,10 +2,10 @@
 1999; the air-circulation setting of section 4.1) through the C ABI, against
 the FP64 oracle on the same seeded scenes.
 
-Tolerances: FP32 advection and a multigrid pressure solve of 6 V-cycles
-(relative residual at the FP32 floor, 1e-6 to 3e-5 depending on the grid)
-against the oracle's exact projection: fields 2e-4 relative after several
-steps; gradients 2e-3 relative.
+Tolerances: FP32 advection and an exact FP32 pressure solve (spectral by
+default, on the matrix cores; the multigrid alternative at 6 V-cycles
+reaches the FP32 residual floor) against the oracle's exact projection in
+FP64: fields 2e-4 relative after several steps; gradients 2e-3 relative.
 """
 import sys
 
@@ -45,8 +45,7 @@ def compare(g, ref, tol_v=2e-4, tol_s=2e-5):
 @pytest.mark.parametrize("n", [16, 32])
 def test_gas_steps_vs_oracle(n):
     """Several steps (moving and turning emitter, buoyancy) against the
-    oracle; 16^3 runs the whole multigrid in one workgroup, 32^3 one grid
-    level above it."""
+    oracle, with the default (spectral) solver."""
     sc = scenes.gas_room(n=n, steps=6, seed=1, translate=True)
     say(f"gas {n}^3, 6 steps")
     sim = gas_sim(sc)
@@ -134,8 +133,9 @@ def test_gas_sensor_loss_and_its_gradient():
 
 
 def test_gas_box_grid_one_scalar_vs_oracle():
-    """A non-cubic box (24 x 16 x 32 cells: its multigrid stops at an odd
-    3 x 2 x 4 level) with one scalar, against the oracle."""
+    """A non-cubic box (24 x 16 x 32 cells: axis lengths below the
+    transform's 64-value chunks, zero-padded) with one scalar, against the
+    oracle."""
     sc = scenes.gas_room(n=(24, 16, 32), steps=4, seed=5, n_scalars=1, translate=True)
     say("gas 24x16x32, one scalar, 4 steps")
     sim = gas_sim(sc)
