@@ -136,7 +136,11 @@ __device__ inline Lerp lerp_setup(const GP& P, int q, const float* x) {
   return L;
 }
 
-__device__ inline size_t gidx(int i, int j, int k, int d1, int d2) { return ((size_t)i * d1 + j) * d2 + k; }
+// flat index in one grid array (every array has fewer than 2^32 values:
+// 32-bit arithmetic, widened for the address)
+__device__ inline size_t gidx(int i, int j, int k, int d1, int d2) {
+  return (size_t)(((uint32_t)i * (uint32_t)d1 + (uint32_t)j) * (uint32_t)d2 + (uint32_t)k);
+}
 
 __device__ inline void cell_of(const Dims& D, size_t g, int& i, int& j, int& k) {
   const uint32_t g32 = (uint32_t)g, r = g32 / (uint32_t)D.z;
@@ -147,8 +151,10 @@ __device__ inline void cell_of(const Dims& D, size_t g, int& i, int& j, int& k) 
 
 // the 8 corner values
 __device__ inline void lerp_load(const float* __restrict__ F, const Lerp& L, int d1, int d2, float* c) {
+  const float* b = F + gidx(L.i0, L.j0, L.k0, d1, d2);
+  const uint32_t sy = (uint32_t)d2, sx = (uint32_t)d1 * (uint32_t)d2;
 #pragma unroll
-  for (int n = 0; n < 8; n++) c[n] = F[gidx(L.i0 + (n >> 2), L.j0 + ((n >> 1) & 1), L.k0 + (n & 1), d1, d2)];
+  for (int n = 0; n < 8; n++) c[n] = b[((n >> 2) ? sx : 0u) + (((n >> 1) & 1) ? sy : 0u) + (uint32_t)(n & 1)];
 }
 __device__ inline float lerp_weight(const Lerp& L, int n) {
   return ((n >> 2) ? L.f[0] : 1.f - L.f[0]) * (((n >> 1) & 1) ? L.f[1] : 1.f - L.f[1]) * ((n & 1) ? L.f[2] : 1.f - L.f[2]);
