@@ -994,16 +994,18 @@ __global__ __launch_bounds__(256) void k_gas_adj_advect(GP P, VelPtrs vel, const
   }
 }
 
-// Adjoint of the velocity sampled at every grid point (U(x) of the
-// back-traces) as a gather: each velocity-grid node sums, over the grid
-// points whose trilinear sample of its grid touches it, the weight times the
-// point's U adjoint (ub, from k_gas_adj_advect).  A point of grid q touches
-// node n of grid a only from index n on an axis where q and a share their
-// staggering and from n - 1 .. n + 1 where they differ; the weights are those
-// of the same sampling routine as the forward.
+// Adjoint of the velocity at every grid point (U of the back-traces, from
+// the stencils of node_velocity) as a gather: each velocity node of grid a
+// sums the U_a adjoints (ub, from k_gas_adj_advect) of the points whose
+// stencil holds it, with the stencil's weights: its own point (1), the two
+// cells beside it along a (1/2 each), and on each other face grid b the
+// points beside it along a (1/2) whose clamped pair along b holds it (1/2
+// per hit).
 __global__ __launch_bounds__(256) void k_gas_adj_ugather(GP P, const float* __restrict__ ub, AdjOut out) {
   const size_t total = P.nu + P.nv + P.nw + P.nc;
   const size_t nvel = P.nu + P.nv + P.nw;
+  const size_t qoff[4] = {0, P.nu, P.nu + P.nv, nvel};
+  const int N[3] = {P.nx, P.ny, P.nz};
   for (size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g0 < nvel; g0 += (size_t)gridDim.x * blockDim.x) {
     size_t g = g0;
     const int a = split_points(P, g);
@@ -1011,32 +1013,34 @@ __global__ __launch_bounds__(256) void k_gas_adj_ugather(GP P, const float* __re
     float xn[3];
     point_of(P, a, g, n[0], n[1], n[2], xn);
     const float* U = ub + (size_t)a * total;
-    float acc = 0.f;
-    size_t qoff = 0;
+    float acc = U[qoff[a] + g];
+    float cs = 0.f;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      int dq[3];
-      gdims(P, q, dq[0], dq[1], dq[2]);
-      int lo[3], hi[3];
+    for (int t = 0; t < 2; t++) {
+      int c[3] = {n[0], n[1], n[2]};
+      c[a] = n[a] - 1 + t;
+      if (c[a] >= 0 && c[a] < N[a]) cs += U[qoff[3] + gidx(c[0], c[1], c[2], P.ny, P.nz)];
+    }
+    acc += 0.5f * cs;
 #pragma unroll
-      for (int e = 0; e < 3; e++) {
-        const bool same = gorigin(q, e) == gorigin(a, e);
-        lo[e] = same ? n[e] : max(n[e] - 1, 0);
-        hi[e] = same ? n[e] : min(n[e] + 1, dq[e] - 1);
+    for (int b = 0; b < 3; b++) {
+      if (b == a) continue;
+      int db0, db1, db2;
+      gdims(P, b, db0, db1, db2);
+      float fs = 0.f;
+#pragma unroll
+      for (int ta = 0; ta < 2; ta++) {
+#pragma unroll
+        for (int tb = 0; tb < 2; tb++) {
+          int p[3] = {n[0], n[1], n[2]};
+          p[a] = n[a] - 1 + ta;
+          p[b] = n[b] + tb;
+          if (p[a] < 0 || p[a] >= N[a] || p[b] > N[b]) continue;
+          const int hits = (max(p[b] - 1, 0) == n[b]) + (min(p[b], N[b] - 1) == n[b]);
+          if (hits) fs += (float)hits * U[qoff[b] + gidx(p[0], p[1], p[2], db1, db2)];
+        }
       }
-      for (int pi = lo[0]; pi <= hi[0]; pi++)
-        for (int pj = lo[1]; pj <= hi[1]; pj++)
-          for (int pk = lo[2]; pk <= hi[2]; pk++) {
-            const float xp[3] = {((float)pi + gorigin(q, 0)) * P.h, ((float)pj + gorigin(q, 1)) * P.h,
-                                 ((float)pk + gorigin(q, 2)) * P.h};
-            const Lerp L = lerp_setup(P, a, xp);
-            const int b[3] = {L.i0, L.j0, L.k0};
-            float w = 1.f;
-#pragma unroll
-            for (int e = 0; e < 3; e++) w *= (n[e] == b[e]) ? 1.f - L.f[e] : ((n[e] == b[e] + 1) ? L.f[e] : 0.f);
-            if (w != 0.f) acc += w * U[qoff + gidx(pi, pj, pk, dq[1], dq[2])];
-          }
-      qoff += (size_t)dq[0] * dq[1] * dq[2];
+      acc += 0.25f * fs;
     }
     float* O = a == 0 ? out.u : (a == 1 ? out.v : out.w);
     O[g] += acc;
