@@ -205,3 +205,16 @@ def test_gas_spectral_and_multigrid_solvers_agree(n):
     say(f"  residual spectral {out['spectral'][2]:.1e} multigrid {out['multigrid'][2]:.1e}; "
         f"state rel {e:.2e}, action gradient rel {eg:.2e}")
     assert out["spectral"][2] <= 1e-5 and e <= 1e-4 and eg <= 1e-3
+
+
+def test_gas_long_axes_vs_oracle():
+    """Axes longer than 128 cells (132 along x, 136 along z) take the axis
+    transform's wider output split (64 outputs per workgroup) with ragged
+    last chunks; a thin y axis (12) the narrow one."""
+    sc = scenes.gas_room(n=(132, 12, 136), steps=3, seed=10, n_scalars=1, translate=True)
+    say("gas 132x12x136, one scalar, 3 steps")
+    sim = gas_sim(sc)
+    sim.enable_stats(True)
+    sim.step(3)
+    say(f"  pressure residual {sim.residual():.2e}")
+    compare(sim.state_numpy(), G.rollout_scene(sc, steps=3))
