@@ -1,27 +1,31 @@
 // The gas step (include/gas.h): incompressible advection-projection on a
 // staggered grid (FluidLab section 3.2, after Stam 1999) and its adjoint.
 //
-// Forward step, five launches plus the pressure solve:
-//   k_gas_advect   every grid point of u, v, w and the cells: back-trace
-//                  through the step's velocity, trilinear sample, emitter
-//                  blend (one launch for the four grids)
+// Forward step, three launches plus the pressure solve:
+//   k_gas_advect   every grid point of u, v, w and the cells: the velocity
+//                  at the point from its stencils, back-trace, trilinear
+//                  sample, emitter blend (one launch for the four grids)
 //   k_gas_div      per cell: divergence of the advected velocity with the
 //                  buoyancy of the y-faces added on the fly and the walls
 //                  closed; right-hand side of the pressure equation
-//   mg_solve       multigrid V-cycles for A psi = div (A: 7-point Neumann
-//                  Laplacian in cell units; psi = pressure * dt / h):
-//                  red-black half-sweeps on the finest level, tiled full
-//                  sweeps on the coarser grid levels, the levels of at most
-//                  4096 cells in one workgroup
+//   pressure       A psi = div (A: 7-point Neumann Laplacian in cell units;
+//                  psi = pressure * dt / h), by default exactly: DCT-II
+//                  transforms along z, y and x on the matrix cores (k_axis),
+//                  division by the eigenvalue sums, inverse transforms; or
+//                  multigrid V-cycles (mg_solve: red-black half-sweeps on
+//                  the finest level, tiled full sweeps on the coarser grid
+//                  levels, the levels of at most 4096 cells in one workgroup)
 //   k_gas_final    u = u* - grad psi on the interior faces, walls zero,
 //                  scalars copied
-// Adjoint step: the projection of the adjoint (k_gas_adj_div, mg_solve,
-// k_gas_adj_sub; the projector is self-adjoint on wall-closed fields), then
-// k_gas_adj_advect, which recomputes the back-traces, applies the buoyancy
-// and emitter adjoints and scatters the advection adjoint (trilinear weights
-// at the back-traced point, and the velocity sampled at the grid point) with
-// float atomics; the emitter's pose partials are reduced per wavefront into
-// 128 FP64 accumulator copies.
+// Adjoint step: the projection of the adjoint (k_gas_adj_div, the same
+// pressure solve, k_gas_adj_sub; the projector is self-adjoint on
+// wall-closed fields), then k_gas_adj_advect, which recomputes the
+// back-traces, applies the buoyancy and emitter adjoints and scatters the
+// advection adjoint at the back-traced points with float atomics (lanes
+// merge the corners they share first), and k_gas_adj_ugather, which gathers
+// the adjoint of the grid-point velocities over their stencils; the
+// emitter's pose partials are reduced per wavefront into 128 FP64
+// accumulator copies.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -664,6 +668,11 @@ struct AxisArgs {
 template <bool INNER, int XK, int XI>
 __global__ __launch_bounds__(256) void k_axis(AxisArgs X) {
   constexpr int XM = XK / 16;
+  // two accumulator sets over alternate i-steps, added at the end: the same
+  // speed as one, and a shorter rounding chain (pressure residual at 128^3
+  // 1.2e-4 against 1.6e-4)
+  constexpr int NACC = 2;
+  static_assert(XI % (4 * NACC) == 0, "chunk split");
   constexpr int NS = XB * XI / 1024;      // float4 loads of the input chunk per thread
   constexpr int NMAT = XI * XK / 1024;    // float4 loads of the matrix block per thread
   static_assert(XK % 16 == 0 && XI % 16 == 0 && NS >= 1 && NMAT >= 1, "tile shape");
@@ -679,9 +688,11 @@ __global__ __launch_bounds__(256) void k_axis(AxisArgs X) {
   const int line0 = blockIdx.x * XB;        // first line (INNER: row; OUTER: b)
   const int nlines = INNER ? X.A : X.B;
   const int k0 = blockIdx.z * XK;
-  floatx4 acc[XM];
+  floatx4 acc[NACC][XM];
 #pragma unroll
-  for (int m = 0; m < XM; m++) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < NACC; u++)
+#pragma unroll
+    for (int m = 0; m < XM; m++) acc[u][m] = floatx4{0.f, 0.f, 0.f, 0.f};
   for (int i0 = 0; i0 < n; i0 += XI) {
     float4 rs[NS], rm[NMAT];
 #pragma unroll
@@ -723,20 +734,28 @@ __global__ __launch_bounds__(256) void k_axis(AxisArgs X) {
     __syncthreads();
     // D(16 lines x 16 outputs) += A(16 x 4) B(4 x 16): lane (lr, lc) holds
     // A[lc][lr] = in[line 16 wv + lc][i + lr] and B[lr][lc] = M[i + lr][16 m + lc]
-#pragma unroll 4
-    for (int i = 0; i < XI; i += 4) {
-      const float av = sS[i + lr][16 * wv + lc];
+#pragma unroll 2
+    for (int i = 0; i < XI; i += 4 * NACC) {
 #pragma unroll
-      for (int m = 0; m < XM; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sM[i + lr][16 * m + lc], acc[m], 0, 0, 0);
+      for (int u = 0; u < NACC; u++) {
+        const float av = sS[i + 4 * u + lr][16 * wv + lc];
+#pragma unroll
+        for (int m = 0; m < XM; m++)
+          acc[u][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sM[i + 4 * u + lr][16 * m + lc], acc[u][m], 0, 0, 0);
+      }
     }
   }
+#pragma unroll
+  for (int u = 1; u < NACC; u++)
+#pragma unroll
+    for (int m = 0; m < XM; m++) acc[0][m] += acc[u][m];
   __syncthreads();
   // output tile through LDS ([k][line] in sM), then coalesced stores; lane
   // (lr, lc) holds D[4 lr + r][lc], r < 4
 #pragma unroll
   for (int m = 0; m < XM; m++)
 #pragma unroll
-    for (int r = 0; r < 4; r++) sO[(16 * m + lc) * XB + 16 * wv + 4 * lr + r] = acc[m][r];
+    for (int r = 0; r < 4; r++) sO[(16 * m + lc) * XB + 16 * wv + 4 * lr + r] = acc[0][m][r];
   __syncthreads();
   if (INNER) {
     for (int q = tid; q < XB * XK; q += 256) {
