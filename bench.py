@@ -256,7 +256,9 @@ def bench_gas(torch, n=128, steps=20, bwd_steps=8):
     contraction of every grid line along one axis with the n x n transform
     matrix on the matrix cores: 2 n flops per cell (32 flops per byte moved,
     above the FP32 machine balance of 157.3 / 8 = 20), so it is priced
-    against the FP32 matrix peak; it also reads and writes 8 B per cell."""
+    against the FP32 matrix peak; it also reads and writes 8 B per cell.
+    The six launches of a solve run back to back inside one HIP event pair;
+    the average per launch is that time over six."""
     from paper_2303_02346_amd import scenes
     from paper_2303_02346_amd.gas import GasSim
     sc = scenes.gas_room(n=n, steps=max(steps, bwd_steps) + 2, seed=0)
@@ -302,7 +304,7 @@ def bench_gas(torch, n=128, steps=20, bwd_steps=8):
            "advect": {"avg_us": round(adv_avg * 1e6, 2), "algorithmic_bytes_per_launch": int(adv_bytes),
                       "achieved_GBps": round(adv_bytes / adv_avg / 1e9, 1) if adv_n else None,
                       "frac_of_hbm": round(adv_bytes / adv_avg / 1e9 / HBM_PEAK_GBS, 4) if adv_n else None},
-           "roofline": {"bound": "mfma", "kernel": "k_axis (z-axis transform)", "dtype": "f32",
+           "roofline": {"bound": "mfma", "kernel": "k_axis (the six transforms of a solve, per launch)", "dtype": "f32",
                         "achieved": round(ach, 2) if ach else None, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(ach / FP32_PEAK_TFLOPS, 4) if ach else None,
                         "avg_us": round(sm_avg * 1e6, 2), "algorithmic_flops_per_launch": int(ax_flops),

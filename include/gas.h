@@ -113,9 +113,10 @@ int gas_enable_stats(gas_ctx* c, int32_t enable);
 int gas_solver_residual(gas_ctx* c, double* rel_residual);
 
 /* Measurement: time launches of the step's dominant kernels with HIP events
- * and read the sums: advection (advect_*), and as smooth_* the first axis
- * transform of each spectral solve (along z) or every finest-level
- * smoothing sweep of the multigrid solver. */
+ * and read the sums: advection (advect_*), and as smooth_* the six axis
+ * transforms of each spectral solve (one event pair around them, counted as
+ * six launches) or every finest-level smoothing sweep of the multigrid
+ * solver. */
 int gas_timing_enable(gas_ctx* c, int32_t enable);
 int gas_timing_read(gas_ctx* c, double* advect_ms, int64_t* advect_launches, double* smooth_ms,
                     int64_t* smooth_launches);
