@@ -332,8 +332,14 @@ struct PartArgs {
 
 enum { FEAT_NONE = 0, FEAT_LOG = 1, FEAT_CLOSURE = 2 };
 
+// The fused kernel (MODE 1 without the closure features) in 256-thread
+// workgroups runs fastest held to three wavefronts per SIMD (168 VGPRs and a
+// few spills): 65.5 us per config-2 step against 69.5 us at two (231 VGPRs)
+// and 81.7 us at four.  In 512-thread workgroups the same bound made the
+// 1e5-particle 64^3 step slower (66 against 62 us), so they keep two.
 template <int MODE, int NT, int FEAT>
-__global__ __launch_bounds__(NT) void k_particles(PartArgs A, StepParams P, FastGeom g) {
+__global__ __launch_bounds__(NT, (MODE == 1 && FEAT == FEAT_NONE && NT == 256) ? 3 : 1) void k_particles(
+    PartArgs A, StepParams P, FastGeom g) {
   constexpr int NW = NT / 64;
   __shared__ MlpBlob s_mlp;
   __shared__ MlpScratch s_mscr[NW];
