@@ -336,10 +336,12 @@ enum { FEAT_NONE = 0, FEAT_LOG = 1, FEAT_CLOSURE = 2 };
 // workgroups runs fastest held to three wavefronts per SIMD (168 VGPRs and a
 // few spills): 65.5 us per config-2 step against 69.5 us at two (231 VGPRs)
 // and 81.7 us at four.  In 512-thread workgroups the same bound made the
-// 1e5-particle 64^3 step slower (66 against 62 us), so they keep two.
+// 1e5-particle 64^3 step slower (66 against 62 us), so they keep two.  The
+// separate P2G (MODE 0, 190 VGPRs unbounded) gains from the same bound too:
+// the rigid-body step at config-2 size 0.126 -> 0.121 ms.
 template <int MODE, int NT, int FEAT>
-__global__ __launch_bounds__(NT, (MODE == 1 && FEAT == FEAT_NONE && NT == 256) ? 3 : 1) void k_particles(
-    PartArgs A, StepParams P, FastGeom g) {
+__global__ __launch_bounds__(NT, (NT == 256 && ((MODE == 1 && FEAT == FEAT_NONE) || MODE == 0)) ? 3 : 1) void
+k_particles(PartArgs A, StepParams P, FastGeom g) {
   constexpr int NW = NT / 64;
   __shared__ MlpBlob s_mlp;
   __shared__ MlpScratch s_mscr[NW];
