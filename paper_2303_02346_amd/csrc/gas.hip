@@ -1473,7 +1473,7 @@ int gas_create(const gas_desc* d, void* workspace_dev, size_t ws_bytes, void* st
   c->last_res = 0.0;
   c->last_err_bits = 0;
   c->t_adv.name = "k_gas_advect";
-  c->t_smooth.name = "k_rb_half";
+  c->t_smooth.name = d->pressure_solver == 0 ? "k_axis" : "k_rb_half";
   c->act_set.assign(d->horizon, 0);
   GP& P = c->P;
   P.nx = d->nx; P.ny = d->ny; P.nz = d->nz; P.K = d->n_scalars;
