@@ -35,6 +35,39 @@ __device__ inline void key_decode(const FastGeom& g, uint32_t key, int& s, int& 
   bz = (int)compact3(m);
 }
 
+// Reductions over the 64 lanes of a wavefront without LDS: DPP lane moves
+// within each row of 16 lanes (swap of neighbours, swap of pairs, mirror of
+// each half row, mirror of the row) leave every lane with its row's result,
+// and the four rows are combined from readlanes.  Every lane of the wave must
+// be active.
+namespace dpp {
+constexpr int kSwap1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kSwap2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kHalfMirror = 0x141;  // row_half_mirror
+constexpr int kMirror = 0x140;      // row_mirror
+template <int CTRL> __device__ __forceinline__ int mov(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
+}  // namespace dpp
+
+__device__ __forceinline__ float wave_sum(float x) {
+  x += __int_as_float(dpp::mov<dpp::kSwap1>(__float_as_int(x)));
+  x += __int_as_float(dpp::mov<dpp::kSwap2>(__float_as_int(x)));
+  x += __int_as_float(dpp::mov<dpp::kHalfMirror>(__float_as_int(x)));
+  x += __int_as_float(dpp::mov<dpp::kMirror>(__float_as_int(x)));
+  const int xi = __float_as_int(x);
+  return (__int_as_float(__builtin_amdgcn_readlane(xi, 0)) + __int_as_float(__builtin_amdgcn_readlane(xi, 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(xi, 32)) + __int_as_float(__builtin_amdgcn_readlane(xi, 48)));
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
+  int v = (int)x;
+  v |= dpp::mov<dpp::kSwap1>(v);
+  v |= dpp::mov<dpp::kSwap2>(v);
+  v |= dpp::mov<dpp::kHalfMirror>(v);
+  v |= dpp::mov<dpp::kMirror>(v);
+  return (uint32_t)(__builtin_amdgcn_readlane(v, 0) | __builtin_amdgcn_readlane(v, 16) |
+                    __builtin_amdgcn_readlane(v, 32) | __builtin_amdgcn_readlane(v, 48));
+}
+
 // Rank of each lane's key among equal keys of the wavefront, in two phases
 // so that the global atomic's latency overlaps other work: rank_issue groups
 // the lanes by key (ballots only) and lets one leader lane per distinct key
@@ -58,7 +91,7 @@ __device__ inline WaveRank rank_issue(uint32_t* counts, uint32_t key, bool valid
   uint32_t lcount = 0;
   while (pending) {
     int leader = __ffsll((long long)pending) - 1;
-    uint32_t k = __shfl(key, leader);
+    const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
     unsigned long long m = __ballot(valid && key == k) & pending;
     if ((m >> lane) & 1ull) { R.leader = leader; R.prefix = (uint32_t)__popcll(m & ((1ull << lane) - 1ull)); }
     if (lane == leader) lcount = (uint32_t)__popcll(m);

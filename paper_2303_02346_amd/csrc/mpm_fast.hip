@@ -298,6 +298,51 @@ __global__ __launch_bounds__(256) void k_export(PBuf X, PState u, const MatDev* 
   }
 }
 
+// G2P gather from the staged velocity tile (VT^3 nodes, lb = the stencil's
+// first node in it): vn = sum_i w_i v_i and Bi = sum_i w_i v_i idx_i^T with
+// idx_i in {0,1,2}^3 the node's offset in the stencil.  The sums run over z
+// inside y inside x, so that each partial sum is weighted once by the outer
+// weights; the loads of one x plane are issued together, and the compiler
+// barrier between planes keeps the next plane's loads from being hoisted
+// (nine float3 loads in flight rather than 27 bounds the register count).
+__device__ __forceinline__ void g2p_gather(const float4* __restrict__ s_v, const int* lb, const Stencil& S,
+                                           float* vn, float* Bi) {
+#pragma unroll
+  for (int q = 0; q < 3; q++) vn[q] = 0.f;
+#pragma unroll
+  for (int q = 0; q < 9; q++) Bi[q] = 0.f;
+  const float wz1 = S.w[2][1], wz2 = S.w[2][2], wz2x2 = 2.f * S.w[2][2];
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    float p0[3] = {0, 0, 0}, pj[3] = {0, 0, 0}, pk[3] = {0, 0, 0};
+#pragma unroll
+    for (int jj = 0; jj < 3; jj++) {
+      const float4* row = s_v + ((lb[0] + i) * VT + lb[1] + jj) * VT + lb[2];
+      const float4 g0 = row[0], g1 = row[1], g2 = row[2];
+      // r = sum_k w_k v_k, rk = sum_k k w_k v_k along z
+      const float r[3] = {S.w[2][0] * g0.x + wz1 * g1.x + wz2 * g2.x, S.w[2][0] * g0.y + wz1 * g1.y + wz2 * g2.y,
+                          S.w[2][0] * g0.z + wz1 * g1.z + wz2 * g2.z};
+      const float rk[3] = {wz1 * g1.x + wz2x2 * g2.x, wz1 * g1.y + wz2x2 * g2.y, wz1 * g1.z + wz2x2 * g2.z};
+      const float wy = S.w[1][jj];
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        p0[a] += wy * r[a];
+        if (jj) pj[a] += ((float)jj * wy) * r[a];
+        pk[a] += wy * rk[a];
+      }
+    }
+    const float wx = S.w[0][i];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      vn[a] += wx * p0[a];
+      if (i) Bi[a * 3 + 0] += ((float)i * wx) * p0[a];
+      Bi[a * 3 + 1] += wx * pj[a];
+      Bi[a * 3 + 2] += wx * pk[a];
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
 // ---------------------------------------------------------------------------
 // particle kernel
 // ---------------------------------------------------------------------------
@@ -356,7 +401,7 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
   __shared__ float4 s_v[VT_NODES];
   __shared__ int s_lo[3], s_hi[3];
   __shared__ float s_red[NW * 4], s_scale[8];
-  __shared__ int s_ired[NW * 6 + 6];   // per-wave boxes, then the chunk's box at RB
+  __shared__ int s_ired[NW * 6 + 6];   // per-wave box bits, then the chunk's box at RB
   constexpr int RB = NW * 6;
   const int tid = threadIdx.x;
   const int N = A.N;
@@ -368,6 +413,27 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
     int sc, bx, by, bz;
     key_decode(g, (uint32_t)ent.x, sc, bx, by, bz);
     const int ox = 4 * bx, oy = 4 * by, oz = 4 * bz;
+    const int start = ent.y, count = ent.z;
+    // The inputs of a chunk are loaded one chunk ahead (the first chunk's
+    // before the staging below), so that their latency overlaps other work.
+    // F and J are both loaded, whatever the material, so that no load waits
+    // for the material's kind; v and C are replaced by G2P and not read.
+    float px[3] = {0, 0, 0}, pF[9], pJ = 1.f;
+    int pm = 0;
+    uint32_t pkey = 0, prank = 0;
+    auto prefetch = [&](int c0n) {
+      const int jn = start + c0n + tid;
+      if (c0n + tid < count && jn < N) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) px[a] = A.in.f[a * (size_t)N + jn];
+#pragma unroll
+        for (int k = 0; k < 9; k++) pF[k] = A.in.f[(15 + k) * (size_t)N + jn];
+        pJ = A.in.f[24 * (size_t)N + jn];
+        pm = A.in.mat[jn];
+        if (MODE != MODE_P2G) { pkey = A.in.key[jn]; prank = A.in.rank[jn]; }
+      }
+    };
+    prefetch(0);
     // ---- stage grid velocities of nodes [4b-1, 4b+7) for G2P
     if (MODE != MODE_P2G) {
       for (int q = tid; q < VT_NODES; q += NT) {
@@ -386,36 +452,29 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
       if (tid < 3) { s_lo[tid] = 1 << 20; s_hi[tid] = -(1 << 20); }
     }
     __syncthreads();
-    const int start = ent.y, count = ent.z;
     for (int c0 = 0; c0 < count; c0 += NT) {
       const int j = start + c0 + tid;
       const bool has = (c0 + tid) < count && j < N;
-      float x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, C[9], F[9], J = 1.f;
-      int m = 0;
+      float x[3] = {px[0], px[1], px[2]}, v[3] = {0, 0, 0}, C[9], F[9], J = pJ;
+#pragma unroll
+      for (int k = 0; k < 9; k++) { F[k] = pF[k]; C[k] = 0.f; }
+      const int m = has ? pm : 0;
       bool ok = has;
+      // destination slot in the output buffer (the key -> offset lookup
+      // overlaps the G2P arithmetic); the P2G-only mode reads v and C
       uint32_t dst = 0;
       if (has) {
-        load_state(A.in, N, j, x, v, C, F, J);
-        m = A.in.mat[j];
-        // destination slot in the output buffer; loaded now so that the
-        // dependent key -> offset lookup overlaps the G2P arithmetic
-        if (MODE != MODE_P2G) dst = A.offsets[A.in.key[j]] + A.in.rank[j];
+        if (MODE == MODE_P2G) load_state(A.in, N, j, x, v, C, F, J);
+        else dst = A.offsets[pkey] + prank;
       }
       const MatDev& M = P.mats[m];
       const bool liquid = M.kind == KIND_LIQUID;
-      if (has) {
-        if (liquid) J = A.in.f[24 * (size_t)N + j];
-        else {
-#pragma unroll
-          for (int k = 0; k < 9; k++) F[k] = A.in.f[(15 + k) * (size_t)N + j];
-        }
-      }
       float tau[9];
       bool have_tau = false;
       // cone-case sample of this particle (closure input and exact answer)
       bool cone = false;
       float xin[MLP_IN] = {0, 0, 0, 0, 0, 0}, eex[MLP_OUT] = {0, 0, 0};
-      double Uk[9], Vk[9];
+      float Uk[9], Vk[9];
       // ---------------- G2P of the previous step ----------------
       if (MODE != MODE_P2G && has) {
         Stencil S;
@@ -427,26 +486,8 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
         if (ok) {
           // sum_i w v_i and sum_i w v_i idx^T (idx = the node offset in
           // {0,1,2}^3); then B = sum w v (x_i - x_p)^T = dx (Bi - vn f^T)
-          float vn[3] = {0, 0, 0}, Bi[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-          for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int jj = 0; jj < 3; jj++) {
-              const float wxy = S.w[0][i] * S.w[1][jj];
-#pragma unroll
-              for (int k = 0; k < 3; k++) {
-                const float w = wxy * S.w[2][k];
-                const float4 gv4 = s_v[((lb[0] + i) * VT + lb[1] + jj) * VT + lb[2] + k];
-                const float wv[3] = {w * gv4.x, w * gv4.y, w * gv4.z};
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                  vn[a] += wv[a];
-                  if (i) Bi[a * 3 + 0] += (float)i * wv[a];
-                  if (jj) Bi[a * 3 + 1] += (float)jj * wv[a];
-                  if (k) Bi[a * 3 + 2] += (float)k * wv[a];
-                }
-              }
-            }
+          float vn[3], Bi[9];
+          g2p_gather(s_v, lb, S, vn, Bi);
           float B[9];
 #pragma unroll
           for (int a = 0; a < 3; a++)
@@ -469,62 +510,38 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
 #pragma unroll
             for (int k = 0; k < 9; k++) F[k] = Fn[k];
           } else {
-            double Mdd[9], Fd[9], Ft[9], Uu[9], s[3], V[9];
+            // plastic solids: FP32 SVD and return map, redone in FP64 for an
+            // ill-conditioned trial state (or an unconverged sweep)
+            float Fn[9];
+            PlasticStep<float> R;
+            int st = plastic_step<float, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R);
+            if (st == PLASTIC_RETRY) {
+              PlasticStep<double> R2;
+              st = plastic_step<double, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R2);
+              R.cse = R2.cse;
 #pragma unroll
-            for (int k = 0; k < 9; k++) { Mdd[k] = Md[k]; Fd[k] = F[k]; }
-            matmul(Mdd, Fd, Ft);
-            svd3(Ft, Uu, s, V);
-            if (!(s[2] > 0.0)) {
+              for (int k = 0; k < 9; k++) { R.U[k] = (float)R2.U[k]; R.V[k] = (float)R2.V[k]; }
+#pragma unroll
+              for (int a = 0; a < 3; a++) { R.e[a] = (float)R2.e[a]; R.ep[a] = (float)R2.ep[a]; }
+            }
+#pragma unroll
+            for (int k = 0; k < 9; k++) F[k] = Fn[k];
+            if (st == PLASTIC_SIGMA) {
               atomicOr(P.err, ERR_SAND_SIGMA);
               ok = false;
-#pragma unroll
-              for (int k = 0; k < 9; k++) F[k] = (float)Ft[k];
-            } else if (M.kind == KIND_BOX) {
-              double gg[3], Fo[9];
-              const bool clamped = box_clamp(s, M, gg);
-              if (clamped) usv(Uu, gg, V, Fo);
-#pragma unroll
-              for (int k = 0; k < 9; k++) F[k] = (float)(clamped ? Fo[k] : Ft[k]);
             } else {
-              double e[3] = {log(s[0]), log(s[1]), log(s[2])}, ep[3];
-              DPInfo I;
-              plastic_project(e, M, ep, I);
-              if (FEAT != FEAT_NONE && M.kind == KIND_SAND && I.cse == 2) {
+              have_tau = MODE == MODE_FUSED && M.kind != KIND_BOX;
+              if (FEAT != FEAT_NONE && M.kind == KIND_SAND && R.cse == 2) {
                 cone = true;
 #pragma unroll
-                for (int a = 0; a < 3; a++) { xin[a] = (float)e[a]; eex[a] = (float)ep[a]; }
+                for (int a = 0; a < 3; a++) { xin[a] = R.e[a]; eex[a] = R.ep[a]; }
                 xin[3] = M.alpha;
                 xin[4] = M.coh;
                 xin[5] = M.kappa;
                 if (FEAT == FEAT_CLOSURE) {
 #pragma unroll
-                  for (int k = 0; k < 9; k++) { Uk[k] = Uu[k]; Vk[k] = V[k]; }
+                  for (int k = 0; k < 9; k++) { Uk[k] = R.U[k]; Vk[k] = R.V[k]; }
                 }
-              }
-              double gg[3], Fo[9];
-              if (I.cse == 0) {
-#pragma unroll
-                for (int k = 0; k < 9; k++) F[k] = (float)Ft[k];
-              } else {
-#pragma unroll
-                for (int a = 0; a < 3; a++) gg[a] = exp(ep[a]);
-                usv(Uu, gg, V, Fo);
-#pragma unroll
-                for (int k = 0; k < 9; k++) F[k] = (float)Fo[k];
-              }
-              if (MODE == MODE_FUSED) {
-                // Hencky stress of the projected state from the same SVD
-                double tr = ep[0] + ep[1] + ep[2];
-                double h[3];
-#pragma unroll
-                for (int a = 0; a < 3; a++) h[a] = 2.0 * (double)M.mu * ep[a] + (double)M.lam * tr;
-#pragma unroll
-                for (int i = 0; i < 3; i++)
-#pragma unroll
-                  for (int jj = 0; jj < 3; jj++)
-                    tau[i * 3 + jj] = (float)(Uu[i * 3] * h[0] * Uu[jj * 3] + Uu[i * 3 + 1] * h[1] * Uu[jj * 3 + 1] +
-                                              Uu[i * 3 + 2] * h[2] * Uu[jj * 3 + 2]);
-                have_tau = true;
               }
             }
           }
@@ -554,6 +571,7 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
           ok = false;
         }
       }
+      if (MODE == MODE_G2P && c0 + NT < count) prefetch(c0 + NT);
       if (FEAT == FEAT_LOG) {
         // append the exact cone-case samples, one counter atomic per wavefront
         const unsigned long long m = __ballot(cone);
@@ -593,22 +611,11 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
             const double r = fabs(f) + fabs(((double)yp[0] + yp[1] + yp[2]) - ((double)xin[0] + xin[1] + xin[2]));
             accepted = r <= (double)A.closure_tol && isfinite(r);
             if (accepted) {
-              double gg[3] = {exp((double)yp[0]), exp((double)yp[1]), exp((double)yp[2])}, Fo[9];
+              float gg[3] = {expf(yp[0]), expf(yp[1]), expf(yp[2])}, Fo[9];
               usv(Uk, gg, Vk, Fo);
 #pragma unroll
-              for (int k = 0; k < 9; k++) F[k] = (float)Fo[k];
-              if (MODE == MODE_FUSED) {
-                const double trp = (double)yp[0] + yp[1] + yp[2];
-                double h[3];
-#pragma unroll
-                for (int a = 0; a < 3; a++) h[a] = 2.0 * (double)M.mu * yp[a] + (double)M.lam * trp;
-#pragma unroll
-                for (int i = 0; i < 3; i++)
-#pragma unroll
-                  for (int jj = 0; jj < 3; jj++)
-                    tau[i * 3 + jj] = (float)(Uk[i * 3] * h[0] * Uk[jj * 3] + Uk[i * 3 + 1] * h[1] * Uk[jj * 3 + 1] +
-                                              Uk[i * 3 + 2] * h[2] * Uk[jj * 3 + 2]);
-              }
+              for (int k = 0; k < 9; k++) F[k] = Fo[k];
+              if (MODE == MODE_FUSED) hencky_tau(Uk, yp, M, tau);
               // the corrected F goes to the output slot written above
               if (dst < (uint32_t)N) {
 #pragma unroll
@@ -644,7 +651,7 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
         float Am[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, mvp[3] = {0, 0, 0}, bnd[4] = {0, 0, 0, 0};
         if (ok) {
           if (liquid) stress_liquid(J, C, M, tau);
-          else if (!have_tau && !stress_solid(F, M, tau)) atomicOr(P.err, ERR_SAND_SIGMA);
+          else if (!have_tau && !stress_solid_fast(F, M, tau)) atomicOr(P.err, ERR_SAND_SIGMA);
           const float scl = -P.dt * M.vol * 4.f * P.inv_dx * P.inv_dx;
 #pragma unroll
           for (int k = 0; k < 9; k++) Am[k] = scl * tau[k] + M.mass * C[k];
@@ -669,23 +676,20 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
         // consumed after the scatter, so the atomic's latency is hidden
         WaveRank WR = {0, 0, 0};
         if (MODE == MODE_FUSED) WR = rank_issue(A.counts, nkey, counted && has);
-        // chunk-wide bound sums and box (wave shuffles, then 4 waves in LDS)
-        int clo[3], chi[3];
+        // chunk-wide bound sums and box: DPP reductions over the wavefront,
+        // then the waves' results combined in LDS.  The box is kept as one
+        // bit per occupied stencil origin and axis (bit lb_a of byte a; lb
+        // is at most TILE - 3 = 7), so that one OR gives it.
+        const uint32_t obits = ok ? ((1u << lb[0]) | (1u << (8 + lb[1])) | (1u << (16 + lb[2]))) : 0u;
+        const uint32_t wbits = wave_or(obits);
+        float wb[4];
 #pragma unroll
-        for (int a = 0; a < 3; a++) { clo[a] = ok ? lb[a] : 1 << 20; chi[a] = ok ? lb[a] : -(1 << 20); }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-          for (int q = 0; q < 4; q++) bnd[q] += __shfl_xor(bnd[q], off);
-#pragma unroll
-          for (int a = 0; a < 3; a++) { clo[a] = min(clo[a], __shfl_xor(clo[a], off)); chi[a] = max(chi[a], __shfl_xor(chi[a], off)); }
-        }
+        for (int q = 0; q < 4; q++) wb[q] = wave_sum(bnd[q]);
         const int wv = tid >> 6;
         if ((tid & 63) == 0) {
 #pragma unroll
-          for (int q = 0; q < 4; q++) s_red[wv * 4 + q] = bnd[q];
-#pragma unroll
-          for (int a = 0; a < 3; a++) { s_ired[wv * 6 + a] = clo[a]; s_ired[wv * 6 + 3 + a] = chi[a]; }
+          for (int q = 0; q < 4; q++) s_red[wv * 4 + q] = wb[q];
+          s_ired[wv] = (int)wbits;
         }
         __syncthreads();
         if (tid == 0) {
@@ -702,11 +706,13 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
             s_scale[q] = ldexpf(1.f, 30 - e);
             s_scale[4 + q] = ldexpf(1.f, e - 30);
           }
+          uint32_t cb = 0;
+#pragma unroll
+          for (int w = 0; w < NW; w++) cb |= (uint32_t)s_ired[w];
 #pragma unroll
           for (int a = 0; a < 3; a++) {
-            int lo = s_ired[a], hi = s_ired[3 + a];
-#pragma unroll
-            for (int w = 1; w < NW; w++) { lo = min(lo, s_ired[w * 6 + a]); hi = max(hi, s_ired[w * 6 + 3 + a]); }
+            const uint32_t ab = (cb >> (8 * a)) & 0xffu;
+            const int lo = ab ? __ffs(ab) - 1 : 1 << 20, hi = ab ? 31 - __clz(ab) : -(1 << 20);
             s_ired[RB + a] = lo;
             s_ired[RB + 3 + a] = hi;
             if (lo <= hi) { s_lo[a] = min(s_lo[a], lo); s_hi[a] = max(s_hi[a], hi); }
@@ -749,6 +755,7 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
             }
           }
         }
+        if (c0 + NT < count) prefetch(c0 + NT);
         __syncthreads();
         {
           // flush the chunk's box into the float tile and clear the integers

@@ -51,33 +51,48 @@ template <typename T> MPM_DI void cof3(const T* A, T* K) {
   K[8] = A[0] * A[4] - A[1] * A[3];
 }
 
+// Precision helpers: the FP32 versions use the hardware reciprocal, square
+// root and reciprocal square root (about 1 ulp; no denormal inputs arise).
+MPM_DI double t_rsqrt(double x) { return rsqrt(x); }
+MPM_DI float t_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+MPM_DI double t_sqrt(double x) { return sqrt(x); }
+MPM_DI float t_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+MPM_DI double t_div(double a, double b) { return a / b; }
+MPM_DI float t_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+MPM_DI double t_abs(double x) { return fabs(x); }
+MPM_DI float t_abs(float x) { return fabsf(x); }
+MPM_DI double t_log(double x) { return log(x); }
+MPM_DI float t_log(float x) { return logf(x); }
+MPM_DI double t_exp(double x) { return exp(x); }
+MPM_DI float t_exp(float x) { return expf(x); }
+
 // ---------------------------------------------------------------------------
 // Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (Golub and
 // Van Loan, "Matrix Computations", section 8.5): A <- J^T A J, V <- V J.
 // ---------------------------------------------------------------------------
-MPM_DI void jacobi_rotate(double* A, double* V, int p, int q) {
-  double apq = A[p * 3 + q];
-  if (apq == 0.0) return;
-  double app = A[p * 3 + p], aqq = A[q * 3 + q];
+template <typename T> MPM_DI void jacobi_rotate(T* A, T* V, int p, int q) {
+  T apq = A[p * 3 + q];
+  if (apq == T(0)) return;
+  T app = A[p * 3 + p], aqq = A[q * 3 + q];
   // t = tan(theta) of the smaller rotation angle: with d = aqq - app and
   // e = 2 apq, t = sign(d) e / (|d| + sqrt(d^2 + e^2)) (one division, one
   // square root); c = 1/sqrt(1 + t^2) keeps c^2 + s^2 = 1 for whatever t
-  const double d = aqq - app, e = 2.0 * apq;
-  double t = (d >= 0.0 ? e : -e) / (fabs(d) + sqrt(d * d + e * e));
-  double c = rsqrt(1.0 + t * t);
-  double s = t * c;
+  const T d = aqq - app, e = T(2) * apq;
+  T t = t_div(d >= T(0) ? e : -e, t_abs(d) + t_sqrt(d * d + e * e));
+  T c = t_rsqrt(T(1) + t * t);
+  T s = t * c;
   A[p * 3 + p] = app - t * apq;
   A[q * 3 + q] = aqq + t * apq;
-  A[p * 3 + q] = 0.0;
-  A[q * 3 + p] = 0.0;
+  A[p * 3 + q] = T(0);
+  A[q * 3 + p] = T(0);
   int r = 3 - p - q;
-  double arp = A[r * 3 + p], arq = A[r * 3 + q];
-  double nrp = c * arp - s * arq, nrq = s * arp + c * arq;
+  T arp = A[r * 3 + p], arq = A[r * 3 + q];
+  T nrp = c * arp - s * arq, nrq = s * arp + c * arq;
   A[r * 3 + p] = nrp; A[p * 3 + r] = nrp;
   A[r * 3 + q] = nrq; A[q * 3 + r] = nrq;
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    double vp = V[k * 3 + p], vq = V[k * 3 + q];
+    T vp = V[k * 3 + p], vq = V[k * 3 + q];
     V[k * 3 + p] = c * vp - s * vq;
     V[k * 3 + q] = s * vp + c * vq;
   }
@@ -86,69 +101,75 @@ MPM_DI void jacobi_rotate(double* A, double* V, int p, int q) {
 // Signed SVD F = U diag(s) V^T with U, V in SO(3), s0 >= s1 >= |s2|, and the
 // sign of det F carried by s2.  V and s^2 come from the eigen-decomposition
 // of F^T F; U from the columns of F V (Gram-Schmidt, u2 = u0 x u1).
-MPM_DI void svd3(const double* F, double* U, double* s, double* V) {
-  double A[9];
+// In FP64 the sweeps stop once the off-diagonal part is below 1e-12 of the
+// diagonal (eigenvalues then exact to about 1e-24 relative where separated,
+// 1e-12 where they nearly coincide).  In FP32 they stop at 1e-7, the
+// rounding level, within at most 6 sweeps.  Returns whether that happened.
+template <typename T> MPM_DI bool svd3(const T* F, T* U, T* s, T* V) {
+  constexpr bool dbl = sizeof(T) == 8;
+  constexpr int max_sweeps = dbl ? 12 : 6;
+  const T tol2 = dbl ? T(1e-24) : T(1e-14);
+  T A[9];
   matmul_tn(F, F, A);
   mat_eye(V);
-  double scale = A[0] * A[0] + A[4] * A[4] + A[8] * A[8] + 1e-300;
-  // stop once the off-diagonal part is below 1e-12 of the diagonal: the
-  // eigenvalues are then exact to about 1e-24 relative where they are
-  // separated and to 1e-12 where they (nearly) coincide
-  for (int sweep = 0; sweep < 12; sweep++) {
-    double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
-    if (off <= 1e-24 * scale) break;
+  T scale = A[0] * A[0] + A[4] * A[4] + A[8] * A[8] + (dbl ? T(1e-300) : T(1e-36));
+  bool conv = false;
+  for (int sweep = 0; sweep < max_sweeps; sweep++) {
+    T off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    if (off <= tol2 * scale) { conv = true; break; }
     jacobi_rotate(A, V, 0, 1);
     jacobi_rotate(A, V, 0, 2);
     jacobi_rotate(A, V, 1, 2);
   }
-  double lam[3] = {A[0], A[4], A[8]};
+  if (!conv) conv = A[1] * A[1] + A[2] * A[2] + A[5] * A[5] <= tol2 * scale;
+  T lam[3] = {A[0], A[4], A[8]};
   // sort descending, permuting the columns of V
 #pragma unroll
   for (int pass = 0; pass < 2; pass++) {
 #pragma unroll
     for (int i = 0; i < 2; i++) {
       if (lam[i] < lam[i + 1]) {
-        double tl = lam[i]; lam[i] = lam[i + 1]; lam[i + 1] = tl;
+        T tl = lam[i]; lam[i] = lam[i + 1]; lam[i + 1] = tl;
 #pragma unroll
-        for (int k = 0; k < 3; k++) { double tv = V[k * 3 + i]; V[k * 3 + i] = V[k * 3 + i + 1]; V[k * 3 + i + 1] = tv; }
+        for (int k = 0; k < 3; k++) { T tv = V[k * 3 + i]; V[k * 3 + i] = V[k * 3 + i + 1]; V[k * 3 + i + 1] = tv; }
       }
     }
   }
-  if (det3(V) < 0.0) {
+  if (det3(V) < T(0)) {
 #pragma unroll
     for (int k = 0; k < 3; k++) V[k * 3 + 2] = -V[k * 3 + 2];
   }
-  double B[9];
+  T B[9];
   matmul(F, V, B);
-  double b0[3] = {B[0], B[3], B[6]}, b1[3] = {B[1], B[4], B[7]}, b2[3] = {B[2], B[5], B[8]};
+  T b0[3] = {B[0], B[3], B[6]}, b1[3] = {B[1], B[4], B[7]}, b2[3] = {B[2], B[5], B[8]};
   // norms and normalisations from one reciprocal square root each
-  const double q0 = b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2];
-  double n0 = 0.0;
-  double u0[3], u1[3], u2[3];
-  if (q0 > 0.0) {
-    const double r0 = rsqrt(q0);
+  const T q0 = b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2];
+  T n0 = T(0);
+  T u0[3], u1[3], u2[3];
+  if (q0 > T(0)) {
+    const T r0 = t_rsqrt(q0);
     n0 = q0 * r0;
     u0[0] = b0[0] * r0; u0[1] = b0[1] * r0; u0[2] = b0[2] * r0;
   } else {
-    u0[0] = 1; u0[1] = 0; u0[2] = 0;
+    u0[0] = T(1); u0[1] = T(0); u0[2] = T(0);
   }
-  double d01 = u0[0] * b1[0] + u0[1] * b1[1] + u0[2] * b1[2];
-  double w1[3] = {b1[0] - d01 * u0[0], b1[1] - d01 * u0[1], b1[2] - d01 * u0[2]};
-  const double q1 = w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2];
-  double n1 = 0.0;
-  if (q1 > 1e-28 * q0 && q1 > 0.0) {
-    const double r1 = rsqrt(q1);
+  T d01 = u0[0] * b1[0] + u0[1] * b1[1] + u0[2] * b1[2];
+  T w1[3] = {b1[0] - d01 * u0[0], b1[1] - d01 * u0[1], b1[2] - d01 * u0[2]};
+  const T q1 = w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2];
+  T n1 = T(0);
+  if (q1 > (dbl ? T(1e-28) : T(1e-12)) * q0 && q1 > T(0)) {
+    const T r1 = t_rsqrt(q1);
     n1 = q1 * r1;
     u1[0] = w1[0] * r1; u1[1] = w1[1] * r1; u1[2] = w1[2] * r1;
   } else {
     // any unit vector orthogonal to u0
-    double a[3] = {0, 0, 0};
-    int k = (fabs(u0[0]) < 0.57) ? 0 : ((fabs(u0[1]) < 0.57) ? 1 : 2);
-    a[k] = 1.0;
-    double d = a[0] * u0[0] + a[1] * u0[1] + a[2] * u0[2];
+    T a[3] = {T(0), T(0), T(0)};
+    int k = (t_abs(u0[0]) < T(0.57)) ? 0 : ((t_abs(u0[1]) < T(0.57)) ? 1 : 2);
+    a[k] = T(1);
+    T d = a[0] * u0[0] + a[1] * u0[1] + a[2] * u0[2];
     w1[0] = a[0] - d * u0[0]; w1[1] = a[1] - d * u0[1]; w1[2] = a[2] - d * u0[2];
-    double nn = sqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2]);
-    u1[0] = w1[0] / nn; u1[1] = w1[1] / nn; u1[2] = w1[2] / nn;
+    T rn = t_rsqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2]);
+    u1[0] = w1[0] * rn; u1[1] = w1[1] * rn; u1[2] = w1[2] * rn;
     n1 = u1[0] * b1[0] + u1[1] * b1[1] + u1[2] * b1[2];
   }
   u2[0] = u0[1] * u1[2] - u0[2] * u1[1];
@@ -159,10 +180,11 @@ MPM_DI void svd3(const double* F, double* U, double* s, double* V) {
   s[2] = u2[0] * b2[0] + u2[1] * b2[1] + u2[2] * b2[2];
 #pragma unroll
   for (int k = 0; k < 3; k++) { U[k * 3 + 0] = u0[k]; U[k * 3 + 1] = u1[k]; U[k * 3 + 2] = u2[k]; }
+  return conv;
 }
 
 // U diag(g) V^T
-MPM_DI void usv(const double* U, const double* g, const double* V, double* out) {
+template <typename T> MPM_DI void usv(const T* U, const T* g, const T* V, T* out) {
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll

@@ -86,6 +86,19 @@ MPM_DI bool corotated_kind(int kind) { return kind == KIND_ELASTIC || kind == KI
 // body's particles too: the rigid projection that follows replaces F).
 MPM_DI bool elastic_update_kind(int kind) { return kind == KIND_ELASTIC || kind == KIND_RIGID; }
 
+// Hencky Kirchhoff stress U diag(2 mu eps + lam tr eps) U^T.
+template <typename T> MPM_DI void hencky_tau(const T* U, const T* e, const MatDev& M, float* tau) {
+  const T tr = e[0] + e[1] + e[2];
+  T h[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) h[a] = T(2) * (T)M.mu * e[a] + (T)M.lam * tr;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+      tau[i * 3 + j] = (float)(U[i * 3] * h[0] * U[j * 3] + U[i * 3 + 1] * h[1] * U[j * 3 + 1] + U[i * 3 + 2] * h[2] * U[j * 3 + 2]);
+}
+
 // The stress from a given signed SVD F = U diag(s) V^T of the FP64 copy F.
 MPM_DI bool stress_solid_usv(const double* F, const double* U, const double* s, const double* V, const MatDev& M,
                              float* tau) {
@@ -124,6 +137,32 @@ MPM_DI bool stress_solid(const float* Ff, const MatDev& M, float* tau) {
   for (int k = 0; k < 9; k++) F[k] = (double)Ff[k];
   svd3(F, U, s, V);
   return stress_solid_usv(F, U, s, V, M, tau);
+}
+
+// The solid stress with an FP32 SVD, redone in FP64 when F is
+// ill-conditioned (s2 < s0/4) or the FP32 sweeps do not converge.
+// Returns false when a Hencky solid has a singular value that is not positive.
+MPM_DI bool stress_solid_fast(const float* Ff, const MatDev& M, float* tau) {
+  float U[9], s[3], V[9];
+  const bool conv = svd3(Ff, U, s, V);
+  if (!conv || !(s[2] > 0.25f * s[0])) return stress_solid(Ff, M, tau);
+  if (corotated_kind(M.kind)) {
+    float R[9], D[9], T[9];
+    matmul_nt(U, V, R);
+#pragma unroll
+    for (int k = 0; k < 9; k++) D[k] = Ff[k] - R[k];
+    matmul_nt(D, Ff, T);
+    const float J = s[0] * s[1] * s[2];
+    const float pr = M.lam * J * (J - 1.f), m2 = 2.f * M.mu;
+#pragma unroll
+    for (int k = 0; k < 9; k++) tau[k] = m2 * T[k] + ((k % 4 == 0) ? pr : 0.f);
+    return true;
+  }
+  float e[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) e[a] = logf(s[a]);
+  hencky_tau(U, e, M, tau);
+  return true;
 }
 
 // Adjoint of the solid stress, from a given signed SVD of the FP64 copy F.
@@ -206,32 +245,33 @@ MPM_DI void stress_solid_adjoint(const float* Ff, const MatDev& M, const float* 
 // map is eps' = t/3 1 + k0 + beta |dev| nh - k1 t nh with nh = dev/|dev|, so
 // its Jacobian is 11^T/3 - k1 nh 1^T + beta (I - nh nh^T - 11^T/3) and
 // eps'_i - eps'_j = beta (eps_i - eps_j).
-struct DPInfo {
+template <typename T> struct DPInfoT {
   int cse;            // 0 inside, 1 apex (Drucker-Prager only), 2 flowing
-  double t, ndev, beta, k1;
-  double nh[3];
+  T t, ndev, beta, k1;
+  T nh[3];
 };
+using DPInfo = DPInfoT<double>;
 
-MPM_DI void dp_project(const double* e, const MatDev& M, double* ep, DPInfo& I) {
-  double c = M.coh;
-  double es[3] = {e[0] - c, e[1] - c, e[2] - c};
-  double t = es[0] + es[1] + es[2];
-  double dev[3] = {es[0] - t / 3.0, es[1] - t / 3.0, es[2] - t / 3.0};
-  double nd = sqrt(dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]);
-  double ka = (double)M.kappa * (double)M.alpha;
-  double dg = nd + ka * t;
+template <typename T> MPM_DI void dp_project(const T* e, const MatDev& M, T* ep, DPInfoT<T>& I) {
+  T c = M.coh;
+  T es[3] = {e[0] - c, e[1] - c, e[2] - c};
+  T t = es[0] + es[1] + es[2];
+  T dev[3] = {es[0] - t / T(3), es[1] - t / T(3), es[2] - t / T(3)};
+  T nd = t_sqrt(dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]);
+  T ka = (T)M.kappa * (T)M.alpha;
+  T dg = nd + ka * t;
   I.t = t; I.ndev = nd;
-  if (t > 0.0) {
-    I.cse = 1; I.beta = 0.0;
+  if (t > T(0)) {
+    I.cse = 1; I.beta = T(0);
 #pragma unroll
-    for (int a = 0; a < 3; a++) { ep[a] = c; I.nh[a] = 0.0; }
-  } else if (dg <= 0.0) {
-    I.cse = 0; I.beta = 1.0;
+    for (int a = 0; a < 3; a++) { ep[a] = c; I.nh[a] = T(0); }
+  } else if (dg <= T(0)) {
+    I.cse = 0; I.beta = T(1);
 #pragma unroll
-    for (int a = 0; a < 3; a++) { ep[a] = e[a]; I.nh[a] = 0.0; }
+    for (int a = 0; a < 3; a++) { ep[a] = e[a]; I.nh[a] = T(0); }
   } else {
     I.cse = 2;
-    const double ind = 1.0 / nd;
+    const T ind = t_div(T(1), nd);
 #pragma unroll
     for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] * ind; ep[a] = es[a] - dg * I.nh[a] + c; }
     I.beta = -ka * t * ind;
@@ -241,41 +281,105 @@ MPM_DI void dp_project(const double* e, const MatDev& M, double* ep, DPInfo& I) 
 
 // Von Mises return (section 3.2, non-Newtonian liquid): |dev| <= r inside,
 // else the deviatoric part is scaled back to radius r, the trace kept.
-MPM_DI void vm_project(const double* e, const MatDev& M, double* ep, DPInfo& I) {
-  const double t = e[0] + e[1] + e[2];
-  const double dev[3] = {e[0] - t / 3.0, e[1] - t / 3.0, e[2] - t / 3.0};
-  const double nd = sqrt(dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]);
-  const double r = (double)M.yrad;
-  I.t = t; I.ndev = nd; I.k1 = 0.0;
+template <typename T> MPM_DI void vm_project(const T* e, const MatDev& M, T* ep, DPInfoT<T>& I) {
+  const T t = e[0] + e[1] + e[2];
+  const T dev[3] = {e[0] - t / T(3), e[1] - t / T(3), e[2] - t / T(3)};
+  const T nd = t_sqrt(dev[0] * dev[0] + dev[1] * dev[1] + dev[2] * dev[2]);
+  const T r = (T)M.yrad;
+  I.t = t; I.ndev = nd; I.k1 = T(0);
   if (nd <= r) {
-    I.cse = 0; I.beta = 1.0;
+    I.cse = 0; I.beta = T(1);
 #pragma unroll
-    for (int a = 0; a < 3; a++) { ep[a] = e[a]; I.nh[a] = 0.0; }
+    for (int a = 0; a < 3; a++) { ep[a] = e[a]; I.nh[a] = T(0); }
   } else {
     I.cse = 2;
-    const double ind = 1.0 / nd;
+    const T ind = t_div(T(1), nd);
     I.beta = r * ind;
 #pragma unroll
-    for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] * ind; ep[a] = t * (1.0 / 3.0) + r * I.nh[a]; }
+    for (int a = 0; a < 3; a++) { I.nh[a] = dev[a] * ind; ep[a] = t * (T(1) / T(3)) + r * I.nh[a]; }
   }
 }
 
 // Box yield (section 3.2's plastic material, Stomakhin et al. 2013): the
 // singular values clamped to [box_lo, box_hi]; returns whether any changed.
-MPM_DI bool box_clamp(const double* s, const MatDev& M, double* g) {
+template <typename T> MPM_DI bool box_clamp(const T* s, const MatDev& M, T* g) {
   bool changed = false;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    g[a] = fmin(fmax(s[a], (double)M.box_lo), (double)M.box_hi);
+    g[a] = fmin(fmax(s[a], (T)M.box_lo), (T)M.box_hi);
     changed |= g[a] != s[a];
   }
   return changed;
 }
 
 // The return map of a plastic material (sand or von Mises).
-MPM_DI void plastic_project(const double* e, const MatDev& M, double* ep, DPInfo& I) {
+template <typename T> MPM_DI void plastic_project(const T* e, const MatDev& M, T* ep, DPInfoT<T>& I) {
   if (M.kind == KIND_VONMISES) vm_project(e, M, ep, I);
   else dp_project(e, M, ep, I);
+}
+
+// ---------------------------------------------------------------------------
+// G2P update of a plastic solid (sand, von Mises, Box yield) in precision T:
+// the trial F_tr = Md F, its signed SVD, the return map, F' and, for the
+// Hencky kinds, the Kirchhoff stress of F' from the same SVD.
+// ---------------------------------------------------------------------------
+enum { PLASTIC_OK = 0, PLASTIC_SIGMA = 1, PLASTIC_RETRY = 2 };
+
+template <typename T> struct PlasticStep {
+  T U[9], V[9];     // SVD of F_tr
+  T e[3], ep[3];    // trial and returned log singular values (Hencky kinds)
+  int cse;          // return-map case (0 inside, 1 apex, 2 flowing)
+};
+
+// In FP32 the SVD comes from F_tr^T F_tr, whose rounding costs the smallest
+// singular value eps (s0/s2)^2 of relative accuracy; a trial state with
+// s2 < s0/4 (relative error above 16 eps) or an unconverged sweep returns
+// PLASTIC_RETRY without output so that the caller redoes it in FP64.
+// PLASTIC_SIGMA: a singular value is not positive (F' = F_tr, no stress).
+template <typename T, bool TAU>
+MPM_DI int plastic_step(const float* Md, const float* Fin, const MatDev& M, float* Fo, float* tau, PlasticStep<T>& R) {
+  constexpr bool dbl = sizeof(T) == 8;
+  T Ft[9], s[3];
+  {
+    T Mdd[9], Fd[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) { Mdd[k] = (T)Md[k]; Fd[k] = (T)Fin[k]; }
+    matmul(Mdd, Fd, Ft);
+  }
+  const bool conv = svd3(Ft, R.U, s, R.V);
+  if (!dbl && (!conv || !(s[2] > T(0.25) * s[0]))) return PLASTIC_RETRY;
+  R.cse = 0;
+  if (!(s[2] > T(0))) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) Fo[k] = (float)Ft[k];
+    return PLASTIC_SIGMA;
+  }
+  if (M.kind == KIND_BOX) {
+    T gg[3], Fn[9];
+    const bool clamped = box_clamp(s, M, gg);
+    if (clamped) usv(R.U, gg, R.V, Fn);
+#pragma unroll
+    for (int k = 0; k < 9; k++) Fo[k] = (float)(clamped ? Fn[k] : Ft[k]);
+    return PLASTIC_OK;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; a++) R.e[a] = t_log(s[a]);
+  DPInfoT<T> I;
+  plastic_project(R.e, M, R.ep, I);
+  R.cse = I.cse;
+  if (I.cse == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) Fo[k] = (float)Ft[k];
+  } else {
+    T gg[3], Fn[9];
+#pragma unroll
+    for (int a = 0; a < 3; a++) gg[a] = t_exp(R.ep[a]);
+    usv(R.U, gg, R.V, Fn);
+#pragma unroll
+    for (int k = 0; k < 9; k++) Fo[k] = (float)Fn[k];
+  }
+  if (TAU) hencky_tau(R.U, R.ep, M, tau);
+  return PLASTIC_OK;
 }
 
 // ---------------------------------------------------------------------------
