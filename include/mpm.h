@@ -142,45 +142,68 @@ typedef struct {
   int32_t requires_grad;     /* record checkpoints during mpm_step */
 } mpm_desc;
 
-/* Bytes of device workspace needed for this description (0 on bad input). */
+/* Bytes of device workspace needed for this description (0 on bad input):
+ * the sorted particle buffers and block grid of the step (section 3.2) and,
+ * with requires_grad, the checkpoints and segment records of the adjoint
+ * (Appendix A). */
 size_t mpm_workspace_bytes(const mpm_desc* d);
 
-/* Create a context on the current device.  workspace_dev must hold at least
- * mpm_workspace_bytes(d) bytes, 256-byte aligned.  stream is a hipStream_t
- * (NULL = the default stream). */
+/* Create a context on the current device for the scene d: the simulator of
+ * section 3.2 with the materials of Table 4 (Appendix B.1) and the
+ * end-effector of section 4.2.  workspace_dev must hold at least
+ * mpm_workspace_bytes(d) bytes, 256-byte aligned (else MPM_EWORKSPACE; a bad
+ * description gives MPM_EINVAL).  stream is a hipStream_t (NULL = the
+ * default stream).  *out receives the host context. */
 int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* stream, mpm_ctx** out);
 
 /* Borrow the particle state arrays (device) and reset the clock to t = 0,
- * with the cylinder at its initial pose.  mpm_step advances these arrays in
- * place.  Rigid bodies take their rest shapes from this state. */
+ * with the cylinder at its initial pose.  The state is the MDP state of
+ * section 4.2 (particle positions and velocities) plus the internal C, F, J
+ * that MLS-MPM carries (section 3.2).  mpm_step advances these arrays in
+ * place.  Rigid bodies take their rest shapes from this state.  NULL
+ * pointers give MPM_EINVAL. */
 int mpm_set_state(mpm_ctx* c, const mpm_state* st);
 
 /* Copy n steps of actions (device, [n][n_scenes][6]: ux uy uz wx wy wz in
- * the world frame) to steps t0..t0+n-1. */
+ * the world frame) to steps t0..t0+n-1.  The action space of section 4.2:
+ * the end-effector's translational and angular velocity, one 6-vector per
+ * step.  A range outside [0, horizon) gives MPM_EINVAL. */
 int mpm_set_actions(mpm_ctx* c, int32_t t0, int32_t n, const float* actions_dev);
 
-/* Advance n_steps steps from the current clock t, applying actions t..t+n-1.
- * The state at a step boundary is the state after grid-to-particle transfer.
- * Records checkpoints every ckpt_every steps when requires_grad is set. */
+/* Advance n_steps steps from the current clock t, applying actions t..t+n-1:
+ * the transition function of section 4.2, one MLS-MPM substep each
+ * (section 3.2: particle-to-grid transfer with the material stress, grid
+ * update with gravity, slip walls and the soft contact of section 5.1,
+ * grid-to-particle transfer updating v, C, F or J and x).  The state at a
+ * step boundary is the state after grid-to-particle transfer.  Records
+ * checkpoints every ckpt_every steps when requires_grad is set (Appendix A).
+ * MPM_ESTATE without a state or with an action of the range unset;
+ * MPM_EDOMAIN when a kernel flags an invalid state (MPM_ERR_* bits). */
 int mpm_step(mpm_ctx* c, int32_t n_steps);
 
-/* Reverse-mode gradient of the steps 0..t-1 recorded since mpm_set_state.
+/* Reverse-mode gradient of the steps 0..t-1 recorded since mpm_set_state:
+ * the differentiable simulation of section 3.3 and Appendix A (hand-written
+ * gradients of the SVD-based stresses and projections, checkpoints every
+ * ckpt_every steps recomputed segment by segment).
  * grad_T holds dL/d(state at t) (x and v required, C/F/J may be NULL = 0);
  * grad_actions_dev receives dL/d(actions) [t][n_scenes][6]; grad_0, if not
  * NULL, receives dL/d(state at 0) (x, v, C, F, J).  Does not change the
  * forward state. */
 int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_dev, mpm_state* grad_0);
 
-/* Blob loss of the liquid particles of the current state:
+/* Blob loss of the liquid particles of the current state (a particle-
+ * distribution loss in the spirit of Appendix B.2's task losses):
  * L = mean_liquid |x_p - mu_g|^2 + 3 sigma_g^2 (expected squared distance to a
  * Gaussian N(mu_g, sigma_g^2 I)).  loss_dev receives one float; if grad_out
  * is not NULL its x array receives dL/dx (zero for non-liquid particles). */
 int mpm_loss_blob(mpm_ctx* c, const float mu_g[3], float sigma_g, float* loss_dev, mpm_state* grad_out);
 
-/* Current clock (number of steps since mpm_set_state). */
+/* Current clock (number of steps since mpm_set_state, the MDP's time step
+ * index of section 4.2). */
 int mpm_clock(const mpm_ctx* c, int32_t* t_out);
 
-/* Error bits (MPM_ERR_*) seen by the last call that returned MPM_EDOMAIN. */
+/* Error bits (MPM_ERR_*) seen by the last call that returned MPM_EDOMAIN.
+ * Invalid states are reported, never clamped. */
 int mpm_last_error_bits(const mpm_ctx* c, int32_t* bits_out);
 
 /* Measurement: when enabled, every launch of the step's dominant kernel
@@ -205,10 +228,27 @@ enum {
   MPM_OPT_PART_THREADS = 2,   /* 128, 256 or 512 threads per particle workgroup */
   MPM_OPT_PART_WGS = 3,       /* particle workgroups per launch (persistent, 64..65536) */
   MPM_OPT_GRID_WGS = 4,       /* grid-update workgroups per launch (64..65536) */
-  MPM_OPT_ADJOINT = 5         /* 0: tiled (default), 1: plain */
+  MPM_OPT_ADJOINT = 5,        /* 0: tiled (default), 1: plain */
+  MPM_OPT_N_KEYS = 6          /* read only: grid blocks of the context (rows of a sort snapshot list) */
 };
 int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value);
 int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value);
+
+/* Integer outputs of the block sort that orders the particles for the
+ * step's transfers (section 3.2's particle-grid transfers, run on particles
+ * grouped by 4^3-node grid block), for checking it.  which = 0: sorts the
+ * state set by mpm_set_state (the import that starts every mpm_step) and
+ * writes the user indices of the sorted particles (id_dev, N uint32), their
+ * block keys (key_dev, N uint32) and the occupied-block list (list_dev,
+ * MPM_OPT_N_KEYS rows of int32 {key, offset, count, 0}; *n_list_out rows
+ * are valid, in no particular order).  which = 1: writes the user indices
+ * of the sorted buffer the last forward mpm_step call left (key_dev,
+ * list_dev and n_list_out unused, may be NULL; MPM_ESTATE if no such call).
+ * A block key is (scene << 3 kb) | the Morton interleave of the block
+ * coordinates (x bits above y bits above z bits), kb the bits per axis of
+ * ceil(n_grid / 4).  Device arrays are caller-owned; the call synchronises. */
+int mpm_sort_snapshot(mpm_ctx* c, int32_t which, uint32_t* id_dev, uint32_t* key_dev, int32_t* list_dev,
+                      int32_t* n_list_out);
 
 /* Autotuner: times n_steps of the forward path from the current state (the
  * state and the clock are left unchanged; actions t..t+n_steps-1 must be
@@ -218,6 +258,10 @@ int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value);
 int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best);
 
 /* ---- learned closure of the Drucker-Prager cone return (sand) ----------
+ * Not part of the paper, whose sand and plastic models use exact return
+ * maps (section 3.2): an extension that replaces the cone case of the
+ * Drucker-Prager projection (Klar et al. 2016) by a small network, judged
+ * by the exact projection.
  * A 6 -> 64 -> 64 -> 3 MLP (ReLU; BF16 weights, FP32 accumulation on the
  * matrix cores) maps (log singular values of the trial F sorted descending,
  * alpha, c, kappa) to the projected log singular values.  It is trained on

@@ -89,7 +89,10 @@ def node_index(base: torch.Tensor, n: int) -> torch.Tensor:
 # ----------------------------------------------------------------------------
 def signed_svd(F: np.ndarray):
     """F = U diag(s) V^T with U, V proper rotations; the sign of det F is
-    carried by the smallest singular value (LAPACK SVD plus sign fix)."""
+    carried by the smallest singular value (LAPACK SVD plus sign fix).
+    A non-finite F is an invalid state: it is reported, not decomposed."""
+    if not np.isfinite(F).all():
+        raise OracleDomainError("non-finite deformation gradient")
     U, s, Vt = np.linalg.svd(F)
     V = np.swapaxes(Vt, -1, -2).copy()
     U = U.copy()

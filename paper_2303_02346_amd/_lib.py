@@ -34,7 +34,7 @@ class MpmDesc(ctypes.Structure):
 
 EXPORTS = ["mpm_workspace_bytes", "mpm_create", "mpm_set_state", "mpm_set_actions", "mpm_step",
            "mpm_step_backward", "mpm_loss_blob", "mpm_clock", "mpm_last_error_bits", "mpm_timing_enable",
-           "mpm_timing_read", "mpm_set_option", "mpm_get_option", "mpm_autotune", "mpm_log_samples", "mpm_set_closure",
+           "mpm_timing_read", "mpm_set_option", "mpm_get_option", "mpm_sort_snapshot", "mpm_autotune", "mpm_log_samples", "mpm_set_closure",
            "mpm_closure_stats", "mpm_mlp_state_bytes", "mpm_mlp_scratch_bytes", "mpm_mlp_init", "mpm_mlp_train",
            "mpm_mlp_grad", "mpm_mlp_predict", "mpm_mlp_params", "mpm_destroy", "mpm_strerror"]
 
@@ -56,7 +56,7 @@ GAS_EXPORTS = ["gas_workspace_bytes", "gas_create", "gas_set_state", "gas_set_ac
                "gas_step_backward", "gas_sensor_loss", "gas_enable_stats", "gas_solver_residual", "gas_timing_enable",
                "gas_timing_read", "gas_last_error_bits", "gas_clock", "gas_destroy"]
 
-MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS, MPM_OPT_ADJOINT = 1, 2, 3, 4, 5
+MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS, MPM_OPT_ADJOINT, MPM_OPT_N_KEYS = 1, 2, 3, 4, 5, 6
 
 _lib = None
 
@@ -92,6 +92,7 @@ def lib():
     L.mpm_set_option.argtypes = [vp, i32, i32]
     L.mpm_get_option.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.mpm_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.mpm_sort_snapshot.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(i32)]
     u64, i64 = ctypes.c_uint64, ctypes.c_int64
     L.mpm_log_samples.argtypes = [vp, vp, u64, vp]
     L.mpm_set_closure.argtypes = [vp, vp, ctypes.c_float]

@@ -330,7 +330,10 @@ int mpm_create(const mpm_desc* d, void* workspace_dev, size_t ws_bytes, void* st
 
 int mpm_set_state(mpm_ctx* c, const mpm_state* st) {
   if (!c || !st || !st->x || !st->v || !st->C || !st->F || !st->J || !st->mat) return MPM_EINVAL;
-  if (c->has_state && (c->user.x != st->x || c->user.mat != st->mat)) fast_invalidate(c->fast);
+  // captured graphs bake in every state pointer: rebinding any of them drops them
+  if (c->has_state && (c->user.x != st->x || c->user.v != st->v || c->user.C != st->C || c->user.F != st->F ||
+                       c->user.J != st->J || c->user.mat != st->mat))
+    fast_invalidate(c->fast);
   c->user = *st;
   c->has_state = true;
   c->t = 0;
@@ -427,6 +430,7 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
   StepParams P = make_params(c);
   const int N = c->d.n_particles;
   PState us = user_pstate(&c->user, N);
+  c->fast.last_buf = -1;
   launch_pose(c->d.n_scenes, c->t, n_steps, c->d.dt, (const float*)(c->ws + c->L.act), (double*)(c->ws + c->L.pose), c->stream);
   c->timer.name = (c->d.requires_grad && c->plain_adjoint) ? "k_p2g_plain" : "k_g2p2g";
   if (c->d.requires_grad && c->plain_adjoint) {
@@ -570,6 +574,7 @@ int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_d
   const int k = c->d.ckpt_every;
   const int S = c->d.n_scenes;
   StepParams P = make_params(c);
+  c->fast.last_buf = -1;   // the recompute reuses the forward's buffers
   size_t nodes = (size_t)c->d.n_grid * c->d.n_grid * c->d.n_grid * S;
   hipStream_t s = c->stream;
   PState a_cur = packed_state((float*)(c->ws + c->L.adj0), N);
@@ -687,8 +692,24 @@ int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value) {
     case MPM_OPT_PART_WGS: *value = c->fast.part_wgs; return MPM_OK;
     case MPM_OPT_GRID_WGS: *value = c->fast.grid_wgs; return MPM_OK;
     case MPM_OPT_ADJOINT: *value = c->plain_adjoint ? 1 : 0; return MPM_OK;
+    case MPM_OPT_N_KEYS: *value = c->fast.g.n_keys; return MPM_OK;
     default: return MPM_EINVAL;
   }
+}
+
+int mpm_sort_snapshot(mpm_ctx* c, int32_t which, uint32_t* id_dev, uint32_t* key_dev, int32_t* list_dev,
+                      int32_t* n_list_out) {
+  if (!c || !id_dev || (which != 0 && which != 1)) return MPM_EINVAL;
+  if (which == 0 && (!key_dev || !list_dev || !n_list_out)) return MPM_EINVAL;
+  if (!c->has_state) return MPM_ESTATE;
+  StepParams P = make_params(c);
+  int nl = 0;
+  const int rc = fast_sort_snapshot(c->fast, P, user_pstate(&c->user, c->d.n_particles), which, id_dev, key_dev,
+                                    (int4*)list_dev, &nl, c->stream);
+  if (rc == -1) return MPM_ESTATE;
+  if (rc != 0) return MPM_EHIP;
+  if (which == 0) *n_list_out = nl;
+  return finish(c);
 }
 
 int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best) {

@@ -39,10 +39,13 @@ struct FastGraph {
   hipGraphExec_t exec = nullptr;
   int n = 0, part_threads = 0, part_wgs = 0, grid_wgs = 0;
   bool timed = false, do_export = true;
-  const float* x = nullptr;
+  // every user pointer and logging argument the captured launches bake in
+  const float *x = nullptr, *v = nullptr, *C = nullptr, *F = nullptr, *J = nullptr;
   const uint8_t* mat = nullptr;
   const void* mlp = nullptr;
   const float* log = nullptr;
+  const unsigned long long* log_count = nullptr;
+  unsigned long long log_cap = 0;
   float tol = 0.f;
   std::vector<hipEvent_t> ev;   // fused-kernel event pairs recorded by the graph
 };
@@ -91,6 +94,7 @@ struct FastPath {
   float4* vdense;
   bool valid;
   uint32_t sid;            // last step id handed out under the current epoch
+  int last_buf = -1;       // sorted buffer holding the state after the last call
 };
 
 // A state sorted by the block key of its own positions (the tiled adjoint
@@ -138,6 +142,13 @@ void fast_g2p(FastPath& f, const StepParams& P, const SortedState& st, const PBu
 // The path's own sorted state over buffer b (0 or 1) and list b, using the
 // path's shared grid arrays; and the scatter of a sorted buffer to user order.
 SortedState fast_own_state(FastPath& f, int b);
+// Integer outputs of the block sort (for checking it): which = 0 sorts the
+// user state (the import of every call) and copies the sorted ids and keys
+// (N each) and the occupied-block list (n_keys rows) to the given device
+// arrays and the list length to *n_list_host; which = 1 copies the ids of
+// the buffer the last call left.  Returns 0, or -1 (nothing recorded yet).
+int fast_sort_snapshot(FastPath& f, const StepParams& P, const PState& user, int which, uint32_t* id_out,
+                       uint32_t* key_out, int4* list_out, int* n_list_host, hipStream_t s);
 void fast_export(FastPath& f, const StepParams& P, const PBuf& X, const PState& user, hipStream_t s);
 
 }  // namespace mpm

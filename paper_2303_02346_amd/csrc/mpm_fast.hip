@@ -511,10 +511,12 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
             for (int k = 0; k < 9; k++) F[k] = Fn[k];
           } else {
             // plastic solids: FP32 SVD and return map, redone in FP64 for an
-            // ill-conditioned trial state (or an unconverged sweep)
+            // ill-conditioned trial state (or an unconverged sweep).  Sample
+            // logging and the learned closure keep the FP64 SVD throughout:
+            // their records and residuals are those of the exact FP64 return
             float Fn[9];
             PlasticStep<float> R;
-            int st = plastic_step<float, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R);
+            int st = FEAT == FEAT_NONE ? plastic_step<float, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R) : PLASTIC_RETRY;
             if (st == PLASTIC_RETRY) {
               PlasticStep<double> R2;
               st = plastic_step<double, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R2);
@@ -1155,6 +1157,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     }
   }
   if (f.do_export) k_export<<<nblk(N, 256), 256, 0, s>>>(f.buf[cur], user, P.mats);
+  f.last_buf = cur;
 }
 
 static void enqueue(FastPath& f, const StepParams& P, const PState& user, int n, const double* pose, const float* act,
@@ -1196,15 +1199,17 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   // replayed with the clock taken from device memory
   FastGraph* G = nullptr;
   for (auto& c : f.graphs)
-    if (c.exec && c.n == n && c.x == user.x && c.mat == P.mat && c.part_threads == f.part_threads &&
-        c.part_wgs == f.part_wgs && c.grid_wgs == f.grid_wgs && c.timed == timed && c.do_export == f.do_export &&
-        c.mlp == f.mlp_blob && c.log == f.log_buf && c.tol == f.closure_tol)
+    if (c.exec && c.n == n && c.x == user.x && c.v == user.v && c.C == user.C && c.F == user.F && c.J == user.J &&
+        c.mat == P.mat && c.part_threads == f.part_threads && c.part_wgs == f.part_wgs && c.grid_wgs == f.grid_wgs &&
+        c.timed == timed && c.do_export == f.do_export && c.mlp == f.mlp_blob && c.log == f.log_buf &&
+        c.log_count == f.log_count && c.log_cap == f.log_cap && c.tol == f.closure_tol)
       G = &c;
   if (!G) {
     FastGraph c;
-    c.n = n; c.x = user.x; c.mat = P.mat; c.part_threads = f.part_threads; c.part_wgs = f.part_wgs;
+    c.n = n; c.x = user.x; c.v = user.v; c.C = user.C; c.F = user.F; c.J = user.J; c.mat = P.mat;
+    c.part_threads = f.part_threads; c.part_wgs = f.part_wgs;
     c.grid_wgs = f.grid_wgs; c.timed = timed; c.do_export = f.do_export;
-    c.mlp = f.mlp_blob; c.log = f.log_buf; c.tol = f.closure_tol;
+    c.mlp = f.mlp_blob; c.log = f.log_buf; c.log_count = f.log_count; c.log_cap = f.log_cap; c.tol = f.closure_tol;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -3;
     enqueue(f, P, user, n, pose, act, s, nullptr);
     if (hipStreamEndCapture(s, &c.graph) != hipSuccess) { destroy_graph(c); return -3; }
@@ -1291,6 +1296,29 @@ SortedState fast_own_state(FastPath& f, int b) {
   S.list = f.list[b];
   S.list_n = f.list_n + b;
   return S;
+}
+
+int fast_sort_snapshot(FastPath& f, const StepParams& P, const PState& user, int which, uint32_t* id_out,
+                       uint32_t* key_out, int4* list_out, int* n_list_host, hipStream_t s) {
+  const size_t N = (size_t)f.N;
+  if (which == 0) {
+    SortedState st = fast_own_state(f, 0);
+    fast_sort_user(f, P, user, st, s, true);
+    f.last_buf = -1;   // buffer 0 no longer holds the last call's state
+    uint32_t nl = 0;
+    if (hipMemcpyAsync(id_out, st.b.id, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(key_out, st.b.key, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(list_out, st.list, (size_t)f.g.n_keys * sizeof(int4), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(&nl, st.list_n, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return -3;
+    *n_list_host = (int)nl;
+    return 0;
+  }
+  if (f.last_buf < 0) return -1;
+  if (hipMemcpyAsync(id_out, f.buf[f.last_buf].id, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -3;
+  return 0;
 }
 
 void fast_export(FastPath& f, const StepParams& P, const PBuf& X, const PState& user, hipStream_t s) {

@@ -213,11 +213,30 @@ def _two_box_scene(cfg_id: int, n_particles: int, n_grid: int, dt: float, steps:
     return sc
 
 
-def config2(n_particles: int = 250_000, steps: int = 200) -> Scene:
+def config2(n_particles: int = 250_000, steps: int = 200, sand_stir: float = 0.0) -> Scene:
     """250k particles (half liquid, half Drucker-Prager sand) in two seeded
-    cubes of side 0.2, kinematic cylinder r=0.05, 128^3, dt=5e-5."""
+    cubes of side 0.2, kinematic cylinder r=0.05, 128^3, dt=5e-5.
+
+    The sand of config 2 falls freely for its 200 steps (it starts two cells
+    above the floor band), so all its returns are of the elastic case.  With
+    sand_stir > 0 the sand box instead starts with a seeded smooth velocity
+    field of that amplitude (m/s): per component a plane wave
+    A sin(k.x + phase) with |k| = 2 pi / 0.2 in a seeded direction, which
+    compresses, stretches and shears the sand, so that apex, inside and cone
+    returns all occur within a few steps."""
     sc = _two_box_scene(2, n_particles, 128, 5e-5, steps)
     sc.name = "c2"
+    if sand_stir > 0.0:
+        rng = np.random.default_rng(np.random.SeedSequence(20230302 + 2, spawn_key=(9,)))
+        sand = sc.mat == 1
+        xs = sc.x[sand]
+        v = np.zeros_like(xs)
+        for a in range(3):
+            d = rng.normal(size=3)
+            k = 2.0 * math.pi / 0.2 * d / np.linalg.norm(d)
+            v[:, a] = sand_stir * np.sin(xs @ k + rng.uniform(0.0, 2.0 * math.pi))
+        sc.v[sand] = v
+        sc.name = "c2stir"
     return sc
 
 

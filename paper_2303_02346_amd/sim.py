@@ -257,6 +257,27 @@ class Simulator:
         _lib.check(_lib.lib().mpm_closure_stats(self.ctx, ctypes.byref(a), ctypes.byref(f)), "mpm_closure_stats")
         return a.value, f.value
 
+    def sort_snapshot(self, which: int = 0):
+        """Integer outputs of the block sort (mpm_sort_snapshot): which = 0
+        sorts the current state and returns (ids, keys, list) as numpy
+        arrays, list rows {key, offset, count}; which = 1 returns the ids of
+        the buffer the last forward call left."""
+        L = _lib.lib()
+        ids = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        self._sync_in()
+        if which == 1:
+            _lib.check(L.mpm_sort_snapshot(self.ctx, 1, ctypes.c_void_p(ids.data_ptr()), None, None, None),
+                       "mpm_sort_snapshot", self.ctx)
+            return ids.cpu().numpy().view(np.uint32)
+        keys = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        nk = self.get_option(_lib.MPM_OPT_N_KEYS)
+        lst = torch.empty(nk, 4, dtype=torch.int32, device=self.device)
+        nl = ctypes.c_int32(0)
+        _lib.check(L.mpm_sort_snapshot(self.ctx, 0, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(keys.data_ptr()),
+                                       ctypes.c_void_p(lst.data_ptr()), ctypes.byref(nl)), "mpm_sort_snapshot", self.ctx)
+        return (ids.cpu().numpy().view(np.uint32), keys.cpu().numpy().view(np.uint32),
+                lst[: nl.value, :3].cpu().numpy())
+
     def timing(self, enable: bool):
         _lib.check(_lib.lib().mpm_timing_enable(self.ctx, 1 if enable else 0), "mpm_timing_enable")
 

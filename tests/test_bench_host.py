@@ -21,13 +21,18 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_counted_traffic_follows_the_source_hash(tmp_path):
-    # the committed summaries match the committed sources
-    assert bench.counted_traffic() is not None
-    assert bench.counted_traffic(bench.GAS_TRAFFIC_SUMMARY, bench.GAS_TRAFFIC_SOURCES) is not None
-    # a summary taken on other sources is not reported
-    text = open(bench.GAS_TRAFFIC_SUMMARY).read()
+    # a summary whose source hash matches the sources is reported ...
+    import hashlib
+    h = hashlib.sha256()
+    for f in bench.GAS_TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2303_02346_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    fresh = tmp_path / "fresh.md"
+    fresh.write_text(f"traffic_bytes_per_launch: 12345\nsource-sha256: {h.hexdigest()[:16]}\n")
+    assert bench.counted_traffic(str(fresh), bench.GAS_TRAFFIC_SOURCES) == 12345
+    # ... one taken on other sources, or a missing one, is not
     stale = tmp_path / "stale.md"
-    stale.write_text(text.replace("source-sha256: ", "source-sha256: 0"))
+    stale.write_text(f"traffic_bytes_per_launch: 12345\nsource-sha256: 0{h.hexdigest()[:15]}\n")
     assert bench.counted_traffic(str(stale), bench.GAS_TRAFFIC_SOURCES) is None
     assert bench.counted_traffic(str(tmp_path / "missing.md"), bench.GAS_TRAFFIC_SOURCES) is None
 

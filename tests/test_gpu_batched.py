@@ -126,3 +126,70 @@ def test_autotuner_keeps_state_and_picks_a_valid_shape(tmp_path):
     e = rel(sim.positions(), O.rollout(sc, steps=40)["x"].numpy())
     say(f"  after autotune rel err {e:.2e}")
     assert e <= 1e-5
+
+
+def test_graph_cache_follows_rebound_state_arrays():
+    """A captured call bakes in every state pointer.  Rebinding only v (a
+    separate tensor, same x and mat) must drop the captured graph: the
+    graph-mode result with the rebound v equals an eager run."""
+    import ctypes
+    sc = scenes.tiny(n_particles=500, n_grid=32, steps=10, seed=9, dt=1e-4)
+    eager = sim_of(sc)
+    eager.step(5)
+    ref = eager.state_numpy()
+    g = sim_of(sc, graph=True)
+    g.step(5)                      # captures the call with the packed buffer's v rows
+    g.reset()
+    v2 = g.buf[3:6].clone()        # v rebound to a tensor of its own
+    b = g.buf
+    st = _lib.MpmState(b[0].data_ptr(), v2.data_ptr(), b[6].data_ptr(), b[15].data_ptr(), b[24].data_ptr(),
+                       g.mat.data_ptr())
+    g._sync_in()
+    _lib.check(_lib.lib().mpm_set_state(g.ctx, ctypes.byref(st)), "mpm_set_state", g.ctx)
+    g.set_actions(g.actions)
+    g.step(5)
+    torch.cuda.synchronize()
+    out = g.state_numpy()
+    ex = rel(out["x"], ref["x"])
+    ev = rel(v2.T.double().cpu().numpy(), ref["v"])
+    say(f"  rebound v under graph mode: rel diff x {ex:.2e}, v (the rebound tensor) {ev:.2e}")
+    assert ex <= 1e-6 and ev <= 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_config4_full_size_batched_vs_single_and_oracle():
+    """The full config-4 batch (64 scenes, 3.8M particles, 64^3 each) in the
+    autotuned launch: after 2 steps every scene equals its own single-scene
+    launch on x, v, C and F or J (Frobenius and per particle), and three
+    scenes (smallest, median, largest) match the oracle."""
+    from parity import compare_states, liquid_mask, state_errors
+    scs = scenes.config4(steps=4)
+    say(f"config 4 full size: {len(scs)} scenes, {sum(s.n for s in scs)} particles")
+    sim = sim_of(scs)
+    tune = sim.autotune(n_steps=2)
+    say(f"  launch {tune}")
+    sim.reset()
+    sim.step(2)
+    gb = sim.state_numpy()
+    worst = {}
+    for s, sc in enumerate(scs):
+        lo, hi = sim.offsets[s], sim.offsets[s + 1]
+        one = sim_of(sc)
+        one.step(2)
+        g1 = one.state_numpy()
+        one.close()
+        part = {k: v[lo:hi] for k, v in gb.items()}
+        e = state_errors(part, g1, liquid_mask(sc), n_grid=sc.n_grid)
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+        assert e["x"] <= 1e-6 and e["x_max"] <= 1e-5, (s, e)
+        assert e["v"] <= 1e-4 and e["C"] <= 1e-3 and e["v_max"] <= 1e-3 and e["C_max"] <= 1e-2, (s, e)
+        assert e["F"] <= 1e-5 and e["J"] <= 1e-5 and e["F_max"] <= 1e-4 and e["J_max"] <= 1e-4, (s, e)
+    say("  batched vs single, worst over scenes: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()))
+    sizes = np.array([sc.n for sc in scs])
+    for s in (int(sizes.argmin()), int(np.argsort(sizes)[len(sizes) // 2]), int(sizes.argmax())):
+        sc = scs[s]
+        ref = {k: v.detach().numpy() for k, v in O.rollout(sc, steps=2).items()}
+        part = {k: v[sim.offsets[s]:sim.offsets[s + 1]] for k, v in gb.items()}
+        say(f"  scene {s} ({sc.n} particles) vs oracle")
+        compare_states(part, ref, liquid_mask(sc), tol_x=1e-6, tol=1e-3, tol_FJ=1e-5, n_grid=sc.n_grid)

@@ -48,7 +48,11 @@ def test_mfma_forward_matches_oracle():
     yref = yref.numpy()
     e = rel(y - norm["out_mean"], yref - norm["out_mean"])
     say(f"  MFMA forward vs FP64 oracle (BF16 weights): rel err {e:.2e}")
-    assert e < 2e-2
+    # the oracle network runs the same BF16-rounded weights in FP64; what is
+    # left is the BF16 rounding of the activations fed to the matrix cores
+    # (8 significant bits, relative 2^-9 per operand, about 2e-3 after the
+    # three layers): the gate is three times that
+    assert e < 6e-3
 
 
 def test_mlp_gradient_vs_oracle():
@@ -61,8 +65,10 @@ def test_mlp_gradient_vs_oracle():
     Lref, gref = MO.loss_and_grad(pb, norm, rec.double().cpu().numpy())
     e = rel(g.double().cpu().numpy(), gref)
     say(f"  loss gpu {loss:.6f} oracle {Lref:.6f}; gradient rel err {e:.2e}")
-    assert abs(loss - Lref) <= 2e-2 * Lref
-    assert e < 5e-2
+    # forward in BF16 on the matrix cores, backward in FP32 (about 1e-3 from
+    # the forward's activations); the gate is three times that
+    assert abs(loss - Lref) <= 5e-3 * Lref
+    assert e < 3.5e-3
 
 
 def test_logged_samples_are_exact_returns():
@@ -114,6 +120,7 @@ def test_training_and_closure_in_the_simulator():
     r = MO.yield_residual(y, h)
     say(f"  held-out |eps_pred - eps_exact|_inf: median {np.median(err):.2e}, p99 {np.quantile(err, 0.99):.2e}; "
         f"residual <= 1e-3 for {(r <= 1e-3).mean() * 100:.1f}%")
+    assert np.median(err) <= 2e-4 and (r <= 1e-3).mean() >= 0.85
     # closure inside the simulator against the exact projection
     sc = sand_scene(99, n_particles=60000, n_grid=64, steps=40)
     exact = Simulator(sc)
@@ -128,5 +135,8 @@ def test_training_and_closure_in_the_simulator():
         shares[name] = acc / max(acc + fb, 1)
         say(f"  {name} closure: {acc} predictions accepted, {fb} fell back; position rel diff vs exact {ex:.2e}")
         assert acc + fb > 0
-        assert ex < 1e-3
-    assert shares["trained"] > shares["untrained"]
+        assert ex < 1e-4
+    # what the trained network gains (6 epochs on 400k samples here; the
+    # benchmark trains on 10M): it takes over most cone-case returns at the
+    # residual tolerance, where an untrained one is nearly always rejected
+    assert shares["trained"] >= 0.6 and shares["untrained"] <= 0.1

@@ -18,9 +18,7 @@ from paper_2303_02346_amd import _lib
 pytestmark = pytest.mark.gpu
 
 
-def say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+from parity import compare_states, liquid_mask, rel, say, state_errors
 
 
 def sim_of(sc, **kw):
@@ -28,30 +26,9 @@ def sim_of(sc, **kw):
     return Simulator(sc, **kw)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
-
-
 def oracle_state(sc, steps):
     st = O.rollout(sc, steps=steps)
     return {k: v.detach().numpy() for k, v in st.items()}
-
-
-def compare_states(gpu, ref, liquid, tol_x=1e-5, tol=1e-3):
-    ex = rel(gpu["x"], ref["x"])
-    ev = rel(gpu["v"], ref["v"])
-    eC = rel(gpu["C"], ref["C"])
-    solid = ~liquid
-    eF = rel(gpu["F"][solid], ref["F"][solid]) if solid.any() else 0.0
-    eJ = rel(gpu["J"][liquid], ref["J"][liquid]) if liquid.any() else 0.0
-    say(f"  rel err x {ex:.2e} v {ev:.2e} C {eC:.2e} F {eF:.2e} J {eJ:.2e}")
-    assert ex <= tol_x
-    assert ev <= tol and eC <= tol and eF <= tol_x * 10 and eJ <= tol_x * 10
-
-
-def liquid_mask(sc):
-    kinds = np.array([m.kind for m in sc.materials])
-    return kinds[sc.mat] == scenes.LIQUID
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -81,9 +58,8 @@ def test_config1_free_fall_100_steps():
     dy = -9.8 * sc.dt ** 2 * 100 * 101 / 2
     assert np.abs(g["x"][:, 1] - x0[:, 1] - dy).max() < 2e-6
     ref = oracle_state(sc, 100)
-    e = rel(g["x"], ref["x"])
-    say(f"  config 1 rel err {e:.2e}")
-    assert e <= 1e-4
+    compare_states(g, ref, liquid_mask(sc), tol_x=1e-6, tol=1e-4, tol_x_max=1e-5, tol_max=1e-3, tol_FJ=1e-5,
+                   n_grid=sc.n_grid)
 
 
 def test_config1b_affine_100_steps():
@@ -93,10 +69,9 @@ def test_config1b_affine_100_steps():
     sim.step(100)
     g = sim.state_numpy()
     ref = oracle_state(sc, 100)
-    e = rel(g["x"], ref["x"])
-    eF = rel(g["F"], ref["F"])
-    say(f"  config 1b rel err x {e:.2e} F {eF:.2e}")
-    assert e <= 1e-4 and eF <= 1e-3
+    # the stiff elastic body's velocities carry the FP32 rounding of 100
+    # steps of its stress (1.3e-4 measured): their gates are 5e-4 / 2e-3
+    compare_states(g, ref, liquid_mask(sc), tol_x=1e-6, tol=5e-4, tol_x_max=1e-5, tol_max=2e-3, tol_FJ=1e-5)
 
 
 def test_config2_full_size_first_steps():
@@ -109,6 +84,48 @@ def test_config2_full_size_first_steps():
     g = sim.state_numpy()
     ref = oracle_state(sc, 3)
     compare_states(g, ref, liquid_mask(sc), tol_x=1e-6, tol=1e-3)
+
+
+@pytest.mark.timeout(900)
+def test_config2_full_size_100_steps_vs_oracle():
+    """Config 2 at its full size (250k particles, 128^3) in the launch the
+    benchmark times (autotuned shape), 100 steps against the oracle: the
+    stated bar of 1e-4 relative error on positions after 100 steps, here
+    asserted per particle as well.  The window holds particles inside the
+    cylinder's contact band."""
+    from parity import oracle_rollout_coverage
+    sc = scenes.config2(steps=100)
+    say("config 2 full size, 100 steps (autotuned launch)")
+    sim = sim_of(sc)
+    tune = sim.autotune(n_steps=10)
+    say(f"  launch {tune}")
+    sim.reset()
+    sim.step(100)
+    g = sim.state_numpy()
+    ref, cases, band = oracle_rollout_coverage(O, sc, 100)
+    say(f"  oracle window: sand cases inside/apex/cone {cases.tolist()}, particle-steps in the contact band {band}")
+    assert band > 1000
+    compare_states(g, ref, liquid_mask(sc), tol_x=1e-5, tol=1e-3, tol_x_max=1e-4, tol_max=1e-2, tol_FJ=1e-4,
+                   tol_FJ_max=1e-3)
+
+
+@pytest.mark.timeout(900)
+def test_config2_stirred_sand_100_steps_vs_oracle():
+    """Config 2 at full size with the sand box stirred (a seeded smooth
+    velocity field of 1 m/s), so that the window holds all three
+    Drucker-Prager cases (inside, apex, cone) and the contact band; 100
+    steps against the oracle, Frobenius and per-particle."""
+    from parity import oracle_rollout_coverage
+    sc = scenes.config2(steps=100, sand_stir=1.0)
+    say("config 2 full size with stirred sand, 100 steps")
+    sim = sim_of(sc)
+    sim.step(100)
+    g = sim.state_numpy()
+    ref, cases, band = oracle_rollout_coverage(O, sc, 100)
+    say(f"  oracle window: sand cases inside/apex/cone {cases.tolist()}, particle-steps in the contact band {band}")
+    assert (cases > 100).all() and band > 1000
+    compare_states(g, ref, liquid_mask(sc), tol_x=1e-5, tol=1e-3, tol_x_max=1e-4, tol_max=1e-2, tol_FJ=1e-4,
+                   tol_FJ_max=1e-2)
 
 
 def test_config2_full_horizon_invariants():
@@ -148,6 +165,54 @@ def test_nonfinite_error_is_reported():
     with pytest.raises(_lib.MpmError) as e:
         sim.step(2)
     assert e.value.status == _lib.MPM_EDOMAIN
+
+
+def test_sand_sigma_error_is_reported():
+    """A sand particle whose deformation gradient has det F <= 0 (here
+    diag(1, 1, -1)) is an invalid state: the call reports MPM_ERR_SAND_SIGMA
+    and does not clamp it."""
+    sc = scenes.tiny(n_particles=60, n_grid=16, steps=2, kinds=(scenes.SAND,), with_cylinder=False)
+    sc.F[7] = np.diag([1.0, 1.0, -1.0])
+    say("sand sigma error")
+    sim = sim_of(sc)
+    with pytest.raises(_lib.MpmError) as e:
+        sim.step(1)
+    assert e.value.status == _lib.MPM_EDOMAIN and e.value.bits & 4
+
+
+def test_tile_reach_error_is_reported():
+    """A particle that moves more than one cell in a step leaves the reach of
+    the transfer tiles (the CFL > 1 condition): MPM_ERR_TILE."""
+    sc = scenes.tiny(n_particles=60, n_grid=32, steps=3, kinds=(scenes.ELASTIC,), with_cylinder=False)
+    dx = 1.0 / sc.n_grid
+    # one particle far from the others, moving 8 cells per step along x (a
+    # particle's stencil may drift at most one cell per step from its block)
+    sc.x[11] = [0.4, 0.8, 0.5]
+    sc.v[11] = [8.0 * dx / sc.dt, 0.0, 0.0]
+    say("tile reach error")
+    sim = sim_of(sc)
+    with pytest.raises(_lib.MpmError) as e:
+        sim.step(3)
+    assert e.value.status == _lib.MPM_EDOMAIN and e.value.bits & 8
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("threads", [512, 0])
+def test_paper_operating_point_vs_oracle(threads):
+    """The paper's operating point (section 4.2, App. B.1: about 1e5
+    particles of Table 4 water, viscous liquid and elastic solid on 64^3, dt
+    1e-4) in the 512-thread launch the autotuner picks for it (and, threads
+    = 0, whatever it picks), 20 steps against the oracle."""
+    sc = scenes.paper_point(steps=20)
+    say(f"paper operating point, {sc.n} particles, 20 steps, threads {threads or 'autotuned'}")
+    sim = sim_of(sc)
+    tune = sim.autotune(n_steps=10)
+    if threads:
+        sim.set_option(_lib.MPM_OPT_PART_THREADS, threads)
+    say(f"  launch {tune}, particle threads {sim.get_option(_lib.MPM_OPT_PART_THREADS)}")
+    sim.reset()
+    sim.step(20)
+    compare_states(sim.state_numpy(), oracle_state(sc, 20), liquid_mask(sc), tol_x=1e-6, tol=1e-3, tol_FJ=1e-5)
 
 
 # ---------------------------------------------------------------------------
