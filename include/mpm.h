@@ -305,6 +305,18 @@ int mpm_mlp_train(void* state_dev, const float* samples_dev, int64_t n, int32_t 
  * min(n, batch) records, without updating the weights. */
 int mpm_mlp_grad(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, void* scratch_dev,
                  float* grad_out_dev, double* loss_out_host, void* stream);
+/* mpm_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the per-sample scratch is a static device array of the library, sized for
+ * MPM_MLP_NOALLOC_MAX_BATCH records (2.2 MB, held by each device the
+ * library runs on until the process ends), instead of a caller buffer.
+ * min(n, batch) above the maximum returns MPM_EWORKSPACE and does nothing.
+ * The call allocates nothing.  Every call on one device shares that
+ * device's scratch (each call writes all of it that it reads): calls that
+ * overlap on one device, from several streams or host threads, race. */
+#define MPM_MLP_NOALLOC_MAX_BATCH 2048
+int mpm_mlp_grad_noalloc(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, float* grad_out_dev,
+                         double* loss_out_host, void* stream);
 /* Outputs (n x 3) for n records of 9 floats (only the 6 inputs are read). */
 int mpm_mlp_predict(const void* state_dev, const float* records_dev, int64_t n, float* y_dev, void* stream);
 /* Copy the FP32 parameter vector and/or the inference blob to the host. */

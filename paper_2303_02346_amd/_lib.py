@@ -36,7 +36,7 @@ EXPORTS = ["mpm_workspace_bytes", "mpm_create", "mpm_set_state", "mpm_set_action
            "mpm_step_backward", "mpm_loss_blob", "mpm_clock", "mpm_last_error_bits", "mpm_timing_enable",
            "mpm_timing_read", "mpm_set_option", "mpm_get_option", "mpm_sort_snapshot", "mpm_autotune", "mpm_log_samples", "mpm_set_closure",
            "mpm_closure_stats", "mpm_mlp_state_bytes", "mpm_mlp_scratch_bytes", "mpm_mlp_init", "mpm_mlp_train",
-           "mpm_mlp_grad", "mpm_mlp_predict", "mpm_mlp_params", "mpm_destroy", "mpm_strerror"]
+           "mpm_mlp_grad", "mpm_mlp_grad_noalloc", "mpm_mlp_predict", "mpm_mlp_params", "mpm_destroy", "mpm_strerror"]
 
 class GasDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("h", ctypes.c_float),
@@ -104,6 +104,7 @@ def lib():
     L.mpm_mlp_init.argtypes = [vp, vp, i64, vp, u64, vp]
     L.mpm_mlp_train.argtypes = [vp, vp, i64, i32, i32, ctypes.c_float, u64, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.mpm_mlp_grad.argtypes = [vp, vp, i64, i32, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.mpm_mlp_grad_noalloc.argtypes = [vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
     L.mpm_mlp_predict.argtypes = [vp, vp, i64, vp, vp]
     L.mpm_mlp_params.argtypes = [vp, vp, vp, vp]
     L.mpm_destroy.argtypes = [vp]

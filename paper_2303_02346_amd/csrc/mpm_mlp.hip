@@ -14,6 +14,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -229,11 +230,33 @@ __global__ void k_mlp_adam(float* __restrict__ p, float* __restrict__ m, float* 
   g[i] = 0.f;
 }
 
+// Per-sample backward scratch of mpm_mlp_grad_noalloc: at most
+// MPM_MLP_NOALLOC_MAX_BATCH samples of SCR floats (2.2 MB), one copy per
+// device for the life of the process.  Host code never passes this name to
+// a kernel: it uses the address hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) float scratch[MPM_MLP_NOALLOC_MAX_BATCH * SCR];
+
 }  // namespace mpm
 
 using namespace mpm;
 
 static int hipok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_EHIP; }
+
+// Device address of `scratch` on device dev, looked up once per device (with
+// that device current: the caller's) and kept.
+static void* noalloc_scratch(int dev) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(mpm::scratch)) != hipSuccess || !p) return nullptr;
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
 
 extern "C" {
 
@@ -292,16 +315,15 @@ static void batch_grad(char* st, const float* samples, long long n, long long i0
   k_mlp_wgrad<<<grid, 256, 0, s>>>(scr, nb, 16, (float*)(st + L.grad));
 }
 
-int mpm_mlp_grad(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, void* scratch_dev,
-                 float* grad_out_dev, double* loss_out_host, void* stream) {
-  if (!state_dev || !samples_dev || n < 1 || batch < 1 || !scratch_dev || !grad_out_dev) return MPM_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
+// Loss and gradient of the first nb records with the per-sample scratch scr
+// (shared by mpm_mlp_grad and mpm_mlp_grad_noalloc).
+static int grad_impl(void* state_dev, const float* samples_dev, int64_t n, int nb, float* scr, float* grad_out_dev,
+                     double* loss_out_host, hipStream_t s) {
   MlpLayout L = mlp_layout();
   char* st = (char*)state_dev;
   if (hipMemsetAsync(st + L.grad, 0, al(MLP_NPARAM * 4), s) != hipSuccess) return MPM_EHIP;
   if (hipMemsetAsync(st + L.misc, 0, 64, s) != hipSuccess) return MPM_EHIP;
-  int nb = (int)(n < batch ? n : batch);
-  batch_grad(st, samples_dev, n, 0, nb, (float*)scratch_dev, s);
+  batch_grad(st, samples_dev, n, 0, nb, scr, s);
   if (hipMemcpyAsync(grad_out_dev, st + L.grad, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return MPM_EHIP;
   double loss = 0.0;
@@ -309,6 +331,25 @@ int mpm_mlp_grad(void* state_dev, const float* samples_dev, int64_t n, int32_t b
   if (hipStreamSynchronize(s) != hipSuccess) return MPM_EHIP;
   if (loss_out_host) *loss_out_host = loss;
   return hipok(hipMemsetAsync(st + L.grad, 0, al(MLP_NPARAM * 4), s));
+}
+
+int mpm_mlp_grad(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, void* scratch_dev,
+                 float* grad_out_dev, double* loss_out_host, void* stream) {
+  if (!state_dev || !samples_dev || n < 1 || batch < 1 || !scratch_dev || !grad_out_dev) return MPM_EINVAL;
+  const int nb = (int)(n < batch ? n : batch);
+  return grad_impl(state_dev, samples_dev, n, nb, (float*)scratch_dev, grad_out_dev, loss_out_host, (hipStream_t)stream);
+}
+
+int mpm_mlp_grad_noalloc(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, float* grad_out_dev,
+                         double* loss_out_host, void* stream) {
+  if (!state_dev || !samples_dev || n < 1 || batch < 1 || !grad_out_dev) return MPM_EINVAL;
+  const int64_t nb = n < batch ? n : batch;
+  if (nb > MPM_MLP_NOALLOC_MAX_BATCH) return MPM_EWORKSPACE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MPM_EHIP;
+  float* scr = (float*)noalloc_scratch(dev);
+  if (!scr) return MPM_EHIP;
+  return grad_impl(state_dev, samples_dev, n, (int)nb, scr, grad_out_dev, loss_out_host, (hipStream_t)stream);
 }
 
 int mpm_mlp_train(void* state_dev, const float* samples_dev, int64_t n, int32_t batch, int32_t epochs, float lr,
