@@ -29,6 +29,7 @@
 #include "mpm_blocks.h"
 #include "mpm_math.h"
 #include "mpm_phys.h"
+#include "mpm_transfer.h"
 
 namespace mpm {
 
@@ -107,24 +108,8 @@ __global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P
       float vbt[3] = {0, 0, 0}, Bb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, bnd[NQ] = {0, 0, 0};
       if (ok) {
         // G2P recomputed from the staged velocities
-        float vn[3] = {0, 0, 0}, Bi[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-          for (int jj = 0; jj < 3; jj++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-              const float w = S.w[0][i] * S.w[1][jj] * S.w[2][k];
-              const float4 gv4 = s_v[((lv[0] + i) * VT + lv[1] + jj) * VT + lv[2] + k];
-              const float wv[3] = {w * gv4.x, w * gv4.y, w * gv4.z};
-#pragma unroll
-              for (int a = 0; a < 3; a++) {
-                vn[a] += wv[a];
-                Bi[a * 3 + 0] += (float)i * wv[a];
-                Bi[a * 3 + 1] += (float)jj * wv[a];
-                Bi[a * 3 + 2] += (float)k * wv[a];
-              }
-            }
+        float vn[3], Bi[9];
+        g2p_gather(s_v, lv, S, vn, Bi);
         float B[9];
 #pragma unroll
         for (int a = 0; a < 3; a++)
@@ -141,27 +126,22 @@ __global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P
         const float Jb = an[24 * (size_t)N + jn];
         float Fbo[9], Jbo;
         particle_update_adjoint(x, vn, B, M, P, st, j, xb, vb, Cb, Fb, Jb, vbt, Bb, Fbo, Jbo);
-        // position adjoint through the weights and the node offsets
-        float xo[3] = {xb[0], xb[1], xb[2]};
+        // position adjoint through the weights and the node offsets:
+        // xo = xb + sum_i grad w_i (v_i . (vbt + Bb (x_i - x_p))) - Bb^T vn
+        float xo[3];
+        {
+          float c0[3], Ad[9], X[3];
 #pragma unroll
-        for (int i = 0; i < 3; i++)
+          for (int a = 0; a < 3; a++) {
 #pragma unroll
-          for (int jj = 0; jj < 3; jj++)
+            for (int b = 0; b < 3; b++) Ad[a * 3 + b] = P.dx * Bb[a * 3 + b];
+            c0[a] = vbt[a] - (Ad[a * 3] * S.f[0] + Ad[a * 3 + 1] * S.f[1] + Ad[a * 3 + 2] * S.f[2]);
+          }
+          weight_grad_sum<false>(s_v, lv, S, c0, Ad, 0.f, X, nullptr, nullptr);
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-              const float w = S.w[0][i] * S.w[1][jj] * S.w[2][k];
-              const float d[3] = {(i - S.f[0]) * P.dx, (jj - S.f[1]) * P.dx, (k - S.f[2]) * P.dx};
-              const float4 gv4 = s_v[((lv[0] + i) * VT + lv[1] + jj) * VT + lv[2] + k];
-              const float gv[3] = {gv4.x, gv4.y, gv4.z};
-              float Wb = 0.f, gw[3];
-#pragma unroll
-              for (int a = 0; a < 3; a++)
-                Wb += gv[a] * (vbt[a] + Bb[a * 3] * d[0] + Bb[a * 3 + 1] * d[1] + Bb[a * 3 + 2] * d[2]);
-              S.grad_w(i, jj, k, P.inv_dx, gw);
-#pragma unroll
-              for (int a = 0; a < 3; a++)
-                xo[a] += Wb * gw[a] - w * (Bb[a] * gv[0] + Bb[3 + a] * gv[1] + Bb[6 + a] * gv[2]);
-            }
+          for (int a = 0; a < 3; a++)
+            xo[a] = xb[a] + P.inv_dx * X[a] - (Bb[a] * vn[0] + Bb[3 + a] * vn[1] + Bb[6 + a] * vn[2]);
+        }
         float* ab = A.abar;
 #pragma unroll
         for (int a = 0; a < 3; a++) { ab[a * (size_t)N + j] = xo[a]; ab[(3 + a) * (size_t)N + j] = 0.f; }
@@ -416,53 +396,52 @@ __global__ __launch_bounds__(NT) void k_p2g_adj_tiled(AdjArgs A, StepParams P, F
       for (int k = 0; k < 9; k++) C[k] = st.C[k * (size_t)N + j];
       float tau[9];
       const float Jv = st.J[j];
-      // one FP64 SVD serves the stress and its adjoint
-      double Fd[9], U[9], sv[3], V[9];
+      // one FP32 SVD serves the stress and its adjoint; an ill-conditioned
+      // F (s2 < s0/4) or an unconverged sweep takes the FP64 SVD instead,
+      // for the stress here and again for its adjoint after the gather (so
+      // that no FP64 factor stays live across it)
+      float Ff[9], U[9], sv[3], V[9];
+      bool fp32 = true;
       if (M.kind == KIND_LIQUID) {
         stress_liquid(Jv, C, M, tau);
       } else {
 #pragma unroll
-        for (int k = 0; k < 9; k++) Fd[k] = (double)st.F[k * (size_t)N + j];
-        svd3(Fd, U, sv, V);
-        stress_solid_usv(Fd, U, sv, V, M, tau);
+        for (int k = 0; k < 9; k++) Ff[k] = st.F[k * (size_t)N + j];
+        fp32 = svd3(Ff, U, sv, V) && sv[2] > 0.25f * sv[0];
+        if (fp32) stress_solid_usv(Ff, U, sv, V, M, tau);
+        else stress_solid(Ff, M, tau);
       }
       float Am[9];
       const float scl = -P.dt * M.vol * 4.f * P.inv_dx * P.inv_dx;
 #pragma unroll
       for (int k = 0; k < 9; k++) Am[k] = scl * tau[k] + M.mass * C[k];
       const float mvp[3] = {M.mass * v[0], M.mass * v[1], M.mass * v[2]};
-      float vb[3] = {0, 0, 0}, Ab[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, xb[3] = {0, 0, 0};
+      // node adjoints gathered: mom_i = mvp + Am (x_i - x_p) = c0 + Ad idx_i
+      float vb[3], Ab[9], xb[3];
+      {
+        float c0[3], Ad[9], X[3], G0[3], Gi[9];
 #pragma unroll
-      for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 3; a++) {
 #pragma unroll
-        for (int jj = 0; jj < 3; jj++)
+          for (int b = 0; b < 3; b++) Ad[a * 3 + b] = P.dx * Am[a * 3 + b];
+          c0[a] = mvp[a] - (Ad[a * 3] * S.f[0] + Ad[a * 3 + 1] * S.f[1] + Ad[a * 3 + 2] * S.f[2]);
+        }
+        weight_grad_sum<true>(s_g, lv, S, c0, Ad, M.mass, X, G0, Gi);
 #pragma unroll
-          for (int k = 0; k < 3; k++) {
-            const float w = S.w[0][i] * S.w[1][jj] * S.w[2][k];
-            const float d[3] = {(i - S.f[0]) * P.dx, (jj - S.f[1]) * P.dx, (k - S.f[2]) * P.dx};
-            const float4 gb4 = s_g[((lv[0] + i) * VT + lv[1] + jj) * VT + lv[2] + k];
-            const float gb[3] = {gb4.x, gb4.y, gb4.z};
-            float mom[3];
+        for (int a = 0; a < 3; a++) {
+          vb[a] = M.mass * G0[a];
 #pragma unroll
-            for (int a = 0; a < 3; a++) mom[a] = mvp[a] + Am[a * 3] * d[0] + Am[a * 3 + 1] * d[1] + Am[a * 3 + 2] * d[2];
-            const float Wb = gb4.w * M.mass + gb[0] * mom[0] + gb[1] * mom[1] + gb[2] * mom[2];
-            float gw[3];
-            S.grad_w(i, jj, k, P.inv_dx, gw);
-#pragma unroll
-            for (int a = 0; a < 3; a++) {
-              vb[a] += w * M.mass * gb[a];
-#pragma unroll
-              for (int b = 0; b < 3; b++) Ab[a * 3 + b] += w * gb[a] * d[b];
-              const float ATg = Am[a] * gb[0] + Am[3 + a] * gb[1] + Am[6 + a] * gb[2];
-              xb[a] += Wb * gw[a] - w * ATg;
-            }
-          }
+          for (int b = 0; b < 3; b++) Ab[a * 3 + b] = P.dx * (Gi[a * 3 + b] - G0[a] * S.f[b]);
+          xb[a] = P.inv_dx * X[a] - (Am[a] * G0[0] + Am[3 + a] * G0[1] + Am[6 + a] * G0[2]);
+        }
+      }
       float taub[9], Cb[9], Fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int k = 0; k < 9; k++) { taub[k] = scl * Ab[k]; Cb[k] = M.mass * Ab[k]; }
       float Jb = 0.f;
       if (M.kind == KIND_LIQUID) stress_liquid_adjoint(Jv, C, M, taub, Jb, Cb);
-      else stress_solid_adjoint_usv(Fd, U, sv, V, M, taub, Fb);
+      else if (fp32) stress_solid_adjoint_usv(Ff, U, sv, V, M, taub, Fb);
+      else stress_solid_adjoint(Ff, M, taub, Fb);
       float* ab = A.abar;
 #pragma unroll
       for (int a = 0; a < 3; a++) { ab[a * (size_t)N + j] += xb[a]; ab[(3 + a) * (size_t)N + j] += vb[a]; }

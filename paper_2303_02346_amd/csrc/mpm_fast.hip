@@ -29,6 +29,7 @@
 #include "mpm_math.h"
 #include "mpm_mlp.h"
 #include "mpm_phys.h"
+#include "mpm_transfer.h"
 
 namespace mpm {
 
@@ -295,51 +296,6 @@ __global__ __launch_bounds__(256) void k_export(PBuf X, PState u, const MatDev* 
   } else {
 #pragma unroll
     for (int k = 0; k < 9; k++) u.F[k * N + p] = X.f[(15 + k) * (size_t)N + j];
-  }
-}
-
-// G2P gather from the staged velocity tile (VT^3 nodes, lb = the stencil's
-// first node in it): vn = sum_i w_i v_i and Bi = sum_i w_i v_i idx_i^T with
-// idx_i in {0,1,2}^3 the node's offset in the stencil.  The sums run over z
-// inside y inside x, so that each partial sum is weighted once by the outer
-// weights; the loads of one x plane are issued together, and the compiler
-// barrier between planes keeps the next plane's loads from being hoisted
-// (nine float3 loads in flight rather than 27 bounds the register count).
-__device__ __forceinline__ void g2p_gather(const float4* __restrict__ s_v, const int* lb, const Stencil& S,
-                                           float* vn, float* Bi) {
-#pragma unroll
-  for (int q = 0; q < 3; q++) vn[q] = 0.f;
-#pragma unroll
-  for (int q = 0; q < 9; q++) Bi[q] = 0.f;
-  const float wz1 = S.w[2][1], wz2 = S.w[2][2], wz2x2 = 2.f * S.w[2][2];
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    float p0[3] = {0, 0, 0}, pj[3] = {0, 0, 0}, pk[3] = {0, 0, 0};
-#pragma unroll
-    for (int jj = 0; jj < 3; jj++) {
-      const float4* row = s_v + ((lb[0] + i) * VT + lb[1] + jj) * VT + lb[2];
-      const float4 g0 = row[0], g1 = row[1], g2 = row[2];
-      // r = sum_k w_k v_k, rk = sum_k k w_k v_k along z
-      const float r[3] = {S.w[2][0] * g0.x + wz1 * g1.x + wz2 * g2.x, S.w[2][0] * g0.y + wz1 * g1.y + wz2 * g2.y,
-                          S.w[2][0] * g0.z + wz1 * g1.z + wz2 * g2.z};
-      const float rk[3] = {wz1 * g1.x + wz2x2 * g2.x, wz1 * g1.y + wz2x2 * g2.y, wz1 * g1.z + wz2x2 * g2.z};
-      const float wy = S.w[1][jj];
-#pragma unroll
-      for (int a = 0; a < 3; a++) {
-        p0[a] += wy * r[a];
-        if (jj) pj[a] += ((float)jj * wy) * r[a];
-        pk[a] += wy * rk[a];
-      }
-    }
-    const float wx = S.w[0][i];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-      vn[a] += wx * p0[a];
-      if (i) Bi[a * 3 + 0] += ((float)i * wx) * p0[a];
-      Bi[a * 3 + 1] += wx * pj[a];
-      Bi[a * 3 + 2] += wx * pk[a];
-    }
-    asm volatile("" ::: "memory");
   }
 }
 

@@ -198,55 +198,61 @@ template <typename T> MPM_DI void usv(const T* U, const T* g, const T* V, T* out
 //   Abar_ij = sdd[i][j] (M_ij + M_ji)/2 + (g_i + g_j)/(s_i + s_j) (M_ij - M_ji)/2
 // where sdd[i][j] is the divided difference (g_i - g_j)/(s_i - s_j) supplied
 // by the caller in a form that is exact at s_i = s_j.
-MPM_DI void iso_adjoint(const double* U, const double* s, const double* V, const double* g, const double* dg,
-                        const double* sdd, const double* Pbar, double* Fbar) {
-  double T1[9], M[9];
+template <typename T>
+MPM_DI void iso_adjoint(const T* U, const T* s, const T* V, const T* g, const T* dg, const T* sdd, const T* Pbar,
+                        T* Fbar) {
+  T T1[9], M[9];
   matmul_tn(U, Pbar, T1);
   matmul(T1, V, M);
-  double A[9];
+  T A[9];
 #pragma unroll
   for (int k = 0; k < 3; k++) A[k * 4] = M[0] * dg[0 * 3 + k] + M[4] * dg[1 * 3 + k] + M[8] * dg[2 * 3 + k];
   // (g_i + g_j)/(s_i + s_j) is symmetric: one division per pair
-  const double t01 = (g[0] + g[1]) / (s[0] + s[1]), t02 = (g[0] + g[2]) / (s[0] + s[2]),
-               t12 = (g[1] + g[2]) / (s[1] + s[2]);
+  const T t01 = t_div(g[0] + g[1], s[0] + s[1]), t02 = t_div(g[0] + g[2], s[0] + s[2]),
+          t12 = t_div(g[1] + g[2], s[1] + s[2]);
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int j = 0; j < 3; j++) {
       if (i == j) continue;
-      const double t = (i + j == 1) ? t01 : ((i + j == 2) ? t02 : t12);
-      A[i * 3 + j] = sdd[i * 3 + j] * 0.5 * (M[i * 3 + j] + M[j * 3 + i]) + t * 0.5 * (M[i * 3 + j] - M[j * 3 + i]);
+      const T t = (i + j == 1) ? t01 : ((i + j == 2) ? t02 : t12);
+      A[i * 3 + j] = sdd[i * 3 + j] * T(0.5) * (M[i * 3 + j] + M[j * 3 + i]) + t * T(0.5) * (M[i * 3 + j] - M[j * 3 + i]);
     }
   matmul(U, A, T1);
   matmul_nt(T1, V, Fbar);
 }
 
+MPM_DI double t_log1p(double x) { return log1p(x); }
+MPM_DI float t_log1p(float x) { return log1pf(x); }
+MPM_DI double t_expm1(double x) { return expm1(x); }
+MPM_DI float t_expm1(float x) { return expm1f(x); }
+
 // (log a - log b)/(a - b) for a, b > 0, exact as a -> b.
-MPM_DI double log_divdiff(double a, double b) {
-  double x = (a - b) / b;
-  if (fabs(x) < 1e-4) return (1.0 - x * (0.5 - x * (1.0 / 3.0 - 0.25 * x))) / b;
-  return log1p(x) / (a - b);
+template <typename T> MPM_DI T log_divdiff(T a, T b) {
+  const T x = t_div(a - b, b);
+  if (t_abs(x) < T(1e-4)) return t_div(T(1) - x * (T(0.5) - x * (T(1) / T(3) - T(0.25) * x)), b);
+  return t_div(t_log1p(x), a - b);
 }
 
 // expm1(beta d) / expm1(d), exact as d -> 0.
-MPM_DI double expm1_ratio(double beta, double d) {
-  if (fabs(d) < 1e-6) return beta * (1.0 + 0.5 * (beta - 1.0) * d);
-  return expm1(beta * d) / expm1(d);
+template <typename T> MPM_DI T expm1_ratio(T beta, T d) {
+  if (t_abs(d) < T(1e-6)) return beta * (T(1) + T(0.5) * (beta - T(1)) * d);
+  return t_div(t_expm1(beta * d), t_expm1(d));
 }
 
 // Both expm1(beta d)/expm1(d) (into r) and expm1(-beta d)/expm1(-d) (into
 // rm) from one pair of expm1 evaluations: with E1 = expm1(beta d) and
 // E0 = expm1(d), expm1(-x) = -expm1(x)/(1 + expm1(x)) gives
 // rm = r (1 + E0)/(1 + E1).
-MPM_DI void expm1_ratio_pair(double beta, double d, double& r, double& rm) {
-  if (fabs(d) < 1e-6) {
-    r = beta * (1.0 + 0.5 * (beta - 1.0) * d);
-    rm = beta * (1.0 - 0.5 * (beta - 1.0) * d);
+template <typename T> MPM_DI void expm1_ratio_pair(T beta, T d, T& r, T& rm) {
+  if (t_abs(d) < T(1e-6)) {
+    r = beta * (T(1) + T(0.5) * (beta - T(1)) * d);
+    rm = beta * (T(1) - T(0.5) * (beta - T(1)) * d);
     return;
   }
-  const double E1 = expm1(beta * d), E0 = expm1(d);
-  r = E1 / E0;
-  rm = r * (1.0 + E0) / (1.0 + E1);
+  const T E1 = t_expm1(beta * d), E0 = t_expm1(d);
+  r = t_div(E1, E0);
+  rm = t_div(r * (T(1) + E0), T(1) + E1);
 }
 
 }  // namespace mpm

@@ -99,35 +99,28 @@ template <typename T> MPM_DI void hencky_tau(const T* U, const T* e, const MatDe
       tau[i * 3 + j] = (float)(U[i * 3] * h[0] * U[j * 3] + U[i * 3 + 1] * h[1] * U[j * 3 + 1] + U[i * 3 + 2] * h[2] * U[j * 3 + 2]);
 }
 
-// The stress from a given signed SVD F = U diag(s) V^T of the FP64 copy F.
-MPM_DI bool stress_solid_usv(const double* F, const double* U, const double* s, const double* V, const MatDev& M,
-                             float* tau) {
+// The stress from a given signed SVD F = U diag(s) V^T of the copy F (in the
+// precision T of the SVD).
+template <typename T>
+MPM_DI bool stress_solid_usv(const T* F, const T* U, const T* s, const T* V, const MatDev& M, float* tau) {
   if (corotated_kind(M.kind)) {
-    double R[9], D[9], T[9];
+    T R[9], D[9], Tm[9];
     matmul_nt(U, V, R);
 #pragma unroll
     for (int k = 0; k < 9; k++) D[k] = F[k] - R[k];
-    matmul_nt(D, F, T);
-    double J = s[0] * s[1] * s[2];
-    double pr = (double)M.lam * J * (J - 1.0);
-    double m2 = 2.0 * (double)M.mu;
+    matmul_nt(D, F, Tm);
+    const T J = s[0] * s[1] * s[2];
+    const T pr = (T)M.lam * J * (J - T(1));
+    const T m2 = T(2) * (T)M.mu;
 #pragma unroll
-    for (int k = 0; k < 9; k++) tau[k] = (float)(m2 * T[k] + ((k % 4 == 0) ? pr : 0.0));
+    for (int k = 0; k < 9; k++) tau[k] = (float)(m2 * Tm[k] + ((k % 4 == 0) ? pr : T(0)));
     return true;
   }
-  bool ok = s[2] > 0.0;
-  double e[3];
+  const bool ok = s[2] > T(0);
+  T e[3];
 #pragma unroll
-  for (int a = 0; a < 3; a++) e[a] = ok ? log(s[a]) : 0.0;
-  double tr = e[0] + e[1] + e[2];
-  double h[3];
-#pragma unroll
-  for (int a = 0; a < 3; a++) h[a] = 2.0 * (double)M.mu * e[a] + (double)M.lam * tr;
-#pragma unroll
-  for (int i = 0; i < 3; i++)
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-      tau[i * 3 + j] = (float)(U[i * 3] * h[0] * U[j * 3] + U[i * 3 + 1] * h[1] * U[j * 3 + 1] + U[i * 3 + 2] * h[2] * U[j * 3 + 2]);
+  for (int a = 0; a < 3; a++) e[a] = ok ? t_log(s[a]) : T(0);
+  hencky_tau(U, e, M, tau);
   return ok;
 }
 
@@ -165,59 +158,62 @@ MPM_DI bool stress_solid_fast(const float* Ff, const MatDev& M, float* tau) {
   return true;
 }
 
-// Adjoint of the solid stress, from a given signed SVD of the FP64 copy F.
-MPM_DI void stress_solid_adjoint_usv(const double* F, const double* U, const double* s, const double* V,
-                                     const MatDev& M, const float* taubf, float* Fbf) {
-  double tb[9];
+// Adjoint of the solid stress, from a given signed SVD of the copy F (in the
+// precision T of the SVD).
+template <typename T>
+MPM_DI void stress_solid_adjoint_usv(const T* F, const T* U, const T* s, const T* V, const MatDev& M,
+                                     const float* taubf, float* Fbf) {
+  T tb[9];
 #pragma unroll
-  for (int k = 0; k < 9; k++) tb[k] = (double)taubf[k];
-  double Fb[9];
+  for (int k = 0; k < 9; k++) tb[k] = (T)taubf[k];
+  T Fb[9];
   if (corotated_kind(M.kind)) {
-    double R[9], D[9], T1[9], T2[9], Rb[9];
+    T R[9], D[9], T1[9], T2[9], Rb[9];
     matmul_nt(U, V, R);
 #pragma unroll
     for (int k = 0; k < 9; k++) D[k] = F[k] - R[k];
-    double m2 = 2.0 * (double)M.mu;
+    const T m2 = T(2) * (T)M.mu;
     matmul(tb, F, T1);      // taub F
     matmul_tn(tb, D, T2);   // taub^T (F - R)
 #pragma unroll
     for (int k = 0; k < 9; k++) { Fb[k] = m2 * (T1[k] + T2[k]); Rb[k] = -m2 * T1[k]; }
     // polar rotation: g = 1, dg = 0, divided differences 0
-    double g[3] = {1, 1, 1}, dg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, sdd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double Fr[9];
-    iso_adjoint(U, s, V, g, dg, sdd, Rb, Fr);
-    double J = s[0] * s[1] * s[2];
-    double K[9];
+    const T g[3] = {T(1), T(1), T(1)};
+    const T dg[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    T Fr[9];
+    iso_adjoint(U, s, V, g, dg, dg, Rb, Fr);
+    const T J = s[0] * s[1] * s[2];
+    T K[9];
     cof3(F, K);
-    double jb = (double)M.lam * (2.0 * J - 1.0) * (tb[0] + tb[4] + tb[8]);
+    const T jb = (T)M.lam * (T(2) * J - T(1)) * (tb[0] + tb[4] + tb[8]);
 #pragma unroll
     for (int k = 0; k < 9; k++) Fb[k] += Fr[k] + jb * K[k];
   } else {
-    double e[3], g[3], dg[9], sdd[9];
-    bool ok = s[2] > 0.0;
+    T e[3], g[3], dg[9], sdd[9];
+    const bool ok = s[2] > T(0);
 #pragma unroll
-    for (int a = 0; a < 3; a++) e[a] = ok ? log(s[a]) : 0.0;
-    double tr = e[0] + e[1] + e[2];
-    double mu = M.mu, lam = M.lam;
-    double h[3], is[3];
+    for (int a = 0; a < 3; a++) e[a] = ok ? t_log(s[a]) : T(0);
+    const T tr = e[0] + e[1] + e[2];
+    const T mu = (T)M.mu, lam = (T)M.lam;
+    T h[3], is[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) { is[a] = 1.0 / s[a]; h[a] = 2.0 * mu * e[a] + lam * tr; g[a] = h[a] * is[a]; }
+    for (int a = 0; a < 3; a++) { is[a] = t_div(T(1), s[a]); h[a] = T(2) * mu * e[a] + lam * tr; g[a] = h[a] * is[a]; }
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
       for (int k = 0; k < 3; k++)
-        dg[i * 3 + k] = (2.0 * mu * (i == k) + lam) * is[k] * is[i] - (i == k ? h[i] * is[i] * is[i] : 0.0);
+        dg[i * 3 + k] = (T(2) * mu * T(i == k) + lam) * is[k] * is[i] - (i == k ? h[i] * is[i] * is[i] : T(0));
     // (log s_i - log s_j)/(s_i - s_j) is symmetric: one evaluation per pair
-    const double L01 = log_divdiff(s[0], s[1]), L02 = log_divdiff(s[0], s[2]), L12 = log_divdiff(s[1], s[2]);
+    const T L01 = log_divdiff(s[0], s[1]), L02 = log_divdiff(s[0], s[2]), L12 = log_divdiff(s[1], s[2]);
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
       for (int j = 0; j < 3; j++) {
-        if (i == j) { sdd[i * 3 + j] = 0.0; continue; }
-        const double L = (i + j == 1) ? L01 : ((i + j == 2) ? L02 : L12);
-        sdd[i * 3 + j] = (2.0 * mu * (s[j] * L - e[j]) - lam * tr) * is[i] * is[j];
+        if (i == j) { sdd[i * 3 + j] = T(0); continue; }
+        const T L = (i + j == 1) ? L01 : ((i + j == 2) ? L02 : L12);
+        sdd[i * 3 + j] = (T(2) * mu * (s[j] * L - e[j]) - lam * tr) * is[i] * is[j];
       }
-    double Pm[9], Pb[9], T1[9], Fr[9];
+    T Pm[9], Pb[9], T1[9], Fr[9];
     usv(U, g, V, Pm);
     matmul(tb, F, Pb);        // Pbar = taub F
     matmul_tn(tb, Pm, T1);    // taub^T P
@@ -452,6 +448,96 @@ MPM_DI void particle_update(const float* x, const float* vn, const float* B, con
   U.finite = fin;
 }
 
+// Adjoint of the plastic update F' = Phi(F_tr), F_tr = Md F, of a Box-yield,
+// sand or von Mises solid: Ftb = dL/dF_tr from Fb = dL/dF', through the
+// isotropic-map derivative of the return map, in precision T.  In FP32 an
+// ill-conditioned trial state (s2 < s0/4) or an unconverged sweep returns
+// false without output, for the caller to redo it in FP64.
+template <typename T>
+MPM_DI bool plastic_adjoint(const float* Md, const float* F, const MatDev& M, const float* Fb, float* Ftb) {
+  constexpr bool dbl = sizeof(T) == 8;
+  T Ft[9], Uu[9], s[3], V[9];
+  {
+    T Mdd[9], Fd[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) { Mdd[k] = (T)Md[k]; Fd[k] = (T)F[k]; }
+    matmul(Mdd, Fd, Ft);
+  }
+  const bool conv = svd3(Ft, Uu, s, V);
+  if (!dbl && (!conv || !(s[2] > T(0.25) * s[0]))) return false;
+  T e[3], ep[3];
+  const bool ok = s[2] > T(0);
+#pragma unroll
+  for (int a = 0; a < 3; a++) e[a] = ok ? t_log(s[a]) : T(0);
+  DPInfoT<T> I;
+  if (M.kind == KIND_BOX) {
+    // clamp: dg = diag(inside), divided differences (g_i - g_j)/(s_i - s_j)
+    T g[3], dg[9], sdd[9], Pb[9], Fr[9];
+    const bool clamped = ok && box_clamp(s, M, g);
+    if (!clamped) {
+#pragma unroll
+      for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) dg[i * 3 + k] = (i == k && g[i] == s[i]) ? T(1) : T(0);
+      const T tiny = dbl ? T(1e-12) : T(1e-6);
+#pragma unroll
+      for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+          const T d = s[i] - s[j];
+          sdd[i * 3 + j] = (i == j) ? T(0) : (t_abs(d) > tiny ? t_div(g[i] - g[j], d) : dg[i * 3 + i]);
+        }
+#pragma unroll
+      for (int k = 0; k < 9; k++) Pb[k] = (T)Fb[k];
+      iso_adjoint(Uu, s, V, g, dg, sdd, Pb, Fr);
+#pragma unroll
+      for (int k = 0; k < 9; k++) Ftb[k] = (float)Fr[k];
+    }
+    return true;
+  }
+  plastic_project(e, M, ep, I);
+  if (!ok || I.cse == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
+    return true;
+  }
+  T g[3], dg[9], sdd[9], Pb[9], Fr[9];
+#pragma unroll
+  for (int a = 0; a < 3; a++) g[a] = t_exp(ep[a]);
+  if (I.cse == 1) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) { dg[k] = T(0); sdd[k] = T(0); }
+  } else {
+    const T is[3] = {t_div(T(1), s[0]), t_div(T(1), s[1]), t_div(T(1), s[2])};
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        const T Jik = T(1) / T(3) - I.k1 * I.nh[i] + I.beta * ((i == k ? T(1) : T(0)) - I.nh[i] * I.nh[k] - T(1) / T(3));
+        dg[i * 3 + k] = g[i] * Jik * is[k];
+      }
+    // exp(ep_j - e_j) = g_j / s_j; the ratios of a pair share their expm1s
+    T r01, r10, r02, r20, r12, r21;
+    expm1_ratio_pair(I.beta, e[0] - e[1], r01, r10);
+    expm1_ratio_pair(I.beta, e[0] - e[2], r02, r20);
+    expm1_ratio_pair(I.beta, e[1] - e[2], r12, r21);
+    const T q[3] = {g[0] * is[0], g[1] * is[1], g[2] * is[2]};
+    sdd[0] = sdd[4] = sdd[8] = T(0);
+    sdd[1] = q[1] * r01; sdd[3] = q[0] * r10;
+    sdd[2] = q[2] * r02; sdd[6] = q[0] * r20;
+    sdd[5] = q[2] * r12; sdd[7] = q[1] * r21;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; k++) Pb[k] = (T)Fb[k];
+  iso_adjoint(Uu, s, V, g, dg, sdd, Pb, Fr);
+#pragma unroll
+  for (int k = 0; k < 9; k++) Ftb[k] = (float)Fr[k];
+  return true;
+}
+
 // Adjoint of particle_update.  Inputs: the output adjoints (xb, vb, Cb, Fb,
 // Jb).  Outputs: vbt = adjoint of vn, Bb = adjoint of B, Fbo/Jbo = adjoint of
 // the input F/J.  The direct x term (x' = x + ...) is left to the caller.
@@ -486,80 +572,7 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
 #pragma unroll
       for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
     } else {
-      double Mdd[9], Fd[9], Ft[9], Uu[9], s[3], V[9];
-#pragma unroll
-      for (int k = 0; k < 9; k++) { Mdd[k] = Md[k]; Fd[k] = F[k]; }
-      matmul(Mdd, Fd, Ft);
-      svd3(Ft, Uu, s, V);
-      double e[3], ep[3];
-      bool ok = s[2] > 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; a++) e[a] = ok ? log(s[a]) : 0.0;
-      DPInfo I;
-      if (M.kind == KIND_BOX) {
-        // clamp: dg = diag(inside), divided differences (g_i - g_j)/(s_i - s_j)
-        double g[3], dg[9], sdd[9], Pb[9], Fr[9];
-        const bool clamped = ok && box_clamp(s, M, g);
-        if (!clamped) {
-#pragma unroll
-          for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
-        } else {
-#pragma unroll
-          for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) dg[i * 3 + k] = (i == k && g[i] == s[i]) ? 1.0 : 0.0;
-#pragma unroll
-          for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-              const double d = s[i] - s[j];
-              sdd[i * 3 + j] = (i == j) ? 0.0 : (fabs(d) > 1e-12 ? (g[i] - g[j]) / d : dg[i * 3 + i]);
-            }
-#pragma unroll
-          for (int k = 0; k < 9; k++) Pb[k] = (double)Fb[k];
-          iso_adjoint(Uu, s, V, g, dg, sdd, Pb, Fr);
-#pragma unroll
-          for (int k = 0; k < 9; k++) Ftb[k] = (float)Fr[k];
-        }
-      } else {
-      plastic_project(e, M, ep, I);
-      if (!ok || I.cse == 0) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
-      } else {
-        double g[3], dg[9], sdd[9], Pb[9], Fr[9];
-#pragma unroll
-        for (int a = 0; a < 3; a++) g[a] = exp(ep[a]);
-        if (I.cse == 1) {
-#pragma unroll
-          for (int k = 0; k < 9; k++) { dg[k] = 0.0; sdd[k] = 0.0; }
-        } else {
-          const double is[3] = {1.0 / s[0], 1.0 / s[1], 1.0 / s[2]};
-#pragma unroll
-          for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-              double Jik = 1.0 / 3.0 - I.k1 * I.nh[i] + I.beta * ((i == k ? 1.0 : 0.0) - I.nh[i] * I.nh[k] - 1.0 / 3.0);
-              dg[i * 3 + k] = g[i] * Jik * is[k];
-            }
-          // exp(ep_j - e_j) = g_j / s_j; the ratios of a pair share their expm1s
-          double r01, r10, r02, r20, r12, r21;
-          expm1_ratio_pair(I.beta, e[0] - e[1], r01, r10);
-          expm1_ratio_pair(I.beta, e[0] - e[2], r02, r20);
-          expm1_ratio_pair(I.beta, e[1] - e[2], r12, r21);
-          const double q[3] = {g[0] * is[0], g[1] * is[1], g[2] * is[2]};
-          sdd[0] = sdd[4] = sdd[8] = 0.0;
-          sdd[1] = q[1] * r01; sdd[3] = q[0] * r10;
-          sdd[2] = q[2] * r02; sdd[6] = q[0] * r20;
-          sdd[5] = q[2] * r12; sdd[7] = q[1] * r21;
-        }
-#pragma unroll
-        for (int k = 0; k < 9; k++) Pb[k] = (double)Fb[k];
-        iso_adjoint(Uu, s, V, g, dg, sdd, Pb, Fr);
-#pragma unroll
-        for (int k = 0; k < 9; k++) Ftb[k] = (float)Fr[k];
-      }
-      }
+      if (!plastic_adjoint<float>(Md, F, M, Fb, Ftb)) plastic_adjoint<double>(Md, F, M, Fb, Ftb);
     }
     // F_tr = Md F : Cbar += dt Ftb F^T ; Fbar = Md^T Ftb
     float T1[9];
