@@ -127,13 +127,14 @@ def generate_samples(target: int, device="cuda", n_scenes: int = 32, steps: int 
     """Cone-case samples of the exact projection from seeded sand rollouts:
     each scene contributes at most target / n_scenes records, logged during a
     window of `window` steps that starts at a seeded step of its rollout, so
-    that the set spans materials, grids and impact stages."""
+    that the set spans materials, grids and impact stages.  Scenes are drawn
+    (up to 16 n_scenes of them) until the target is reached."""
     from .sim import Simulator
     rng = np.random.default_rng(np.random.SeedSequence([20230302, 7, seed]))
     buf = torch.zeros(target, RECORD, dtype=torch.float32, device=device)
     quota = -(-target // n_scenes)
     have = 0
-    for s in range(8 * n_scenes):
+    for s in range(16 * n_scenes):
         if have >= target:
             break
         sc = sand_scene(s, steps=steps)

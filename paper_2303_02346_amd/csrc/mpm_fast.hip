@@ -355,10 +355,8 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
   __shared__ float s_tile[4 * TILE_NODES];
   __shared__ int s_itile[4 * TILE_NODES];
   __shared__ float4 s_v[VT_NODES];
-  __shared__ int s_lo[3], s_hi[3];
-  __shared__ float s_red[NW * 4], s_scale[8];
-  __shared__ int s_ired[NW * 6 + 6];   // per-wave box bits, then the chunk's box at RB
-  constexpr int RB = NW * 6;
+  __shared__ float s_red[NW * 4];     // per-wave bound sums of the chunk
+  __shared__ uint32_t s_ired[NW];      // per-wave box bits of the chunk
   const int tid = threadIdx.x;
   const int N = A.N;
   const uint32_t n_list = A.list_n[0];
@@ -405,9 +403,11 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
     }
     if (MODE != MODE_G2P) {
       for (int q = tid; q < 4 * TILE_NODES; q += NT) { s_tile[q] = 0.f; s_itile[q] = 0; }
-      if (tid < 3) { s_lo[tid] = 1 << 20; s_hi[tid] = -(1 << 20); }
+
     }
     __syncthreads();
+    // the tile's non-zero box over all chunks (every thread keeps the same copy)
+    int blo[3] = {1 << 20, 1 << 20, 1 << 20}, bhi[3] = {-(1 << 20), -(1 << 20), -(1 << 20)};
     for (int c0 = 0; c0 < count; c0 += NT) {
       const int j = start + c0 + tid;
       const bool has = (c0 + tid) < count && j < N;
@@ -647,44 +647,50 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
         if ((tid & 63) == 0) {
 #pragma unroll
           for (int q = 0; q < 4; q++) s_red[wv * 4 + q] = wb[q];
-          s_ired[wv] = (int)wbits;
+          s_ired[wv] = wbits;
         }
         __syncthreads();
-        if (tid == 0) {
+        // every thread derives the chunk's scales and box from the waves'
+        // partial results (no second barrier); the previous chunk's flush,
+        // which ran after its scatter barrier, is complete here as well
+        float sc[4], isc[4];
 #pragma unroll
-          for (int q = 0; q < 4; q++) {
-            float T = 0.f;
+        for (int q = 0; q < 4; q++) {
+          float T = 0.f;
 #pragma unroll
-            for (int w = 0; w < NW; w++) T += s_red[w * 4 + q];
-            T *= 0.421875f;
-            if (!isfinite(T)) { atomicOr(P.err, ERR_NONFINITE); T = 1.f; }
-            int e = 0;
-            frexpf(T > 0.f ? T : 1.f, &e);
-            e = max(e, -90);
-            s_scale[q] = ldexpf(1.f, 30 - e);
-            s_scale[4 + q] = ldexpf(1.f, e - 30);
+          for (int w = 0; w < NW; w++) T += s_red[w * 4 + q];
+          T *= 0.421875f;
+          if (!isfinite(T)) {
+            if (tid == 0) atomicOr(P.err, ERR_NONFINITE);
+            T = 1.f;
           }
+          int e = 0;
+          frexpf(T > 0.f ? T : 1.f, &e);
+          e = max(e, -90);
+          sc[q] = ldexpf(1.f, 30 - e);
+          isc[q] = ldexpf(1.f, e - 30);
+        }
+        int clo[3], chi[3];
+        {
           uint32_t cb = 0;
 #pragma unroll
-          for (int w = 0; w < NW; w++) cb |= (uint32_t)s_ired[w];
+          for (int w = 0; w < NW; w++) cb |= s_ired[w];
 #pragma unroll
           for (int a = 0; a < 3; a++) {
             const uint32_t ab = (cb >> (8 * a)) & 0xffu;
-            const int lo = ab ? __ffs(ab) - 1 : 1 << 20, hi = ab ? 31 - __clz(ab) : -(1 << 20);
-            s_ired[RB + a] = lo;
-            s_ired[RB + 3 + a] = hi;
-            if (lo <= hi) { s_lo[a] = min(s_lo[a], lo); s_hi[a] = max(s_hi[a], hi); }
+            clo[a] = ab ? __ffs(ab) - 1 : 1 << 20;
+            chi[a] = ab ? 31 - __clz(ab) : -(1 << 20);
+            if (clo[a] <= chi[a]) { blo[a] = min(blo[a], clo[a]); bhi[a] = max(bhi[a], chi[a]); }
           }
         }
-        __syncthreads();
         if (ok) {
           // mom_a(node) = mvp_a + sum_b A_ab (idx_b - f_b) dx = c0_a + sum_b Ad_ab idx_b,
           // with the quantity's power-of-two scale folded into c0 and Ad
-          const float sm = M.mass * s_scale[0];
+          const float sm = M.mass * sc[0];
           float c0[3], Ad[9];
 #pragma unroll
           for (int a = 0; a < 3; a++) {
-            const float sa = s_scale[1 + a];
+            const float sa = sc[1 + a];
 #pragma unroll
             for (int b = 0; b < 3; b++) Ad[a * 3 + b] = sa * P.dx * Am[a * 3 + b];
             c0[a] = sa * mvp[a] - (Ad[a * 3] * S.f[0] + Ad[a * 3 + 1] * S.f[1] + Ad[a * 3 + 2] * S.f[2]);
@@ -717,25 +723,23 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
         __syncthreads();
         {
           // flush the chunk's box into the float tile and clear the integers
-          const int lo0 = s_ired[RB], lo1 = s_ired[RB + 1], lo2 = s_ired[RB + 2];
-          const int hi0 = s_ired[RB + 3], hi1 = s_ired[RB + 4], hi2 = s_ired[RB + 5];
-          if (lo0 <= hi0) {
-            const int ex = hi0 - lo0 + 3, ey = hi1 - lo1 + 3, ez = hi2 - lo2 + 3;
+          // (the next chunk scatters only after its bound barrier)
+          if (clo[0] <= chi[0]) {
+            const int ex = chi[0] - clo[0] + 3, ey = chi[1] - clo[1] + 3, ez = chi[2] - clo[2] + 3;
             const int cnt = ex * ey * ez;
             for (int r = tid; r < cnt; r += NT) {
-              int qq = ((lo0 + r / (ey * ez)) * TILE + lo1 + (r / ez) % ey) * TILE + lo2 + r % ez;
+              int qq = ((clo[0] + r / (ey * ez)) * TILE + clo[1] + (r / ez) % ey) * TILE + clo[2] + r % ez;
 #pragma unroll
               for (int c = 0; c < 4; c++) {
                 int iv = s_itile[c * TILE_NODES + qq];
                 if (iv != 0) {
-                  s_tile[c * TILE_NODES + qq] += (float)iv * s_scale[4 + c];
+                  s_tile[c * TILE_NODES + qq] += (float)iv * isc[c];
                   s_itile[c * TILE_NODES + qq] = 0;
                 }
               }
             }
           }
         }
-        __syncthreads();
         if (MODE == MODE_FUSED) {
           uint32_t r = rank_finish(WR, A.touched, A.n_touched, (uint32_t)A.n_keys);
           if (has && dst < (uint32_t)N) { A.out.key[dst] = nkey; A.out.rank[dst] = counted ? r : 0u; }
@@ -752,8 +756,8 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
     __syncthreads();
     if (MODE != MODE_G2P) {
       // ---- publish the tile's non-zero box and mark the blocks it touches
-      const int lo0 = s_lo[0], lo1 = s_lo[1], lo2 = s_lo[2];
-      const int hi0 = s_hi[0] + 2, hi1 = s_hi[1] + 2, hi2 = s_hi[2] + 2;
+      const int lo0 = blo[0], lo1 = blo[1], lo2 = blo[2];
+      const int hi0 = bhi[0] + 2, hi1 = bhi[1] + 2, hi2 = bhi[2] + 2;
       const uint32_t bkey = (uint32_t)ent.x;
       if (lo0 <= hi0 - 2) {
         const int ex = hi0 - lo0 + 1, ey = hi1 - lo1 + 1, ez = hi2 - lo2 + 1;

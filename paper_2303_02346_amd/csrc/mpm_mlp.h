@@ -14,6 +14,17 @@
 
 namespace mpm {
 
+// Order the LDS writes of a wavefront's lanes before the other lanes' reads
+// of them: a wavefront-scope release/acquire pair around the wave barrier
+// (the lanes of a 64-wide wavefront execute together; only the compiler's
+// and the memory counters' ordering has to be enforced).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
 constexpr int MLP_IN = 6, MLP_H = 64, MLP_OUT = 3;
 constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_OUT * MLP_H + MLP_OUT;  // 4803
 constexpr int MLP_K1 = 16;   // layer-1 reduction dim padded to the MFMA k
@@ -99,7 +110,7 @@ __device__ inline void mlp_wave_forward(const MlpBlob& W, const float* x, float*
         S.h[(4 * lg + q) * MLP_HROW + col] = f2bf(h);
       }
     }
-    __syncwarp();
+    wave_lds_sync();
     // ---- layer 2: A = H1 (row lr, k = 16 kt + 4 lg + q)
     bf16x4_t a2[4];
 #pragma unroll
@@ -113,7 +124,7 @@ __device__ inline void mlp_wave_forward(const MlpBlob& W, const float* x, float*
         for (int k = 0; k < MLP_H; k++) h1_out[k] = bf2f(S.h[(l & 15) * MLP_HROW + k]);
       }
     }
-    __syncwarp();
+    wave_lds_sync();
     f32x4_t c2[4];
 #pragma unroll
     for (int nt = 0; nt < 4; nt++) {
@@ -136,7 +147,7 @@ __device__ inline void mlp_wave_forward(const MlpBlob& W, const float* x, float*
         S.h[(4 * lg + q) * MLP_HROW + col] = f2bf(h);
       }
     }
-    __syncwarp();
+    wave_lds_sync();
     // ---- layer 3: A = H2, B = W3 (n padded to 16)
     bf16x4_t a3[4];
 #pragma unroll
@@ -162,7 +173,7 @@ __device__ inline void mlp_wave_forward(const MlpBlob& W, const float* x, float*
 #pragma unroll
       for (int q = 0; q < 4; q++) S.y[(16 * rb + 4 * lg + q) * MLP_OUT + lr] = c3[q] + W.b3[lr];
     }
-    __syncwarp();
+    wave_lds_sync();
   }
 #pragma unroll
   for (int o = 0; o < MLP_OUT; o++) y[o] = S.y[l * MLP_OUT + o] * W.out_std[o] + W.out_mean[o];
@@ -171,7 +182,7 @@ __device__ inline void mlp_wave_forward(const MlpBlob& W, const float* x, float*
   const float dtr = ((x[0] + x[1] + x[2]) - (y[0] + y[1] + y[2])) * (1.f / 3.f);
 #pragma unroll
   for (int o = 0; o < MLP_OUT; o++) y[o] += dtr;
-  __syncwarp();
+  wave_lds_sync();
 }
 
 }  // namespace mpm
