@@ -56,6 +56,8 @@ struct FastPath {
   int N;
   PBuf buf[2];
   uint32_t *key_tmp, *rank_tmp;
+  uint32_t* inv;           // slot -> user index (import) or user index -> slot (export)
+  uint32_t* cpad;          // the import's key counters, 64 bytes apart
   uint32_t *counts, *offsets;
   uint32_t *touched, *n_touched;   // keys counted in the current step, in first-touch order
   int4* list[3];           // occupied-block lists (rotating)

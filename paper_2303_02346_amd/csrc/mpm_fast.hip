@@ -42,6 +42,7 @@ inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 // ---------------------------------------------------------------------------
 // import: block key and rank of every particle (user order)
 // ---------------------------------------------------------------------------
+constexpr int IMPORT_PAD = 16;   // uint32 words between two keys' import counters
 __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, FastGeom g, uint32_t* __restrict__ counts,
                                                      uint32_t* __restrict__ key_tmp, uint32_t* __restrict__ rank_tmp,
                                                      uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched) {
@@ -58,8 +59,16 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
       key = block_key(g, P.pscene[p], S.base[0] >> 2, S.base[1] >> 2, S.base[2] >> 2);
     }
   }
-  uint32_t r = wave_rank(counts, key, has, touched, n_touched, (uint32_t)g.n_keys);
-  if (has) { key_tmp[p] = key; rank_tmp[p] = r; }
+  // user order is arbitrary, so the lanes of a wavefront rarely share a key:
+  // one atomic per particle into counters padded to one per 64 bytes (packed
+  // counters would put hundreds of keys' atomics on a few cache lines); the
+  // first reservation of a key appends it to the touched list
+  if (has) {
+    const uint32_t r = atomicAdd(&counts[(size_t)key * IMPORT_PAD], 1u);
+    if (r == 0u) touch_key(key, touched, n_touched, (uint32_t)g.n_keys);
+    key_tmp[p] = key;
+    rank_tmp[p] = r;
+  }
 }
 
 // Exclusive scan of the counts of the touched keys -> their offsets, the
@@ -69,7 +78,7 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
 template <int NT>
 __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
                              const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
-                             int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys) {
+                             int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys, int stride = 1) {
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_sum[NW];
   __shared__ uint32_t s_run;
@@ -80,7 +89,7 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
   for (uint32_t c0 = 0; c0 < n; c0 += NT) {
     const uint32_t i = c0 + t;
     uint32_t key = 0, c = 0;
-    if (i < n) { key = touched[i]; c = counts[key]; }
+    if (i < n) { key = touched[i]; c = counts[(size_t)key * stride]; }
     uint32_t is = c;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -98,7 +107,7 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
     if (i < n) {
       const uint32_t o = woff + is - c;
       offsets[key] = o;
-      counts[key] = 0u;
+      counts[(size_t)key * stride] = 0u;
       list[i] = make_int4((int)key, (int)o, (int)c, 0);
     }
     __syncthreads();
@@ -208,36 +217,48 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, ui
                                                const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
                                                uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count,
-                                               int dense) {
+                                               int dense, int stride) {
   if (dense) {
     scan_keys<1024>(counts, offsets, list, list_n, n_keys);
     if (threadIdx.x == 0) n_touched[0] = 0u;
   } else {
-    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys);
+    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride);
   }
   if (threadIdx.x == 0) { epoch[0] = epoch[0] + 1; cl_count[0] = 0u; cl_count[1] = 0u; }
 }
 
 
 
-// scatter the user-order particles to their sorted slots
-__global__ __launch_bounds__(256) void k_permute(PState u, const uint8_t* __restrict__ umat, PBuf X,
-                                                 const uint32_t* __restrict__ key_tmp, const uint32_t* __restrict__ rank_tmp,
-                                                 const uint32_t* __restrict__ offsets) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= u.N) return;
+// The user-order particles to their sorted slots, as a gather: k_inv records
+// the user index of every slot (one scattered word per particle), k_gather_in
+// then reads each slot's particle (scattered reads) and writes the sorted rows
+// in order.
+__global__ __launch_bounds__(256) void k_inv(int N, const uint32_t* __restrict__ key_tmp,
+                                             const uint32_t* __restrict__ rank_tmp,
+                                             const uint32_t* __restrict__ offsets, uint32_t* __restrict__ inv) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const uint32_t d = offsets[key_tmp[p]] + rank_tmp[p];
+  if (d < (uint32_t)N) inv[d] = (uint32_t)p;
+}
+
+__global__ __launch_bounds__(256) void k_gather_in(PState u, const uint8_t* __restrict__ umat, PBuf X,
+                                                   const uint32_t* __restrict__ inv,
+                                                   const uint32_t* __restrict__ key_tmp,
+                                                   const uint32_t* __restrict__ rank_tmp) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
   const int N = u.N;
-  uint32_t key = key_tmp[p], r = rank_tmp[p];
-  uint32_t d = offsets[key] + r;
-  if (d >= (uint32_t)N) return;
+  if (d >= N) return;
+  const uint32_t p = inv[d];
+  if (p >= (uint32_t)N) return;
 #pragma unroll
   for (int a = 0; a < 3; a++) { X.f[a * (size_t)N + d] = u.x[a * N + p]; X.f[(3 + a) * (size_t)N + d] = u.v[a * N + p]; }
 #pragma unroll
   for (int k = 0; k < 9; k++) { X.f[(6 + k) * (size_t)N + d] = u.C[k * N + p]; X.f[(15 + k) * (size_t)N + d] = u.F[k * N + p]; }
   X.f[24 * (size_t)N + d] = u.J[p];
-  X.id[d] = (uint32_t)p;
-  X.key[d] = key;
-  X.rank[d] = r;
+  X.id[d] = p;
+  X.key[d] = key_tmp[p];
+  X.rank[d] = rank_tmp[p];
   X.mat[d] = umat[p];
 }
 
@@ -279,14 +300,24 @@ __global__ __launch_bounds__(256) void k_sort_permute(PBuf in, PBuf out, int N, 
   map[p] = d;
 }
 
-// scatter the sorted buffer back to the user arrays; liquids keep the user's
-// F and solids the user's J (those rows are not carried by the kernels)
-__global__ __launch_bounds__(256) void k_export(PBuf X, PState u, const MatDev* __restrict__ mats) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= u.N) return;
+// The sorted buffer back to the user arrays, as a gather: k_pos records the
+// sorted slot of every particle, k_gather_out reads each particle's slot and
+// writes the user rows in order.  Liquids keep the user's F and solids the
+// user's J (those rows are not carried by the kernels).
+__global__ __launch_bounds__(256) void k_pos(PBuf X, int N, uint32_t* __restrict__ pos) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= N) return;
+  const uint32_t p = X.id[d];
+  if (p < (uint32_t)N) pos[p] = (uint32_t)d;
+}
+
+__global__ __launch_bounds__(256) void k_gather_out(PBuf X, PState u, const MatDev* __restrict__ mats,
+                                                    const uint32_t* __restrict__ pos) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int N = u.N;
-  uint32_t p = X.id[j];
-  if (p >= (uint32_t)N) return;
+  if (p >= N) return;
+  const uint32_t j = pos[p];
+  if (j >= (uint32_t)N) return;
 #pragma unroll
   for (int a = 0; a < 3; a++) { u.x[a * N + p] = X.f[a * (size_t)N + j]; u.v[a * N + p] = X.f[(3 + a) * (size_t)N + j]; }
 #pragma unroll
@@ -916,7 +947,7 @@ static FastGeom make_geom(int n_grid, int S) {
 
 struct FastLayout {
   size_t buf_f[2], buf_id[2], buf_key[2], buf_rank[2], buf_mat[2], list[3];
-  size_t key_tmp, rank_tmp, counts, offsets, list_n, claim, cl_list, cl_count, touched, n_touched, tile_box, tiles,
+  size_t key_tmp, rank_tmp, inv, cpad, counts, offsets, list_n, claim, cl_list, cl_count, touched, n_touched, tile_box, tiles,
       vgrid, gen, t0;
   size_t total;
 };
@@ -936,6 +967,8 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   }
   L.key_tmp = take((size_t)N * 4);
   L.rank_tmp = take((size_t)N * 4);
+  L.inv = take((size_t)N * 4);
+  L.cpad = take((size_t)g.n_keys * IMPORT_PAD * 4);
   L.counts = take((size_t)g.n_keys * 4);
   L.offsets = take((size_t)g.n_keys * 4);
   L.list_n = take(16);
@@ -958,6 +991,19 @@ int fast_n_keys(int n_grid, int n_scenes) { return make_geom(n_grid, n_scenes).n
 
 static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
+// the import's permutation (after its key count and scan) and the export,
+// both as a scattered word per particle plus a gather
+static void import_permute(FastPath& f, const PState& user, const uint8_t* umat, const PBuf& X, hipStream_t s) {
+  const int N = f.N;
+  k_inv<<<nblk(N, 256), 256, 0, s>>>(N, f.key_tmp, f.rank_tmp, f.offsets, f.inv);
+  k_gather_in<<<nblk(N, 256), 256, 0, s>>>(user, umat, X, f.inv, f.key_tmp, f.rank_tmp);
+}
+static void export_state(FastPath& f, const PBuf& X, const PState& user, const MatDev* mats, hipStream_t s) {
+  const int N = f.N;
+  k_pos<<<nblk(N, 256), 256, 0, s>>>(X, N, f.inv);
+  k_gather_out<<<nblk(N, 256), 256, 0, s>>>(X, user, mats, f.inv);
+}
+
 int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_t s) {
   FastLayout L = fast_plan(n_grid, n_scenes, N);
   f.ws = ws;
@@ -973,6 +1019,8 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   for (int b = 0; b < 3; b++) f.list[b] = (int4*)(ws + L.list[b]);
   f.key_tmp = (uint32_t*)(ws + L.key_tmp);
   f.rank_tmp = (uint32_t*)(ws + L.rank_tmp);
+  f.inv = (uint32_t*)(ws + L.inv);
+  f.cpad = (uint32_t*)(ws + L.cpad);
   f.counts = (uint32_t*)(ws + L.counts);
   f.offsets = (uint32_t*)(ws + L.offsets);
   f.list_n = (uint32_t*)(ws + L.list_n);
@@ -1006,6 +1054,7 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.sid = 0;
   // zero the bookkeeping (counts, stamps, counters, velocity grid)
   launch_zero(ws + L.counts, a256((size_t)f.g.n_keys * 4), s);
+  launch_zero(ws + L.cpad, a256((size_t)f.g.n_keys * IMPORT_PAD * 4), s);
   launch_zero(ws + L.list_n, 256, s);
   launch_zero(ws + L.claim, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.cl_count, 256, s);
@@ -1037,10 +1086,10 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
                          const float* act, hipStream_t s, std::vector<hipEvent_t>* ev) {
   const FastGeom g = f.g;
   const int N = f.N;
-  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.counts, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
-                            f.cl_count, 0);
-  k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, f.buf[0], f.key_tmp, f.rank_tmp, f.offsets);
+  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
+  k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
+                            f.cl_count, 0, IMPORT_PAD);
+  import_permute(f, user, P.mat, f.buf[0], s);
   PartArgs A;
   A.N = N;
   A.counts = f.counts;
@@ -1087,7 +1136,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
       // the state at time t0 + step now sits in the output buffer
       if (f.ck_k > 0 && (f.ck_t0 + step) % f.ck_k == 0) {
         PState ck = packed_state((float*)(f.ck_base + (size_t)((f.ck_t0 + step) / f.ck_k) * f.ck_stride), N);
-        k_export<<<nblk(N, 256), 256, 0, s>>>(A.out, ck, P.mats);
+        export_state(f, A.out, ck, P.mats, s);
       }
     }
     // grid update of this step; from step 1 on, workgroup 0 also scans the
@@ -1116,7 +1165,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
       wr = nwr;
     }
   }
-  if (f.do_export) k_export<<<nblk(N, 256), 256, 0, s>>>(f.buf[cur], user, P.mats);
+  if (f.do_export) export_state(f, f.buf[cur], user, P.mats, s);
   f.last_buf = cur;
 }
 
@@ -1188,11 +1237,12 @@ void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, Sorted
                     bool touched) {
   const int N = f.N;
   new_epoch(f, s);
-  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
-                                             touched ? f.touched : nullptr, f.n_touched);
-  k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, touched ? 0 : 1);
-  k_permute<<<nblk(N, 256), 256, 0, s>>>(user, P.mat, out.b, f.key_tmp, f.rank_tmp, f.offsets);
+  // (the import always scans the keys it counted, in first-touch order)
+  (void)touched;
+  k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
+  k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
+                            out.cl_count ? out.cl_count : f.cl_count, 0, IMPORT_PAD);
+  import_permute(f, user, P.mat, out.b, s);
 }
 
 void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, const PBuf& next, SortedState& out,
@@ -1202,7 +1252,7 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
   k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
                                            touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, touched ? 0 : 1);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? 0 : 1, 1);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 
@@ -1282,7 +1332,7 @@ int fast_sort_snapshot(FastPath& f, const StepParams& P, const PState& user, int
 }
 
 void fast_export(FastPath& f, const StepParams& P, const PBuf& X, const PState& user, hipStream_t s) {
-  k_export<<<nblk(f.N, 256), 256, 0, s>>>(X, user, P.mats);
+  export_state(f, X, user, P.mats, s);
 }
 
 void fast_destroy(FastPath& f) {
