@@ -121,7 +121,7 @@ def bench_batched(torch, steps=100):
     n_tot = sum(sc.n for sc in scs)
     log(f"[bench] batched: {len(scs)} scenes, {n_tot} particles")
     sim = Simulator(scs, graph=True)
-    tune = sim.autotune(n_steps=10)
+    tune = sim.autotune(n_steps=min(10, steps))
     sim.reset()
     sim.step(steps)
     sim.reset()
@@ -411,6 +411,9 @@ def main():
     ap.add_argument("--no-paper-point", action="store_true")
     ap.add_argument("--no-rigid", action="store_true")
     ap.add_argument("--no-gas", action="store_true")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched leg and print its object (for profiling its kernels)")
+    ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--copy-mb", type=int, default=0, help="first run a device copy of this size (counter scaling)")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg (config 5)")
     args = ap.parse_args()
@@ -425,6 +428,9 @@ def main():
     from paper_2303_02346_amd.sim import Simulator
 
     copy_bytes = copy_calibration(torch, args.copy_mb) if args.copy_mb > 0 else None
+    if args.only_batched:
+        print(json.dumps({"batched": bench_batched(torch, steps=args.batched_steps)}), flush=True)
+        return
     ceiling = copy_ceiling(torch)
     log(f"[bench] measured copy ceiling {ceiling['GBps']} GB/s ({ceiling['frac_of_peak']} of 8 TB/s)")
     sc = scenes.config2(n_particles=args.particles, steps=max(args.steps, args.warmup, args.bwd_steps))
@@ -525,7 +531,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = bench_batched(torch)
+        batched = bench_batched(torch, steps=args.batched_steps)
 
     paper = None if args.no_paper_point else bench_paper_point(torch)
 
