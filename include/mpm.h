@@ -241,7 +241,9 @@ int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value);
  * writes the user indices of the sorted particles (id_dev, N uint32), their
  * block keys (key_dev, N uint32) and the occupied-block list (list_dev,
  * MPM_OPT_N_KEYS rows of int32 {key, offset, count, 0}; *n_list_out rows
- * are valid, in no particular order).  which = 1: writes the user indices
+ * are valid, in no particular order).  which = 2: the same, with the rows in
+ * increasing key order (the order the adjoint's recompute lists the blocks
+ * in).  which = 1: writes the user indices
  * of the sorted buffer the last forward mpm_step call left (key_dev,
  * list_dev and n_list_out unused, may be NULL; MPM_ESTATE if no such call).
  * A block key is (scene << 3 kb) | the Morton interleave of the block

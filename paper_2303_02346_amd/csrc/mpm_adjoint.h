@@ -24,6 +24,10 @@ struct AdjArgs {
   const uint32_t* cl_count;
   const float4* mmv;         // node momenta and masses of step t (block layout)
   float4* mmvb;              // their adjoints (block layout)
+  // particles whose FP32 adjoint is ill-conditioned, {row, block key}, for
+  // the FP64 pass; the count starts at zero (one counter per step and kernel)
+  uint32_t* redo_n;
+  uint2* redo;               // room for N entries
 };
 
 void launch_g2p_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, hipStream_t s);

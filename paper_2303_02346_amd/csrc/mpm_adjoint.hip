@@ -13,6 +13,10 @@
 //                         the particle update, and the scatter of the
 //                         velocity adjoint into a fixed-point LDS tile whose
 //                         non-zero box is published (no global float atomics)
+//   k_g2p_adj_redo        the particles whose plastic-return adjoint is
+//                         ill-conditioned in FP32, listed by the kernel
+//                         above: the same steps with the FP64 adjoint, the
+//                         scatter added to the published tiles
 //   k_grid_adj_tiled      per node of the blocks claimed in the recompute:
 //                         sum of the 27 neighbouring tiles, then the adjoint
 //                         of the node update (walls, contact, gravity,
@@ -20,7 +24,11 @@
 //                         per wavefront before one FP64 atomic per scene
 //   k_p2g_adj_tiled       one workgroup per occupied block: the P2G adjoint
 //                         gathered from an LDS copy of the node adjoints,
-//                         through the stress adjoint.
+//                         through the stress adjoint
+//   k_p2g_adj_redo        the solids whose F is ill-conditioned in FP32,
+//                         listed by the kernel above: the same with FP64 SVDs.
+// The FP64 paths run in kernels of their own so that their register demand
+// does not set the occupancy of the common FP32 path.
 // The adjoint of s_{t+1} is read through the row map that the segment's sort
 // recorded, so no separate permutation pass is needed.
 #include <hip/hip_runtime.h>
@@ -48,10 +56,10 @@ __device__ inline float4 stage_node(const float4* __restrict__ src, const FastGe
 // adjoint.  Writes the direct part of the state adjoint of s_t (x, F, J; the
 // v and C adjoints of s_t come only through P2G and are added later).
 // ---------------------------------------------------------------------------
-// (two workgroups per CU: a few spilled registers cost less than the
-// latency that one wavefront per SIMD leaves exposed)
+// (three workgroups per CU; the FP64 plastic-return adjoint runs in
+// k_g2p_adj_redo, so that its registers do not count here)
 template <int NT>
-__global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P, FastGeom g) {
+__global__ __launch_bounds__(NT, 3) void k_g2p_adj_tiled(AdjArgs A, StepParams P, FastGeom g) {
   constexpr int NW = NT / 64;
   constexpr int NQ = 3;   // velocity adjoint components
   __shared__ float4 s_v[VT_NODES];
@@ -106,9 +114,11 @@ __global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P
         else if (A.map[j] >= (uint32_t)N) { atomicOr(P.err, ERR_TILE); ok = false; }
       }
       float vbt[3] = {0, 0, 0}, Bb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, bnd[NQ] = {0, 0, 0};
+      float vn[3], xb[3], Fbo[9], Jbo = 0.f;
+      bool defer = false;
       if (ok) {
         // G2P recomputed from the staged velocities
-        float vn[3], Bi[9];
+        float Bi[9];
         g2p_gather(s_v, lv, S, vn, Bi);
         float B[9];
 #pragma unroll
@@ -118,14 +128,19 @@ __global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P
         // adjoint of s_{t+1}, row jn of the next state's order
         const uint32_t jn = A.map[j];
         const float* an = A.abar_next;
-        float xb[3], vb[3], Cb[9], Fb[9];
+        float vb[3], Cb[9], Fb[9];
 #pragma unroll
         for (int a = 0; a < 3; a++) { xb[a] = an[a * (size_t)N + jn]; vb[a] = an[(3 + a) * (size_t)N + jn]; }
 #pragma unroll
         for (int k = 0; k < 9; k++) { Cb[k] = an[(6 + k) * (size_t)N + jn]; Fb[k] = an[(15 + k) * (size_t)N + jn]; }
         const float Jb = an[24 * (size_t)N + jn];
-        float Fbo[9], Jbo;
-        particle_update_adjoint(x, vn, B, M, P, st, j, xb, vb, Cb, Fb, Jb, vbt, Bb, Fbo, Jbo);
+        defer = !particle_update_adjoint<ADJ_FP32>(x, vn, B, M, P, st, j, xb, vb, Cb, Fb, Jb, vbt, Bb, Fbo, Jbo);
+      }
+      if (defer) {
+        // listed for the FP64 pass; it stays in the tile box, scatters nothing here
+        const uint32_t r = atomicAdd(A.redo_n, 1u);
+        A.redo[r] = make_uint2((uint32_t)j, (uint32_t)ent.x);
+      } else if (ok) {
         // position adjoint through the weights and the node offsets:
         // xo = xb + sum_i grad w_i (v_i . (vbt + Bb (x_i - x_p))) - Bb^T vn
         float xo[3];
@@ -207,7 +222,7 @@ __global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P
         }
       }
       __syncthreads();
-      if (ok) {
+      if (ok && !defer) {
         // c_a(node) = w (vbt_a + sum_b Bb_ab (idx_b - f_b) dx), scaled
         float c0[3], Ad[9];
 #pragma unroll
@@ -275,6 +290,97 @@ __global__ __launch_bounds__(NT, 2) void k_g2p_adj_tiled(AdjArgs A, StepParams P
       }
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The FP64 pass of the G2P adjoint over the particles k_g2p_adj_tiled listed:
+// each thread stages its particle's 27 stencil nodes in LDS and repeats the
+// steps above with the FP64 plastic-return adjoint; its velocity-adjoint
+// scatter goes into the block's published tile with float atomics (the
+// listed particles were kept inside the tile's box).
+// ---------------------------------------------------------------------------
+constexpr int REDO_NT = 64, REDO_WGS = 256;
+
+__global__ __launch_bounds__(REDO_NT) void k_g2p_adj_redo(AdjArgs A, StepParams P, FastGeom g) {
+  __shared__ float4 s_loc[REDO_NT * 27];
+  float4* loc = s_loc + threadIdx.x * 27;
+  const int N = A.N;
+  const PState st = packed_state(A.st.f, N);
+  const uint32_t n = A.redo_n[0];
+  for (uint32_t e = blockIdx.x * REDO_NT + threadIdx.x; e < n; e += gridDim.x * REDO_NT) {
+    const uint2 r = A.redo[e];
+    const int j = (int)r.x;
+    int sc, bx, by, bz;
+    key_decode(g, r.y, sc, bx, by, bz);
+    float x[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) x[a] = st.x[a * (size_t)N + j];
+    const MatDev& M = P.mats[A.st.mat[j]];
+    Stencil S;
+    stencil_setup(x, P, S);   // inside the grid and the tile: checked when listed
+    const int lb[3] = {S.base[0] - (4 * bx - 2), S.base[1] - (4 * by - 2), S.base[2] - (4 * bz - 2)};
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int jj = 0; jj < 3; jj++)
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+          loc[(i * 3 + jj) * 3 + k] = stage_node(A.vgrid, g, sc, S.base[0] + i, S.base[1] + jj, S.base[2] + k);
+    const int l0[3] = {0, 0, 0};
+    float vn[3], Bi[9], B[9];
+    g2p_gather<3>(loc, l0, S, vn, Bi);
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) B[a * 3 + b] = P.dx * (Bi[a * 3 + b] - vn[a] * S.f[b]);
+    const uint32_t jn = A.map[j];
+    const float* an = A.abar_next;
+    float xb[3], vb[3], Cb[9], Fb[9];
+#pragma unroll
+    for (int a = 0; a < 3; a++) { xb[a] = an[a * (size_t)N + jn]; vb[a] = an[(3 + a) * (size_t)N + jn]; }
+#pragma unroll
+    for (int k = 0; k < 9; k++) { Cb[k] = an[(6 + k) * (size_t)N + jn]; Fb[k] = an[(15 + k) * (size_t)N + jn]; }
+    const float Jb = an[24 * (size_t)N + jn];
+    float vbt[3], Bb[9], Fbo[9], Jbo;
+    particle_update_adjoint<ADJ_FP64>(x, vn, B, M, P, st, j, xb, vb, Cb, Fb, Jb, vbt, Bb, Fbo, Jbo);
+    float c0[3], Ad[9], X[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+      for (int b = 0; b < 3; b++) Ad[a * 3 + b] = P.dx * Bb[a * 3 + b];
+      c0[a] = vbt[a] - (Ad[a * 3] * S.f[0] + Ad[a * 3 + 1] * S.f[1] + Ad[a * 3 + 2] * S.f[2]);
+    }
+    weight_grad_sum<false, 3>(loc, l0, S, c0, Ad, 0.f, X, nullptr, nullptr);
+    float* ab = A.abar;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      ab[a * (size_t)N + j] = xb[a] + P.inv_dx * X[a] - (Bb[a] * vn[0] + Bb[3 + a] * vn[1] + Bb[6 + a] * vn[2]);
+      ab[(3 + a) * (size_t)N + j] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) { ab[(6 + k) * (size_t)N + j] = 0.f; ab[(15 + k) * (size_t)N + j] = Fbo[k]; }
+    ab[24 * (size_t)N + j] = Jbo;
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 9; k++) fin = fin && isfinite(Ad[k]);
+    if (!(fin && isfinite(c0[0] + c0[1] + c0[2]))) { atomicOr(P.err, ERR_NONFINITE); continue; }
+    float* T = A.tiles + (size_t)r.y * 4 * TILE_NODES + (lb[0] * TILE + lb[1]) * TILE + lb[2];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int jj = 0; jj < 3; jj++) {
+        const float wxy = S.w[0][i] * S.w[1][jj];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          const float w = wxy * S.w[2][k];
+          const int q = (i * TILE + jj) * TILE + k;
+#pragma unroll
+          for (int a = 0; a < 3; a++)
+            atomicAdd(&T[a * TILE_NODES + q],
+                      w * (c0[a] + (float)i * Ad[a * 3] + (float)jj * Ad[a * 3 + 1] + (float)k * Ad[a * 3 + 2]));
+        }
+      }
   }
 }
 
@@ -363,6 +469,77 @@ __global__ __launch_bounds__(256) void k_grid_adj_tiled(AdjArgs A, StepParams P,
 // Adjoint of P2G: gather of the node adjoints, through the stress adjoint;
 // added to the state adjoint of s_t.
 // ---------------------------------------------------------------------------
+// One particle.  FP64 = false: the stress and its adjoint from one FP32 SVD;
+// returns false, before doing anything, for a solid whose F is
+// ill-conditioned (s2 < s0/4) or whose FP32 sweeps do not converge.
+// FP64 = true: the stress and its adjoint from FP64 SVDs, for the particles
+// the FP32 pass returned (k_p2g_adj_redo).  The tile holds E^3 nodes, lv is
+// the stencil's first node in it.
+template <bool FP64, int E>
+MPM_DI bool p2g_adj_particle(const AdjArgs& A, const StepParams& P, const PState& st, const float4* tile,
+                             const int* lv, const Stencil& S, int j) {
+  const int N = A.N;
+  const MatDev& M = P.mats[A.st.mat[j]];
+  const bool liquid = M.kind == KIND_LIQUID;
+  float Ff[9], U[9], sv[3], V[9], tau[9];
+  const float Jv = st.J[j];
+  float C[9];
+#pragma unroll
+  for (int k = 0; k < 9; k++) C[k] = st.C[k * (size_t)N + j];
+  if (liquid) {
+    if (FP64) return true;
+    stress_liquid(Jv, C, M, tau);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; k++) Ff[k] = st.F[k * (size_t)N + j];
+    if (FP64) {
+      stress_solid(Ff, M, tau);
+    } else {
+      if (!(svd3(Ff, U, sv, V) && sv[2] > 0.25f * sv[0])) return false;
+      stress_solid_usv(Ff, U, sv, V, M, tau);
+    }
+  }
+  float v[3] = {st.v[j], st.v[(size_t)N + j], st.v[2 * (size_t)N + j]};
+  float Am[9];
+  const float scl = -P.dt * M.vol * 4.f * P.inv_dx * P.inv_dx;
+#pragma unroll
+  for (int k = 0; k < 9; k++) Am[k] = scl * tau[k] + M.mass * C[k];
+  const float mvp[3] = {M.mass * v[0], M.mass * v[1], M.mass * v[2]};
+  // node adjoints gathered: mom_i = mvp + Am (x_i - x_p) = c0 + Ad idx_i
+  float vb[3], Ab[9], xb[3];
+  {
+    float c0[3], Ad[9], X[3], G0[3], Gi[9];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+      for (int b = 0; b < 3; b++) Ad[a * 3 + b] = P.dx * Am[a * 3 + b];
+      c0[a] = mvp[a] - (Ad[a * 3] * S.f[0] + Ad[a * 3 + 1] * S.f[1] + Ad[a * 3 + 2] * S.f[2]);
+    }
+    weight_grad_sum<true, E>(tile, lv, S, c0, Ad, M.mass, X, G0, Gi);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      vb[a] = M.mass * G0[a];
+#pragma unroll
+      for (int b = 0; b < 3; b++) Ab[a * 3 + b] = P.dx * (Gi[a * 3 + b] - G0[a] * S.f[b]);
+      xb[a] = P.inv_dx * X[a] - (Am[a] * G0[0] + Am[3 + a] * G0[1] + Am[6 + a] * G0[2]);
+    }
+  }
+  float taub[9], Cb[9], Fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 9; k++) { taub[k] = scl * Ab[k]; Cb[k] = M.mass * Ab[k]; }
+  float Jb = 0.f;
+  if (liquid) stress_liquid_adjoint(Jv, C, M, taub, Jb, Cb);
+  else if (FP64) stress_solid_adjoint(Ff, M, taub, Fb);
+  else stress_solid_adjoint_usv(Ff, U, sv, V, M, taub, Fb);
+  float* ab = A.abar;
+#pragma unroll
+  for (int a = 0; a < 3; a++) { ab[a * (size_t)N + j] += xb[a]; ab[(3 + a) * (size_t)N + j] += vb[a]; }
+#pragma unroll
+  for (int k = 0; k < 9; k++) { ab[(6 + k) * (size_t)N + j] += Cb[k]; ab[(15 + k) * (size_t)N + j] += Fb[k]; }
+  ab[24 * (size_t)N + j] += Jb;
+  return true;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_p2g_adj_tiled(AdjArgs A, StepParams P, FastGeom g) {
   __shared__ float4 s_g[VT_NODES];
@@ -389,67 +566,40 @@ __global__ __launch_bounds__(NT) void k_p2g_adj_tiled(AdjArgs A, StepParams P, F
       if (!stencil_setup(x, P, S)) continue;   // reported by the G2P adjoint
       int lv[3] = {S.base[0] - (ox - 1), S.base[1] - (oy - 1), S.base[2] - (oz - 1)};
       if (lv[0] < 0 || lv[1] < 0 || lv[2] < 0 || lv[0] > VT - 3 || lv[1] > VT - 3 || lv[2] > VT - 3) continue;
-      const MatDev& M = P.mats[A.st.mat[j]];
-      float v[3] = {st.v[j], st.v[(size_t)N + j], st.v[2 * (size_t)N + j]};
-      float C[9];
-#pragma unroll
-      for (int k = 0; k < 9; k++) C[k] = st.C[k * (size_t)N + j];
-      float tau[9];
-      const float Jv = st.J[j];
-      // one FP32 SVD serves the stress and its adjoint; an ill-conditioned
-      // F (s2 < s0/4) or an unconverged sweep takes the FP64 SVD instead,
-      // for the stress here and again for its adjoint after the gather (so
-      // that no FP64 factor stays live across it)
-      float Ff[9], U[9], sv[3], V[9];
-      bool fp32 = true;
-      if (M.kind == KIND_LIQUID) {
-        stress_liquid(Jv, C, M, tau);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 9; k++) Ff[k] = st.F[k * (size_t)N + j];
-        fp32 = svd3(Ff, U, sv, V) && sv[2] > 0.25f * sv[0];
-        if (fp32) stress_solid_usv(Ff, U, sv, V, M, tau);
-        else stress_solid(Ff, M, tau);
+      if (!p2g_adj_particle<false, VT>(A, P, st, s_g, lv, S, j)) {
+        const uint32_t r = atomicAdd(A.redo_n, 1u);
+        A.redo[r] = make_uint2((uint32_t)j, (uint32_t)ent.x);
       }
-      float Am[9];
-      const float scl = -P.dt * M.vol * 4.f * P.inv_dx * P.inv_dx;
-#pragma unroll
-      for (int k = 0; k < 9; k++) Am[k] = scl * tau[k] + M.mass * C[k];
-      const float mvp[3] = {M.mass * v[0], M.mass * v[1], M.mass * v[2]};
-      // node adjoints gathered: mom_i = mvp + Am (x_i - x_p) = c0 + Ad idx_i
-      float vb[3], Ab[9], xb[3];
-      {
-        float c0[3], Ad[9], X[3], G0[3], Gi[9];
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-#pragma unroll
-          for (int b = 0; b < 3; b++) Ad[a * 3 + b] = P.dx * Am[a * 3 + b];
-          c0[a] = mvp[a] - (Ad[a * 3] * S.f[0] + Ad[a * 3 + 1] * S.f[1] + Ad[a * 3 + 2] * S.f[2]);
-        }
-        weight_grad_sum<true>(s_g, lv, S, c0, Ad, M.mass, X, G0, Gi);
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-          vb[a] = M.mass * G0[a];
-#pragma unroll
-          for (int b = 0; b < 3; b++) Ab[a * 3 + b] = P.dx * (Gi[a * 3 + b] - G0[a] * S.f[b]);
-          xb[a] = P.inv_dx * X[a] - (Am[a] * G0[0] + Am[3 + a] * G0[1] + Am[6 + a] * G0[2]);
-        }
-      }
-      float taub[9], Cb[9], Fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int k = 0; k < 9; k++) { taub[k] = scl * Ab[k]; Cb[k] = M.mass * Ab[k]; }
-      float Jb = 0.f;
-      if (M.kind == KIND_LIQUID) stress_liquid_adjoint(Jv, C, M, taub, Jb, Cb);
-      else if (fp32) stress_solid_adjoint_usv(Ff, U, sv, V, M, taub, Fb);
-      else stress_solid_adjoint(Ff, M, taub, Fb);
-      float* ab = A.abar;
-#pragma unroll
-      for (int a = 0; a < 3; a++) { ab[a * (size_t)N + j] += xb[a]; ab[(3 + a) * (size_t)N + j] += vb[a]; }
-#pragma unroll
-      for (int k = 0; k < 9; k++) { ab[(6 + k) * (size_t)N + j] += Cb[k]; ab[(15 + k) * (size_t)N + j] += Fb[k]; }
-      ab[24 * (size_t)N + j] += Jb;
     }
     __syncthreads();
+  }
+}
+
+// The FP64 pass of the P2G adjoint over the solids k_p2g_adj_tiled listed:
+// each thread stages its particle's 27 stencil nodes in LDS.
+__global__ __launch_bounds__(REDO_NT) void k_p2g_adj_redo(AdjArgs A, StepParams P, FastGeom g) {
+  __shared__ float4 s_loc[REDO_NT * 27];
+  float4* loc = s_loc + threadIdx.x * 27;
+  const int N = A.N;
+  const PState st = packed_state(A.st.f, N);
+  const uint32_t n = A.redo_n[0];
+  for (uint32_t e = blockIdx.x * REDO_NT + threadIdx.x; e < n; e += gridDim.x * REDO_NT) {
+    const uint2 r = A.redo[e];
+    const int j = (int)r.x;
+    int sc, bx, by, bz;
+    key_decode(g, r.y, sc, bx, by, bz);
+    float x[3] = {st.x[j], st.x[(size_t)N + j], st.x[2 * (size_t)N + j]};
+    Stencil S;
+    stencil_setup(x, P, S);   // inside the grid and the block's tile: checked when listed
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int jj = 0; jj < 3; jj++)
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+          loc[(i * 3 + jj) * 3 + k] = stage_node(A.mmvb, g, sc, S.base[0] + i, S.base[1] + jj, S.base[2] + k);
+    const int l0[3] = {0, 0, 0};
+    p2g_adj_particle<true, 3>(A, P, st, loc, l0, S, j);
   }
 }
 
@@ -470,6 +620,7 @@ static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1
 
 void launch_g2p_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, hipStream_t s) {
   k_g2p_adj_tiled<256><<<n_wgs, 256, 0, s>>>(A, P, g);
+  k_g2p_adj_redo<<<REDO_WGS, REDO_NT, 0, s>>>(A, P, g);
 }
 void launch_grid_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, const double* pose_t,
                            const float* act_t, double* acc_t, hipStream_t s) {
@@ -477,6 +628,7 @@ void launch_grid_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom
 }
 void launch_p2g_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, hipStream_t s) {
   k_p2g_adj_tiled<256><<<n_wgs, 256, 0, s>>>(A, P, g);
+  k_p2g_adj_redo<<<REDO_WGS, REDO_NT, 0, s>>>(A, P, g);
 }
 void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, bool to_user, hipStream_t s) {
   k_adj_reorder<<<nblk(N, 256), 256, 0, s>>>(in, out, id, N, to_user ? 1 : 0);

@@ -52,6 +52,7 @@ struct Layout {
   size_t mats, offs, pscene, cyl_radius, err, mmv, vgrid, vbar, mmvb, pose, act, acc, ckpt, seg, adj0, adj1, scratch;
   size_t fast, cstats;
   size_t tmp, mmvb_blk;   // tiled adjoint: G2P output, node adjoints of (mv, m)
+  size_t redo_n, redo;    // tiled adjoint: FP64-pass counters (two per step) and list
   SortedRec rec, tmp_rec;
   // rigid bodies: rest offsets, material -> body table, body constants,
   // sums, per-step projection records, adjoint terms, set-up sums, status
@@ -122,12 +123,14 @@ Layout plan(const mpm_desc* d) {
     L.seg = take(plain_seg > tiled_seg ? plain_seg : tiled_seg);
     L.tmp = take(L.tmp_rec.bytes);
     L.mmvb_blk = take(n_keys * 64 * sizeof(float4));
+    L.redo_n = take(2 * T * sizeof(uint32_t));
+    L.redo = take(N * sizeof(uint2));
     L.adj0 = take(st);
     L.adj1 = take(st);
   } else {
     L.n_ckpt = 0;
     L.vbar = L.mmvb = L.acc = L.ckpt = L.seg = L.adj0 = L.adj1 = 0;
-    L.tmp = L.mmvb_blk = 0;
+    L.tmp = L.mmvb_blk = L.redo_n = L.redo = 0;
     L.rec = L.tmp_rec = SortedRec{};
   }
   L.n_bodies = count_bodies(d);
@@ -548,6 +551,8 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
       A.cl_count = Si.cl_count;
       A.mmv = Si.mmv;
       A.mmvb = mmvb_blk;
+      A.redo = (uint2*)(c->ws + c->L.redo);
+      A.redo_n = (uint32_t*)(c->ws + c->L.redo_n) + 2 * t;
       // the adjoint of the rigid projection turns the body rows of the
       // adjoint of s_{t+1} into the adjoint of the G2P output
       if (rigid)
@@ -556,6 +561,7 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
       launch_g2p_adj_tiled(A, P, f.g, f.part_wgs, s);
       launch_grid_adj_tiled(A, P, f.g, f.grid_wgs, pose_at(c, t), act_at(c, t),
                             acc + (size_t)t * c->d.n_scenes * ACC_DOUBLES, s);
+      A.redo_n += 1;
       launch_p2g_adj_tiled(A, P, f.g, f.part_wgs, s);
       PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
     }
@@ -591,6 +597,7 @@ int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_d
   launch_zero(acc, align_up((size_t)T * S * ACC_DOUBLES * sizeof(double)), s);
   int n_seg = (T + k - 1) / k;
   if (!c->plain_adjoint) {
+    launch_zero(c->ws + c->L.redo_n, align_up(2 * (size_t)T * sizeof(uint32_t)), s);
     int rc = backward_tiled(c, P, a_cur, a_nxt, acc);
     if (rc != MPM_OK) return rc;
     n_seg = 0;
@@ -699,8 +706,8 @@ int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value) {
 
 int mpm_sort_snapshot(mpm_ctx* c, int32_t which, uint32_t* id_dev, uint32_t* key_dev, int32_t* list_dev,
                       int32_t* n_list_out) {
-  if (!c || !id_dev || (which != 0 && which != 1)) return MPM_EINVAL;
-  if (which == 0 && (!key_dev || !list_dev || !n_list_out)) return MPM_EINVAL;
+  if (!c || !id_dev || which < 0 || which > 2) return MPM_EINVAL;
+  if (which != 1 && (!key_dev || !list_dev || !n_list_out)) return MPM_EINVAL;
   if (!c->has_state) return MPM_ESTATE;
   StepParams P = make_params(c);
   int nl = 0;
@@ -708,7 +715,7 @@ int mpm_sort_snapshot(mpm_ctx* c, int32_t which, uint32_t* id_dev, uint32_t* key
                                     (int4*)list_dev, &nl, c->stream);
   if (rc == -1) return MPM_ESTATE;
   if (rc != 0) return MPM_EHIP;
-  if (which == 0) *n_list_out = nl;
+  if (which != 1) *n_list_out = nl;
   return finish(c);
 }
 

@@ -130,8 +130,8 @@ void fast_destroy(FastPath& f);
 // one forward step's parts on a sorted state: P2G tiles and block claims
 // under step id `sid` (from fast_next_sid), the grid update of step t (with
 // st.mmv, also the node momenta and masses), and G2P into `out` in the same
-// row order.  The sorts scan all keys (blocks in Morton order) unless
-// `touched` is set: then only the keys counted, in first-touch order.
+// row order.  The sorts scan the keys they counted; the blocks are listed in
+// key (Morton) order unless `touched` is set: then in first-touch order.
 uint32_t fast_next_sid(FastPath& f);
 void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s,
                     bool touched = false);
@@ -147,7 +147,8 @@ SortedState fast_own_state(FastPath& f, int b);
 // Integer outputs of the block sort (for checking it): which = 0 sorts the
 // user state (the import of every call) and copies the sorted ids and keys
 // (N each) and the occupied-block list (n_keys rows) to the given device
-// arrays and the list length to *n_list_host; which = 1 copies the ids of
+// arrays and the list length to *n_list_host; which = 2 the same with the
+// blocks in key order (the adjoint's sorts); which = 1 copies the ids of
 // the buffer the last call left.  Returns 0, or -1 (nothing recorded yet).
 int fast_sort_snapshot(FastPath& f, const StepParams& P, const PState& user, int which, uint32_t* id_out,
                        uint32_t* key_out, int4* list_out, int* n_list_host, hipStream_t s);

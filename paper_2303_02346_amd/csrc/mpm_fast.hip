@@ -120,11 +120,11 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
 // Dense variant: exclusive scan of all counts -> offsets, the list of
 // occupied keys in key (Morton) order, and the counts zeroed.  Run by one
 // workgroup of NT threads; each thread owns a contiguous range of keys,
-// loaded as independent 16-byte loads.  The adjoint's segment sorts use it:
-// its kernels run faster on blocks in Morton order.
+// loaded as independent 16-byte loads (the counters of key k at
+// counts[k * stride]; with stride > 1, one load per key).
 template <int NT>
 __device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, int4* __restrict__ list,
-                          uint32_t* __restrict__ list_n, int n_keys) {
+                          uint32_t* __restrict__ list_n, int n_keys, int stride = 1) {
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_sum[NW], s_nz[NW];
   const int t = threadIdx.x;
@@ -135,12 +135,13 @@ __device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ 
 #pragma unroll
     for (int u = 0; u < 8; u++) {
       const int k = k0 + b + 4 * u;
-      if (b + 4 * u < per && k + 3 < n_keys) v[u] = *(const uint4*)(counts + k);
+      if (stride == 1 && b + 4 * u < per && k + 3 < n_keys) v[u] = *(const uint4*)(counts + k);
       else {
-        v[u].x = (b + 4 * u < per && k < n_keys) ? counts[k] : 0u;
-        v[u].y = (b + 4 * u < per && k + 1 < n_keys) ? counts[k + 1] : 0u;
-        v[u].z = (b + 4 * u < per && k + 2 < n_keys) ? counts[k + 2] : 0u;
-        v[u].w = 0u;
+        const bool in = b + 4 * u < per;
+        v[u].x = (in && k < n_keys) ? counts[(size_t)k * stride] : 0u;
+        v[u].y = (in && k + 1 < n_keys) ? counts[(size_t)(k + 1) * stride] : 0u;
+        v[u].z = (in && k + 2 < n_keys) ? counts[(size_t)(k + 2) * stride] : 0u;
+        v[u].w = (in && k + 3 < n_keys) ? counts[(size_t)(k + 3) * stride] : 0u;
       }
     }
   };
@@ -198,28 +199,33 @@ __device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ 
         if (c[q] > 0) { list[li] = make_int4(k + q, (int)run, (int)c[q], 0); li++; }
         run += c[q];
       }
-      if (k + 3 < n_keys) {
+      if (k + 3 < n_keys && stride == 1) {
         *(uint4*)(offsets + k) = make_uint4(o[0], o[1], o[2], o[3]);
         *(uint4*)(counts + k) = make_uint4(0, 0, 0, 0);
       } else {
 #pragma unroll
         for (int q = 0; q < 4; q++)
-          if (k + q < n_keys) { offsets[k + q] = o[q]; counts[k + q] = 0; }
+          if (k + q < n_keys) { offsets[k + q] = o[q]; counts[(size_t)(k + q) * stride] = 0; }
       }
     }
   }
   if (t == NT - 1) list_n[0] = totnz;
 }
 
-// the import's scan; also advances the per-call epoch of the step stamps
-// (and clears the two claimed-block counters of the steps that follow)
+// The scan of a sort; also advances the per-call epoch of the step stamps
+// (and clears the two claimed-block counters of the steps that follow).
+// mode SCAN_TOUCHED: the touched keys, blocks listed in first-touch order;
+// SCAN_DENSE: all keys, blocks listed in key (Morton) order.
+constexpr int SCAN_TOUCHED = 0, SCAN_DENSE = 1;
+
 __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
                                                const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
                                                uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count,
-                                               int dense, int stride) {
-  if (dense) {
-    scan_keys<1024>(counts, offsets, list, list_n, n_keys);
+                                               int mode, int stride) {
+  constexpr int NT = 1024;
+  if (mode == SCAN_DENSE) {
+    scan_keys<NT>(counts, offsets, list, list_n, n_keys, stride);
     if (threadIdx.x == 0) n_touched[0] = 0u;
   } else {
     scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride);
@@ -1088,7 +1094,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   const int N = f.N;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
-                            f.cl_count, 0, IMPORT_PAD);
+                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD);
   import_permute(f, user, P.mat, f.buf[0], s);
   PartArgs A;
   A.N = N;
@@ -1237,11 +1243,10 @@ void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, Sorted
                     bool touched) {
   const int N = f.N;
   new_epoch(f, s);
-  // (the import always scans the keys it counted, in first-touch order)
-  (void)touched;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, 0, IMPORT_PAD);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE,
+                            IMPORT_PAD);
   import_permute(f, user, P.mat, out.b, s);
 }
 
@@ -1252,7 +1257,7 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
   k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
                                            touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, touched ? 0 : 1, 1);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 
@@ -1311,9 +1316,9 @@ SortedState fast_own_state(FastPath& f, int b) {
 int fast_sort_snapshot(FastPath& f, const StepParams& P, const PState& user, int which, uint32_t* id_out,
                        uint32_t* key_out, int4* list_out, int* n_list_host, hipStream_t s) {
   const size_t N = (size_t)f.N;
-  if (which == 0) {
+  if (which == 0 || which == 2) {
     SortedState st = fast_own_state(f, 0);
-    fast_sort_user(f, P, user, st, s, true);
+    fast_sort_user(f, P, user, st, s, which == 0);
     f.last_buf = -1;   // buffer 0 no longer holds the last call's state
     uint32_t nl = 0;
     if (hipMemcpyAsync(id_out, st.b.id, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||

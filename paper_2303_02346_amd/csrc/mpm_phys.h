@@ -541,7 +541,14 @@ MPM_DI bool plastic_adjoint(const float* Md, const float* F, const MatDev& M, co
 // Adjoint of particle_update.  Inputs: the output adjoints (xb, vb, Cb, Fb,
 // Jb).  Outputs: vbt = adjoint of vn, Bb = adjoint of B, Fbo/Jbo = adjoint of
 // the input F/J.  The direct x term (x' = x + ...) is left to the caller.
-MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float* B, const MatDev& M, const StepParams& P,
+// PREC selects the precision of the plastic-return adjoint: ADJ_AUTO takes
+// the FP32 adjoint and redoes an ill-conditioned one in FP64; ADJ_FP32
+// returns false, with nothing written, where the FP32 adjoint is
+// ill-conditioned (the caller redoes the particle with ADJ_FP64); ADJ_FP64
+// takes the FP64 adjoint.  Returns true otherwise.
+enum { ADJ_AUTO = 0, ADJ_FP32 = 1, ADJ_FP64 = 2 };
+template <int PREC = ADJ_AUTO>
+MPM_DI bool particle_update_adjoint(const float* x, const float* vn, const float* B, const MatDev& M, const StepParams& P,
                                     const PState& in, int p, const float* xb, const float* vb, const float* Cb,
                                     const float* Fb, float Jb, float* vbt, float* Bb, float* Fbo, float& Jbo) {
   const int N = in.N;
@@ -572,7 +579,11 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
 #pragma unroll
       for (int k = 0; k < 9; k++) Ftb[k] = Fb[k];
     } else {
-      if (!plastic_adjoint<float>(Md, F, M, Fb, Ftb)) plastic_adjoint<double>(Md, F, M, Fb, Ftb);
+      if (PREC == ADJ_FP64) plastic_adjoint<double>(Md, F, M, Fb, Ftb);
+      else if (!plastic_adjoint<float>(Md, F, M, Fb, Ftb)) {
+        if (PREC == ADJ_FP32) return false;
+        plastic_adjoint<double>(Md, F, M, Fb, Ftb);
+      }
     }
     // F_tr = Md F : Cbar += dt Ftb F^T ; Fbar = Md^T Ftb
     float T1[9];
@@ -583,6 +594,7 @@ MPM_DI void particle_update_adjoint(const float* x, const float* vn, const float
   }
 #pragma unroll
   for (int k = 0; k < 9; k++) Bb[k] = d4 * Cbt[k];
+  return true;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,5 +1,6 @@
 // Sums over the 27 nodes of a particle's quadratic B-spline stencil, read
-// from a tile of VT^3 nodes staged in LDS (lb = the stencil's first node in
+// from a tile of E^3 nodes staged in LDS (E = VT for a block's velocity
+// tile, 3 for one particle's own stencil; lb = the stencil's first node in
 // the tile), shared by the forward and adjoint transfer kernels.
 //
 // Both sums run over z inside y inside x, so that each partial sum is
@@ -16,6 +17,7 @@ namespace mpm {
 
 // G2P gather: vn = sum_i w_i v_i and Bi = sum_i w_i v_i idx_i^T with idx_i
 // in {0,1,2}^3 the node's offset in the stencil (v_i = the tile's xyz).
+template <int E = VT>
 __device__ __forceinline__ void g2p_gather(const float4* __restrict__ s_v, const int* lb, const Stencil& S,
                                            float* vn, float* Bi) {
 #pragma unroll
@@ -28,7 +30,7 @@ __device__ __forceinline__ void g2p_gather(const float4* __restrict__ s_v, const
     float p0[3] = {0, 0, 0}, pj[3] = {0, 0, 0}, pk[3] = {0, 0, 0};
 #pragma unroll
     for (int jj = 0; jj < 3; jj++) {
-      const float4* row = s_v + ((lb[0] + i) * VT + lb[1] + jj) * VT + lb[2];
+      const float4* row = s_v + ((lb[0] + i) * E + lb[1] + jj) * E + lb[2];
       const float4 g0 = row[0], g1 = row[1], g2 = row[2];
       // r = sum_k w_k v_k, rk = sum_k k w_k v_k along z
       const float r[3] = {S.w[2][0] * g0.x + wz1 * g1.x + wz2 * g2.x, S.w[2][0] * g0.y + wz1 * g1.y + wz2 * g2.y,
@@ -61,7 +63,7 @@ __device__ __forceinline__ void g2p_gather(const float4* __restrict__ s_v, const
 // adjoint of the node's momentum, mom = mvp + A (x_i - x_p), or of the G2P
 // terms v_i (vbt + Bb (x_i - x_p)), written as c0 + Ad idx).  With WANT_G it
 // also returns G0 = sum_i w_i g_i.xyz and Gi = sum_i w_i g_i.xyz idx_i^T.
-template <bool WANT_G>
+template <bool WANT_G, int E = VT>
 __device__ __forceinline__ void weight_grad_sum(const float4* __restrict__ tile, const int* lb, const Stencil& S,
                                                 const float* c0, const float* Ad, float mw, float* X, float* G0,
                                                 float* Gi) {
@@ -82,7 +84,7 @@ __device__ __forceinline__ void weight_grad_sum(const float4* __restrict__ tile,
     float p0[3] = {0, 0, 0}, pj[3] = {0, 0, 0}, pk[3] = {0, 0, 0};
 #pragma unroll
     for (int jj = 0; jj < 3; jj++) {
-      const float4* row = tile + ((lb[0] + i) * VT + lb[1] + jj) * VT + lb[2];
+      const float4* row = tile + ((lb[0] + i) * E + lb[1] + jj) * E + lb[2];
       const float4 g[3] = {row[0], row[1], row[2]};
       float m2[3];
 #pragma unroll

@@ -260,8 +260,9 @@ class Simulator:
     def sort_snapshot(self, which: int = 0):
         """Integer outputs of the block sort (mpm_sort_snapshot): which = 0
         sorts the current state and returns (ids, keys, list) as numpy
-        arrays, list rows {key, offset, count}; which = 1 returns the ids of
-        the buffer the last forward call left."""
+        arrays, list rows {key, offset, count}; which = 2 the same with the
+        rows in key order; which = 1 returns the ids of the buffer the last
+        forward call left."""
         L = _lib.lib()
         ids = torch.empty(self.N, dtype=torch.int32, device=self.device)
         self._sync_in()
@@ -273,7 +274,7 @@ class Simulator:
         nk = self.get_option(_lib.MPM_OPT_N_KEYS)
         lst = torch.empty(nk, 4, dtype=torch.int32, device=self.device)
         nl = ctypes.c_int32(0)
-        _lib.check(L.mpm_sort_snapshot(self.ctx, 0, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(keys.data_ptr()),
+        _lib.check(L.mpm_sort_snapshot(self.ctx, which, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(keys.data_ptr()),
                                        ctypes.c_void_p(lst.data_ptr()), ctypes.byref(nl)), "mpm_sort_snapshot", self.ctx)
         return (ids.cpu().numpy().view(np.uint32), keys.cpu().numpy().view(np.uint32),
                 lst[: nl.value, :3].cpu().numpy())

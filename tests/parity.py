@@ -137,3 +137,31 @@ def oracle_rollout_coverage(O, sc, steps):
             cases += np.bincount(c, minlength=3)
         st = new
     return {k: v.detach().numpy() for k, v in st.items()}, cases, band
+
+
+def ill_conditioned_solids(sc, seed, share=0.5):
+    """Give a seeded share of the scene's solid particles an ill-conditioned
+    initial F = R1 diag(a, b, c) R2^T (proper rotations, a in [1.05, 1.25],
+    b / a in [0.5, 0.9], c / a in [0.14, 0.24]), so that the smallest
+    singular value is below a quarter of the largest.  Returns the number of
+    particles changed."""
+    rng = np.random.default_rng(np.random.SeedSequence([20230302, 77, seed]))
+    kinds = np.array([m.kind for m in sc.materials])[sc.mat]
+    F = np.array(sc.F, np.float64).reshape(sc.n, 3, 3).copy()
+    sel = np.flatnonzero((kinds != scenes.LIQUID) & (rng.random(sc.n) < share))
+
+    def rot(k):
+        q = rng.normal(size=(k, 4))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        w, x, y, z = q.T
+        return np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                         2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                         2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], 1).reshape(k, 3, 3)
+
+    a = rng.uniform(1.05, 1.25, sel.size)
+    b = a * rng.uniform(0.5, 0.9, sel.size)
+    c = a * rng.uniform(0.14, 0.24, sel.size)
+    s = np.stack([a, b, c], 1)
+    F[sel] = rot(sel.size) @ (s[:, :, None] * rot(sel.size).transpose(0, 2, 1))
+    sc.F = F.reshape(np.shape(sc.F))
+    return int(sel.size)

@@ -266,6 +266,44 @@ def _ice_cream_scene(steps, n=600, seed=5):
                        kinds=(scenes.VONMISES, scenes.LIQUID), velocity=3.0, dt=1e-4)
 
 
+@pytest.mark.parametrize("adjoint", ["tiled", "plain"])
+def test_gradient_ill_conditioned_solids_vs_oracle(adjoint):
+    """Half of the solids (elastic, sand, von Mises, box-yield; a liquid box
+    carries the loss) start with
+    s2 < s0/4, so that the forward's FP64 redo of the return map and of the
+    stress, and the adjoint's FP64 passes (plastic-return adjoint, stress
+    adjoint), all run; forward state, action gradient and dL/d(x0, v0, F0)
+    against the oracle."""
+    from parity import ill_conditioned_solids
+    sc = scenes.tiny(n_particles=160, n_grid=16, steps=6, seed=5,
+                     kinds=(scenes.ELASTIC, scenes.LIQUID, scenes.SAND, scenes.VONMISES, scenes.BOX))
+    n_ill = ill_conditioned_solids(sc, 0)
+    say(f"ill-conditioned solids: {n_ill} of {sc.n} particles, {adjoint} adjoint")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=4, adjoint=adjoint)
+    sim.step(sc.horizon)
+    compare_states(sim.state_numpy(), oracle_state(sc, sc.horizon), liquid_mask(sc), tol_x=1e-6, tol=1e-4,
+                   tol_FJ=1e-5, n_grid=sc.n_grid)
+    loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
+    ga, g0 = sim.backward(g[0:3], torch.zeros_like(g[0:3]), want_grad0=True)
+    ga = ga[:, 0].double().cpu().numpy()
+    p = O.params_from_scene(sc)
+    st0 = O.state_from_scene(sc, requires_grad=True)
+    acts = torch.tensor(sc.actions, dtype=torch.float64, requires_grad=True)
+    st = O.rollout(sc, state=st0, params=p, actions=acts)
+    L = O.blob_loss(st["x"], p.kind == O.LIQUID, torch.tensor(sc.target_mu, dtype=torch.float64), sc.target_sigma)
+    L.backward()
+    ea = rel(ga, acts.grad.numpy())
+    ex = rel(g0[0:3].T.double().cpu().numpy(), st0["x"].grad.numpy())
+    ev = rel(g0[3:6].T.double().cpu().numpy(), st0["v"].grad.numpy())
+    solid = ~liquid_mask(sc)
+    gF = g0[15:24].T.double().cpu().numpy().reshape(-1, 3, 3)[solid]
+    eF = rel(gF, st0["F"].grad.numpy()[solid])
+    say(f"  loss gpu {loss.item():.8f} ref {L.item():.8f}; actions {ea:.2e} dL/dx0 {ex:.2e} dL/dv0 {ev:.2e} "
+        f"dL/dF0 {eF:.2e}")
+    assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
+    assert ea <= 1e-4 and ex <= 1e-4 and ev <= 1e-4 and eF <= 1e-4
+
+
 def test_von_mises_forward_vs_oracle():
     """The ice cream yields under a random velocity field (most particles
     return to the yield surface); 20 steps against the oracle."""

@@ -39,8 +39,10 @@ def block_keys(x, n_grid, scene):
     return ((np.asarray(scene, np.uint64) << np.uint64(3 * kb)) | m).astype(np.uint64)
 
 
-def check_sort(sim, x, n_grid, scene):
-    ids, keys, lst = sim.sort_snapshot(0)
+def check_sort(sim, x, n_grid, scene, which=0):
+    """which = 2: the sort of the adjoint's recompute, whose block list must
+    also be in increasing key order (the scan over all keys)."""
+    ids, keys, lst = sim.sort_snapshot(which)
     N = x.shape[0]
     # every particle exactly once
     assert np.array_equal(np.sort(ids.astype(np.int64)), np.arange(N))
@@ -52,6 +54,8 @@ def check_sort(sim, x, n_grid, scene):
     order = np.argsort(lo)
     assert lo[order][0] == 0 and np.array_equal(lo[order][1:], (lo + cnt)[order][:-1]) and (lo + cnt).max() == N
     assert (cnt > 0).all() and len(np.unique(lk)) == len(lk)
+    if which == 2:
+        assert (np.diff(lk) > 0).all()
     for k, o, c in zip(lk, lo, cnt):
         assert (keys[o:o + c] == k).all()
     # counts equal the histogram of the keys
@@ -67,6 +71,8 @@ def test_sort_config2_bit_exact():
     sim = Simulator(sc)
     nl = check_sort(sim, sc.x, sc.n_grid, np.zeros(sc.n, np.int64))
     say(f"  config 2: {sc.n} particles in {nl} blocks, ids, keys, segments and counts exact")
+    check_sort(sim, sc.x, sc.n_grid, np.zeros(sc.n, np.int64), which=2)
+    say("  the same with the blocks in key order")
     # the buffer left by fused steps (sorted by the fused kernel's own key
     # counting and scans) still holds every particle once
     sim.step(20)
@@ -85,6 +91,8 @@ def test_sort_config4_full_bit_exact():
     scene = np.concatenate([np.full(sc.n, s) for s, sc in enumerate(scs)])
     nl = check_sort(sim, x, scs[0].n_grid, scene)
     say(f"  config 4: {x.shape[0]} particles of {len(scs)} scenes in {nl} blocks, exact")
+    check_sort(sim, x, scs[0].n_grid, scene, which=2)
+    say("  the same with the blocks in key order")
     sim.step(4)
     ids = sim.sort_snapshot(1)
     assert np.array_equal(np.sort(ids.astype(np.int64)), np.arange(x.shape[0]))
