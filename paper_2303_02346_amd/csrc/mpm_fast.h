@@ -23,6 +23,10 @@ constexpr int TILE = 10;                     // P2G tile edge (nodes): block +-2
 constexpr int TILE_NODES = TILE * TILE * TILE;
 constexpr int VT = 8;                        // G2P velocity tile edge
 constexpr int VT_NODES = VT * VT * VT;
+// Tile slots per block key: the forward lists a block of more than two
+// chunks twice, and the second workgroup publishes its tile in slot
+// key + n_keys (the adjoint uses slot key only).
+constexpr int NSUB = 2;
 
 // Particle buffer: packed state (25 rows of N floats) plus bookkeeping.
 struct PBuf {
@@ -60,13 +64,13 @@ struct FastPath {
   uint32_t* cpad;          // the import's key counters, 64 bytes apart
   uint32_t *counts, *offsets;
   uint32_t *touched, *n_touched;   // keys counted in the current step, in first-touch order
-  int4* list[3];           // occupied-block lists (rotating)
+  int4* list[3];           // occupied-block lists (rotating; up to NSUB entries per key)
   uint32_t* list_n;        // [3]
   uint32_t* claim;         // per-block stamp: which step last updated the block
   uint32_t* cl_list;       // keys of the blocks claimed in the current step
   uint32_t* cl_count;      // [2]: claims of odd and even step ids
-  int2* tile_box;          // {packed lo/hi, stamp}
-  float* tiles;            // n_keys x 4 x TILE_NODES
+  int2* tile_box;          // {packed lo/hi, stamp} per tile slot
+  float* tiles;            // NSUB n_keys slots x 4 x TILE_NODES
   float4* vgrid;           // n_keys x 64
   uint32_t* gen;           // device per-call epoch of the step stamps
   int* t0_dev;             // device clock at the start of the call

@@ -72,49 +72,64 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
 }
 
 // Exclusive scan of the counts of the touched keys -> their offsets, the
-// list of occupied keys {key, offset, count}, and the counts and the touched
-// counter cleared.  Run by one workgroup of NT threads.  The blocks follow the
-// order in which their keys were first touched; only contiguity matters.
+// list of occupied keys {key, offset, count, sub}, and the counts and the
+// touched counter cleared.  Run by one workgroup of NT threads.  The blocks
+// follow the order in which their keys were first touched; only contiguity
+// matters.  With split_nt > 0 a block of more than two chunks of split_nt
+// particles is listed twice, sub 0 with the first ceil(chunks / 2) chunks
+// and sub 1 with the rest, so that two workgroups share it (each publishes
+// its own tile slot).
 template <int NT>
 __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
                              const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
-                             int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys, int stride = 1) {
+                             int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys, int stride = 1,
+                             int split_nt = 0) {
   constexpr int NW = NT / 64;
-  __shared__ uint32_t s_sum[NW];
-  __shared__ uint32_t s_run;
+  __shared__ uint32_t s_sum[NW], s_sp[NW];
+  __shared__ uint32_t s_run, s_runsp;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const uint32_t n = min(n_touched[0], (uint32_t)n_keys);
-  if (t == 0) s_run = 0;
+  if (t == 0) { s_run = 0; s_runsp = 0; }
   __syncthreads();
   for (uint32_t c0 = 0; c0 < n; c0 += NT) {
     const uint32_t i = c0 + t;
     uint32_t key = 0, c = 0;
     if (i < n) { key = touched[i]; c = counts[(size_t)key * stride]; }
-    uint32_t is = c;
+    const uint32_t nch = split_nt > 0 ? (c + (uint32_t)split_nt - 1) / (uint32_t)split_nt : 0u;
+    const uint32_t sp = nch > 2 ? 1u : 0u;
+    uint32_t is = c, isp = sp;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t o = __shfl_up(is, off);
-      if (lane >= off) is += o;
+      const uint32_t o = __shfl_up(is, off), o2 = __shfl_up(isp, off);
+      if (lane >= off) { is += o; isp += o2; }
     }
-    if (lane == 63) s_sum[wv] = is;
+    if (lane == 63) { s_sum[wv] = is; s_sp[wv] = isp; }
     __syncthreads();
-    uint32_t woff = s_run, tot = s_run;
+    uint32_t woff = s_run, tot = s_run, wsp = s_runsp, totsp = s_runsp;
 #pragma unroll
     for (int q = 0; q < NW; q++) {
-      if (q < wv) woff += s_sum[q];
+      if (q < wv) { woff += s_sum[q]; wsp += s_sp[q]; }
       tot += s_sum[q];
+      totsp += s_sp[q];
     }
     if (i < n) {
       const uint32_t o = woff + is - c;
+      const uint32_t li = i + wsp + isp - sp;
       offsets[key] = o;
       counts[(size_t)key * stride] = 0u;
-      list[i] = make_int4((int)key, (int)o, (int)c, 0);
+      if (sp) {
+        const uint32_t c1 = ((nch + 1) / 2) * (uint32_t)split_nt;
+        list[li] = make_int4((int)key, (int)o, (int)c1, 0);
+        list[li + 1] = make_int4((int)key, (int)(o + c1), (int)(c - c1), 1);
+      } else {
+        list[li] = make_int4((int)key, (int)o, (int)c, 0);
+      }
     }
     __syncthreads();
-    if (t == 0) s_run = tot;
+    if (t == 0) { s_run = tot; s_runsp = totsp; }
     __syncthreads();
   }
-  if (t == 0) { list_n[0] = n; n_touched[0] = 0u; }
+  if (t == 0) { list_n[0] = n + s_runsp; n_touched[0] = 0u; }
 }
 
 // Dense variant: exclusive scan of all counts -> offsets, the list of
@@ -222,13 +237,13 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, ui
                                                const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
                                                uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count,
-                                               int mode, int stride) {
+                                               int mode, int stride, int split_nt) {
   constexpr int NT = 1024;
   if (mode == SCAN_DENSE) {
     scan_keys<NT>(counts, offsets, list, list_n, n_keys, stride);
     if (threadIdx.x == 0) n_touched[0] = 0u;
   } else {
-    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride);
+    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride, split_nt);
   }
   if (threadIdx.x == 0) { epoch[0] = epoch[0] + 1; cl_count[0] = 0u; cl_count[1] = 0u; }
 }
@@ -796,10 +811,11 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
       const int lo0 = blo[0], lo1 = blo[1], lo2 = blo[2];
       const int hi0 = bhi[0] + 2, hi1 = bhi[1] + 2, hi2 = bhi[2] + 2;
       const uint32_t bkey = (uint32_t)ent.x;
+      const size_t slot = (size_t)bkey + (size_t)ent.w * (size_t)A.n_keys;   // the entry's tile slot
       if (lo0 <= hi0 - 2) {
         const int ex = hi0 - lo0 + 1, ey = hi1 - lo1 + 1, ez = hi2 - lo2 + 1;
         const int cnt = ex * ey * ez;
-        float* T = A.tiles + (size_t)bkey * 4 * TILE_NODES;
+        float* T = A.tiles + slot * 4 * TILE_NODES;
         for (int r = tid; r < cnt; r += NT) {
           int qi = lo0 + r / (ey * ez), qj = lo1 + (r / ez) % ey, qk = lo2 + r % ez;
           int q = (qi * TILE + qj) * TILE + qk;
@@ -808,7 +824,7 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
         }
         if (tid == 0) {
           int packed = lo0 | (lo1 << 4) | (lo2 << 8) | (hi0 << 12) | (hi1 << 16) | (hi2 << 20);
-          A.tile_box[bkey] = make_int2(packed, (int)stamp);
+          A.tile_box[slot] = make_int2(packed, (int)stamp);
         }
         // claim the blocks this tile touches: the first entry to claim a block
         // in this step appends it to the list the grid kernel works through
@@ -857,6 +873,7 @@ struct ScanArgs {
   int4* list;
   uint32_t* list_n;
   int n_keys;
+  int split_nt;   // particles per chunk of the particle kernel that reads the list
 };
 
 // With do_scan, workgroup 0 scans the key counts of this step's particle
@@ -869,7 +886,7 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
                                               const float* __restrict__ act_base, const int* __restrict__ t0_dev,
                                               int do_scan, ScanArgs SA, int t_fixed, float4* __restrict__ mmv_out) {
   if (do_scan && blockIdx.x == 0) {
-    scan_touched<256>(SA.counts, SA.offsets, SA.touched, SA.n_touched, SA.list, SA.list_n, SA.n_keys);
+    scan_touched<256>(SA.counts, SA.offsets, SA.touched, SA.n_touched, SA.list, SA.list_n, SA.n_keys, 1, SA.split_nt);
     return;
   }
   const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
@@ -892,12 +909,15 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
     int sc, cx, cy, cz;
     key_decode(g, key, sc, cx, cy, cz);
     {
+      // lanes 0..26 read the boxes of the 27 neighbours' tiles, lanes 32..58
+      // those of their second slots (blocks shared by two workgroups)
       int2 nbox = make_int2(0, 0);
       uint32_t nkey = 0;
-      if (lane < 27) {
-        const int sx = cx + lane / 9 - 1, sy = cy + (lane / 3) % 3 - 1, sz = cz + lane % 3 - 1;
+      const int dl = lane < 32 ? lane : lane - 32;
+      if (dl < 27) {
+        const int sx = cx + dl / 9 - 1, sy = cy + (dl / 3) % 3 - 1, sz = cz + dl % 3 - 1;
         if (sx >= 0 && sy >= 0 && sz >= 0 && sx < g.nb && sy < g.nb && sz < g.nb) {
-          nkey = block_key(g, sc, sx, sy, sz);
+          nkey = block_key(g, sc, sx, sy, sz) + (lane < 32 ? 0u : (uint32_t)g.n_keys);
           nbox = tile_box[nkey];
           if ((uint32_t)nbox.y != stamp) nbox.y = 0;
         }
@@ -923,6 +943,26 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
         acc.x += in ? t1 : 0.f;
         acc.y += in ? t2 : 0.f;
         acc.z += in ? t3 : 0.f;
+      }
+      // the few valid second slots, one at a time
+      unsigned long long m1 = __ballot(lane >= 32 && nbox.y != 0);
+      while (m1) {
+        const int src = __ffsll((long long)m1) - 1;
+        m1 &= m1 - 1ull;
+        const int dd = src - 32;
+        const int bxv = __shfl(nbox.x, src);
+        const uint32_t kk = __shfl(nkey, src);
+        const int sx = cx + dd / 9 - 1, sy = cy + (dd / 3) % 3 - 1, sz = cz + dd % 3 - 1;
+        const int qi = gx - (4 * sx - 2), qj = gy - (4 * sy - 2), qk = gz - (4 * sz - 2);
+        const int lo0 = bxv & 15, lo1 = (bxv >> 4) & 15, lo2 = (bxv >> 8) & 15;
+        const int hi0 = (bxv >> 12) & 15, hi1 = (bxv >> 16) & 15, hi2 = (bxv >> 20) & 15;
+        if (qi >= lo0 && qi <= hi0 && qj >= lo1 && qj <= hi1 && qk >= lo2 && qk <= hi2) {
+          const float* T = tiles + (size_t)kk * 4 * TILE_NODES + (qi * TILE + qj) * TILE + qk;
+          acc.w += T[0];
+          acc.x += T[TILE_NODES];
+          acc.y += T[2 * TILE_NODES];
+          acc.z += T[3 * TILE_NODES];
+        }
       }
       float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
       if (acc.w > 0.f && gx < g.n && gy < g.n && gz < g.n) {
@@ -963,7 +1003,7 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   FastLayout L;
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o += a256(b); return r; };
-  for (int b = 0; b < 3; b++) L.list[b] = take((size_t)g.n_keys * 16);
+  for (int b = 0; b < 3; b++) L.list[b] = take((size_t)g.n_keys * NSUB * 16);
   for (int b = 0; b < 2; b++) {
     L.buf_f[b] = take((size_t)STATE_FLOATS * N * 4);
     L.buf_id[b] = take((size_t)N * 4);
@@ -983,8 +1023,8 @@ static FastLayout fast_plan(int n_grid, int S, int N) {
   L.cl_count = take(16);
   L.touched = take((size_t)g.n_keys * 4);
   L.n_touched = take(16);
-  L.tile_box = take((size_t)g.n_keys * 8);
-  L.tiles = take((size_t)g.n_keys * 4 * TILE_NODES * 4);
+  L.tile_box = take((size_t)g.n_keys * NSUB * 8);
+  L.tiles = take((size_t)g.n_keys * NSUB * 4 * TILE_NODES * 4);
   L.vgrid = take((size_t)g.n_keys * 64 * 16);
   L.gen = take(16);
   L.t0 = take(16);
@@ -1065,7 +1105,7 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   launch_zero(ws + L.claim, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.cl_count, 256, s);
   launch_zero(ws + L.n_touched, 256, s);
-  launch_zero(ws + L.tile_box, a256((size_t)f.g.n_keys * 8), s);
+  launch_zero(ws + L.tile_box, a256((size_t)f.g.n_keys * NSUB * 8), s);
   launch_zero(ws + L.vgrid, a256((size_t)f.g.n_keys * 64 * 16), s);
   launch_zero(ws + L.gen, 256, s);
   return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -1080,7 +1120,7 @@ __global__ void k_set_word(int* w, int v) { w[0] = v; }
 static void new_epoch(FastPath& f, hipStream_t s) {
   if ((++f.calls & 0xffff) == 0) {
     launch_zero(f.claim, (size_t)f.g.n_keys * 4, s);
-    launch_zero(f.tile_box, (size_t)f.g.n_keys * 8, s);
+    launch_zero(f.tile_box, (size_t)f.g.n_keys * NSUB * 8, s);
   }
   f.sid = 0;
 }
@@ -1094,7 +1134,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   const int N = f.N;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
-                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD);
+                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD, NT);
   import_permute(f, user, P.mat, f.buf[0], s);
   PartArgs A;
   A.N = N;
@@ -1162,6 +1202,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     SA.list = f.list[nwr];
     SA.list_n = f.list_n + nwr;
     SA.n_keys = g.n_keys;
+    SA.split_nt = NT;
     k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.cl_list, f.cl_count + ((step + 1) & 1),
                                                f.cl_count + ((step + 2) & 1), f.tile_box, f.tiles, f.gen,
                                                (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA, -1, nullptr);
@@ -1246,7 +1287,7 @@ void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, Sorted
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
                             out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE,
-                            IMPORT_PAD);
+                            IMPORT_PAD, 0);
   import_permute(f, user, P.mat, out.b, s);
 }
 
@@ -1257,7 +1298,7 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
   k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
                                            touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1, 0);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 
