@@ -130,6 +130,19 @@ def bench_batched(torch, steps=100):
     sim.step(steps)
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
+    # the same launch with every block in a single workgroup (no block
+    # shared by two), against the tuned choice
+    from paper_2303_02346_amd import _lib
+    sim.set_option(_lib.MPM_OPT_SHARE_CHUNKS, 0)
+    sim.reset()
+    sim.step(steps)
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t_u = time.perf_counter() - t0
+    sim.set_option(_lib.MPM_OPT_SHARE_CHUNKS, tune["share_chunks"])
     # the same steps eager, with the fused kernel's launches event-timed
     sim.reset()
     sim.timing(True)
@@ -160,9 +173,10 @@ def bench_batched(torch, steps=100):
                 "traffic": counted_traffic(BATCHED_TRAFFIC_SUMMARY)}
     out = {"scenes": len(scs), "particles": n_tot, "steps": steps, "launch": tune,
            "batched_rate": n_tot * steps / t_b, "sequential_rate": n_tot * steps / t_s,
+           "unshared_blocks_rate": n_tot * steps / t_u,
            "speedup": t_s / t_b, "unit": "particle-steps/s", "roofline": roof}
-    log(f"[bench] batched {out['batched_rate']:.3e} vs sequential {out['sequential_rate']:.3e} particle-steps/s "
-        f"(x{out['speedup']:.2f}); fused kernel {roof['avg_us'] if roof else None} us, "
+    log(f"[bench] batched {out['batched_rate']:.3e} (no shared blocks {out['unshared_blocks_rate']:.3e}) vs "
+        f"sequential {out['sequential_rate']:.3e} particle-steps/s (x{out['speedup']:.2f}); fused kernel {roof['avg_us'] if roof else None} us, "
         f"{roof['frac'] if roof else None} of HBM peak")
     return out
 

@@ -229,7 +229,9 @@ enum {
   MPM_OPT_PART_WGS = 3,       /* particle workgroups per launch (persistent, 64..65536) */
   MPM_OPT_GRID_WGS = 4,       /* grid-update workgroups per launch (64..65536) */
   MPM_OPT_ADJOINT = 5,        /* 0: tiled (default), 1: plain */
-  MPM_OPT_N_KEYS = 6          /* read only: grid blocks of the context (rows of a sort snapshot list) */
+  MPM_OPT_N_KEYS = 6,         /* read only: grid blocks of the context (rows of a sort snapshot list) */
+  MPM_OPT_SHARE_CHUNKS = 7    /* a block holding more than this many chunks (of MPM_OPT_PART_THREADS
+                                 particles) is shared by two particle workgroups; 0 = never; default 2 */
 };
 int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value);
 int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value);
@@ -254,9 +256,10 @@ int mpm_sort_snapshot(mpm_ctx* c, int32_t which, uint32_t* id_dev, uint32_t* key
 
 /* Autotuner: times n_steps of the forward path from the current state (the
  * state and the clock are left unchanged; actions t..t+n_steps-1 must be
- * set) for every launch shape in a fixed candidate set, keeps the fastest
- * and returns it in best[4] = {part_threads, part_wgs, grid_wgs,
- * microseconds per step}. */
+ * set) for every launch shape in a fixed candidate set (particles per
+ * chunk, workgroup counts, and the chunk count above which a block is
+ * shared by two workgroups), keeps the fastest and returns it in best[5] =
+ * {part_threads, part_wgs, grid_wgs, microseconds per step, share_chunks}. */
 int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best);
 
 /* ---- learned closure of the Drucker-Prager cone return (sand) ----------

@@ -57,6 +57,7 @@ GAS_EXPORTS = ["gas_workspace_bytes", "gas_create", "gas_set_state", "gas_set_ac
                "gas_timing_read", "gas_last_error_bits", "gas_clock", "gas_destroy"]
 
 MPM_OPT_GRAPH, MPM_OPT_PART_THREADS, MPM_OPT_PART_WGS, MPM_OPT_GRID_WGS, MPM_OPT_ADJOINT, MPM_OPT_N_KEYS = 1, 2, 3, 4, 5, 6
+MPM_OPT_SHARE_CHUNKS = 7
 
 _lib = None
 

@@ -687,6 +687,10 @@ int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return MPM_EINVAL;
       c->plain_adjoint = value == 1;
       return MPM_OK;
+    case MPM_OPT_SHARE_CHUNKS:
+      if (value < 0 || value > 64) return MPM_EINVAL;
+      c->fast.share_chunks = value;
+      return MPM_OK;
     default: return MPM_EINVAL;
   }
 }
@@ -698,6 +702,7 @@ int mpm_get_option(const mpm_ctx* c, int32_t key, int32_t* value) {
     case MPM_OPT_PART_THREADS: *value = c->fast.part_threads; return MPM_OK;
     case MPM_OPT_PART_WGS: *value = c->fast.part_wgs; return MPM_OK;
     case MPM_OPT_GRID_WGS: *value = c->fast.grid_wgs; return MPM_OK;
+    case MPM_OPT_SHARE_CHUNKS: *value = c->fast.share_chunks; return MPM_OK;
     case MPM_OPT_ADJOINT: *value = c->plain_adjoint ? 1 : 0; return MPM_OK;
     case MPM_OPT_N_KEYS: *value = c->fast.g.n_keys; return MPM_OK;
     default: return MPM_EINVAL;
@@ -732,45 +737,57 @@ int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best) {
   const int pts[3] = {128, 256, 512};
   const int pws[4] = {512, 1024, 2048, 4096};
   const int gws[3] = {512, 1024, 2048};
+  const int shs[3] = {2, 1, 0};   // chunks above which a block is shared by two workgroups
   const int save_pt = c->fast.part_threads, save_pw = c->fast.part_wgs, save_gw = c->fast.grid_wgs;
+  const int save_sh = c->fast.share_chunks;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPM_EHIP;
   float best_ms = 1e30f;
-  int bpt = save_pt, bpw = save_pw, bgw = save_gw;
+  int bpt = save_pt, bpw = save_pw, bgw = save_gw, bsh = save_sh;
   c->fast.do_export = false;     // the trial runs leave the user state untouched
   int rc = MPM_OK;
   for (int a = 0; a < 3 && rc == MPM_OK; a++)
     for (int b = 0; b < 4 && rc == MPM_OK; b++)
-      for (int d = 0; d < 3 && rc == MPM_OK; d++) {
-        c->fast.part_threads = pts[a];
-        c->fast.part_wgs = pws[b];
-        c->fast.grid_wgs = gws[d];
-        float ms_min = 1e30f;
-        for (int rep = 0; rep < 3; rep++) {
-          hipEventRecord(e0, s);
-          if (fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), s, nullptr) != 0) { rc = MPM_EHIP; break; }
-          hipEventRecord(e1, s);
-          if (hipEventSynchronize(e1) != hipSuccess) { rc = MPM_EHIP; break; }
-          float ms = 0.f;
-          hipEventElapsedTime(&ms, e0, e1);
-          if (rep > 0 && ms < ms_min) ms_min = ms;   // first run warms up (and captures)
+      for (int d = 0; d < 3 && rc == MPM_OK; d++)
+        for (int h = 0; h < 3 && rc == MPM_OK; h++) {
+          c->fast.part_threads = pts[a];
+          c->fast.part_wgs = pws[b];
+          c->fast.grid_wgs = gws[d];
+          c->fast.share_chunks = shs[h];
+          float ms_min = 1e30f;
+          for (int rep = 0; rep < 3; rep++) {
+            hipEventRecord(e0, s);
+            if (fast_run(c->fast, P, us, c->t, n_steps, pose_at(c, 0), act_at(c, 0), s, nullptr) != 0) {
+              rc = MPM_EHIP;
+              break;
+            }
+            hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = MPM_EHIP; break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0 && ms < ms_min) ms_min = ms;   // first run warms up (and captures)
+          }
+          if (rc == MPM_OK && ms_min < best_ms) {
+            best_ms = ms_min; bpt = pts[a]; bpw = pws[b]; bgw = gws[d]; bsh = shs[h];
+          }
         }
-        if (rc == MPM_OK && ms_min < best_ms) { best_ms = ms_min; bpt = pts[a]; bpw = pws[b]; bgw = gws[d]; }
-      }
   c->fast.do_export = true;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc != MPM_OK) {
     c->fast.part_threads = save_pt; c->fast.part_wgs = save_pw; c->fast.grid_wgs = save_gw;
+    c->fast.share_chunks = save_sh;
     return rc;
   }
   c->fast.part_threads = bpt;
   c->fast.part_wgs = bpw;
   c->fast.grid_wgs = bgw;
+  c->fast.share_chunks = bsh;
   best[0] = bpt;
   best[1] = bpw;
   best[2] = bgw;
   best[3] = (int32_t)(best_ms * 1000.f / n_steps);
+  best[4] = bsh;
   int frc = finish(c);
   return frc == MPM_OK ? MPM_OK : frc;
 }

@@ -41,7 +41,7 @@ struct PBuf {
 struct FastGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int n = 0, part_threads = 0, part_wgs = 0, grid_wgs = 0;
+  int n = 0, part_threads = 0, part_wgs = 0, grid_wgs = 0, share_chunks = 0;
   bool timed = false, do_export = true;
   // every user pointer and logging argument the captured launches bake in
   const float *x = nullptr, *v = nullptr, *C = nullptr, *F = nullptr, *J = nullptr;
@@ -76,7 +76,8 @@ struct FastPath {
   int* t0_dev;             // device clock at the start of the call
   unsigned long long calls;
   // launch shape and mode (set by mpm_set_option / the autotuner)
-  int part_threads;        // 128 or 256 threads per particle workgroup
+  int part_threads;        // 128, 256 or 512 threads (particles per chunk) per particle workgroup
+  int share_chunks;        // a block of more chunks than this is shared by two workgroups (0: never)
   bool use_graph;          // capture each call shape once and replay it
   bool do_export;          // write the result back to the user arrays
   std::vector<FastGraph> graphs;

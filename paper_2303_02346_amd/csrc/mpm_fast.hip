@@ -75,15 +75,15 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
 // list of occupied keys {key, offset, count, sub}, and the counts and the
 // touched counter cleared.  Run by one workgroup of NT threads.  The blocks
 // follow the order in which their keys were first touched; only contiguity
-// matters.  With split_nt > 0 a block of more than two chunks of split_nt
-// particles is listed twice, sub 0 with the first ceil(chunks / 2) chunks
-// and sub 1 with the rest, so that two workgroups share it (each publishes
-// its own tile slot).
+// matters.  With split_nt > 0 a block of more than max_chunks chunks of
+// split_nt particles is listed twice, sub 0 with the first ceil(chunks / 2)
+// chunks and sub 1 with the rest, so that two workgroups share it (each
+// publishes its own tile slot).
 template <int NT>
 __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
                              const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                              int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys, int stride = 1,
-                             int split_nt = 0) {
+                             int split_nt = 0, int max_chunks = 2) {
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_sum[NW], s_sp[NW];
   __shared__ uint32_t s_run, s_runsp;
@@ -96,7 +96,7 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
     uint32_t key = 0, c = 0;
     if (i < n) { key = touched[i]; c = counts[(size_t)key * stride]; }
     const uint32_t nch = split_nt > 0 ? (c + (uint32_t)split_nt - 1) / (uint32_t)split_nt : 0u;
-    const uint32_t sp = nch > 2 ? 1u : 0u;
+    const uint32_t sp = nch > (uint32_t)max_chunks ? 1u : 0u;
     uint32_t is = c, isp = sp;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -237,13 +237,13 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, ui
                                                const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
                                                uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count,
-                                               int mode, int stride, int split_nt) {
+                                               int mode, int stride, int split_nt, int max_chunks) {
   constexpr int NT = 1024;
   if (mode == SCAN_DENSE) {
     scan_keys<NT>(counts, offsets, list, list_n, n_keys, stride);
     if (threadIdx.x == 0) n_touched[0] = 0u;
   } else {
-    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride, split_nt);
+    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride, split_nt, max_chunks);
   }
   if (threadIdx.x == 0) { epoch[0] = epoch[0] + 1; cl_count[0] = 0u; cl_count[1] = 0u; }
 }
@@ -873,7 +873,8 @@ struct ScanArgs {
   int4* list;
   uint32_t* list_n;
   int n_keys;
-  int split_nt;   // particles per chunk of the particle kernel that reads the list
+  int split_nt;     // particles per chunk of the particle kernel that reads the list (0: no sharing)
+  int max_chunks;   // chunks above which a block is shared by two workgroups
 };
 
 // With do_scan, workgroup 0 scans the key counts of this step's particle
@@ -886,7 +887,8 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
                                               const float* __restrict__ act_base, const int* __restrict__ t0_dev,
                                               int do_scan, ScanArgs SA, int t_fixed, float4* __restrict__ mmv_out) {
   if (do_scan && blockIdx.x == 0) {
-    scan_touched<256>(SA.counts, SA.offsets, SA.touched, SA.n_touched, SA.list, SA.list_n, SA.n_keys, 1, SA.split_nt);
+    scan_touched<256>(SA.counts, SA.offsets, SA.touched, SA.n_touched, SA.list, SA.list_n, SA.n_keys, 1, SA.split_nt,
+                      SA.max_chunks);
     return;
   }
   const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
@@ -1081,6 +1083,7 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.gen = (uint32_t*)(ws + L.gen);
   f.t0_dev = (int*)(ws + L.t0);
   f.part_threads = 256;
+  f.share_chunks = 2;
   f.use_graph = false;
   f.do_export = true;
   f.mlp_blob = nullptr;
@@ -1134,7 +1137,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   const int N = f.N;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
-                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD, NT);
+                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD, f.share_chunks > 0 ? NT : 0, f.share_chunks);
   import_permute(f, user, P.mat, f.buf[0], s);
   PartArgs A;
   A.N = N;
@@ -1202,7 +1205,8 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     SA.list = f.list[nwr];
     SA.list_n = f.list_n + nwr;
     SA.n_keys = g.n_keys;
-    SA.split_nt = NT;
+    SA.split_nt = f.share_chunks > 0 ? NT : 0;
+    SA.max_chunks = f.share_chunks;
     k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.cl_list, f.cl_count + ((step + 1) & 1),
                                                f.cl_count + ((step + 2) & 1), f.tile_box, f.tiles, f.gen,
                                                (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA, -1, nullptr);
@@ -1257,13 +1261,14 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   for (auto& c : f.graphs)
     if (c.exec && c.n == n && c.x == user.x && c.v == user.v && c.C == user.C && c.F == user.F && c.J == user.J &&
         c.mat == P.mat && c.part_threads == f.part_threads && c.part_wgs == f.part_wgs && c.grid_wgs == f.grid_wgs &&
+        c.share_chunks == f.share_chunks &&
         c.timed == timed && c.do_export == f.do_export && c.mlp == f.mlp_blob && c.log == f.log_buf &&
         c.log_count == f.log_count && c.log_cap == f.log_cap && c.tol == f.closure_tol)
       G = &c;
   if (!G) {
     FastGraph c;
     c.n = n; c.x = user.x; c.v = user.v; c.C = user.C; c.F = user.F; c.J = user.J; c.mat = P.mat;
-    c.part_threads = f.part_threads; c.part_wgs = f.part_wgs;
+    c.part_threads = f.part_threads; c.part_wgs = f.part_wgs; c.share_chunks = f.share_chunks;
     c.grid_wgs = f.grid_wgs; c.timed = timed; c.do_export = f.do_export;
     c.mlp = f.mlp_blob; c.log = f.log_buf; c.log_count = f.log_count; c.log_cap = f.log_cap; c.tol = f.closure_tol;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -3;
@@ -1287,7 +1292,7 @@ void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, Sorted
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
                             out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE,
-                            IMPORT_PAD, 0);
+                            IMPORT_PAD, 0, 0);
   import_permute(f, user, P.mat, out.b, s);
 }
 
@@ -1298,7 +1303,7 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
   k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
                                            touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1, 0);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1, 0, 0);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 

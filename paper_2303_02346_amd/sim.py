@@ -132,11 +132,13 @@ class Simulator:
             self.set_option(_lib.MPM_OPT_PART_THREADS, best["part_threads"])
             self.set_option(_lib.MPM_OPT_PART_WGS, best["part_wgs"])
             self.set_option(_lib.MPM_OPT_GRID_WGS, best["grid_wgs"])
+            self.set_option(_lib.MPM_OPT_SHARE_CHUNKS, best.get("share_chunks", 2))
             return best
         self._sync_in()
-        out = (ctypes.c_int32 * 4)()
+        out = (ctypes.c_int32 * 5)()
         _lib.check(_lib.lib().mpm_autotune(self.ctx, int(n_steps), out), "mpm_autotune", self.ctx)
-        best = {"part_threads": out[0], "part_wgs": out[1], "grid_wgs": out[2], "us_per_step": out[3]}
+        best = {"part_threads": out[0], "part_wgs": out[1], "grid_wgs": out[2], "us_per_step": out[3],
+                "share_chunks": out[4]}
         if cache:
             table[key] = best
             d = os.path.dirname(os.path.abspath(cache))

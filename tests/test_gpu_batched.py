@@ -119,7 +119,9 @@ def test_autotuner_keeps_state_and_picks_a_valid_shape(tmp_path):
     assert torch.equal(before, sim.buf)
     assert sim.clock() == 0
     assert best["part_threads"] in (128, 256, 512) and best["part_wgs"] >= 64 and best["grid_wgs"] >= 64
+    assert best["share_chunks"] in (0, 1, 2)
     assert sim.get_option(_lib.MPM_OPT_PART_WGS) == best["part_wgs"]
+    assert sim.get_option(_lib.MPM_OPT_SHARE_CHUNKS) == best["share_chunks"]
     again = sim.autotune(n_steps=10, cache=str(tmp_path / "tune.json"))
     assert again == best
     sim.step(40)

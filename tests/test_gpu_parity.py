@@ -375,16 +375,21 @@ def test_box_yield_gradient_vs_oracle(adjoint):
 # ---------------------------------------------------------------------------
 # launch shapes, extreme sizes and degenerate inputs
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("threads,part_wgs,grid_wgs", [(128, 512, 512), (256, 4096, 2048), (512, 1024, 1024)])
-def test_config2_launch_shapes_vs_oracle(threads, part_wgs, grid_wgs):
+@pytest.mark.parametrize("threads,part_wgs,grid_wgs,share", [(128, 512, 512, 1), (256, 4096, 2048, 2),
+                                                              (256, 1024, 1024, 0), (256, 2048, 512, 1),
+                                                              (512, 1024, 1024, 1)])
+def test_config2_launch_shapes_vs_oracle(threads, part_wgs, grid_wgs, share):
     """Every launch shape the autotuner can pick gives the oracle's answer
-    (config 2 at full size, 3 steps)."""
+    (config 2 at full size, 3 steps), with blocks of more than `share`
+    chunks shared by two workgroups (0: never)."""
     sc = scenes.config2()
-    say(f"config 2, launch shape {threads} threads, {part_wgs} particle / {grid_wgs} grid workgroups")
+    say(f"config 2, launch shape {threads} threads, {part_wgs} particle / {grid_wgs} grid workgroups, "
+        f"share above {share} chunks")
     sim = sim_of(sc)
     sim.set_option(_lib.MPM_OPT_PART_THREADS, threads)
     sim.set_option(_lib.MPM_OPT_PART_WGS, part_wgs)
     sim.set_option(_lib.MPM_OPT_GRID_WGS, grid_wgs)
+    sim.set_option(_lib.MPM_OPT_SHARE_CHUNKS, share)
     sim.step(3)
     compare_states(sim.state_numpy(), oracle_state(sc, 3), liquid_mask(sc), tol_x=1e-6, tol=1e-3)
 
