@@ -391,9 +391,14 @@ enum { FEAT_NONE = 0, FEAT_LOG = 1, FEAT_CLOSURE = 2 };
 // and 81.7 us at four.  In 512-thread workgroups the same bound made the
 // 1e5-particle 64^3 step slower (66 against 62 us), so they keep two.  The
 // separate P2G (MODE 0, 190 VGPRs unbounded) gains from the same bound too:
-// the rigid-body step at config-2 size 0.126 -> 0.121 ms.
+// the rigid-body step at config-2 size 0.126 -> 0.121 ms.  The learned-
+// closure variant (FP64 return, network on the matrix cores) held to two
+// wavefronts per SIMD keeps its accumulators in VGPRs (256, a few spills)
+// instead of running at one (0.76 -> 0.57 ms per config-5 step).
 template <int MODE, int NT, int FEAT>
-__global__ __launch_bounds__(NT, (NT == 256 && ((MODE == 1 && FEAT == FEAT_NONE) || MODE == 0)) ? 3 : 1) void
+__global__ __launch_bounds__(NT, (NT == 256 && ((MODE == 1 && FEAT == FEAT_NONE) || MODE == 0))
+                                     ? 3
+                                     : ((MODE == 1 && FEAT == FEAT_CLOSURE) ? 2 : 1)) void
 k_particles(PartArgs A, StepParams P, FastGeom g) {
   constexpr int NW = NT / 64;
   __shared__ MlpBlob s_mlp;
@@ -520,11 +525,11 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
           } else {
             // plastic solids: FP32 SVD and return map, redone in FP64 for an
             // ill-conditioned trial state (or an unconverged sweep).  Sample
-            // logging and the learned closure keep the FP64 SVD throughout:
-            // their records and residuals are those of the exact FP64 return
+            // logging keeps the FP64 SVD throughout: its records are the
+            // exact FP64 return
             float Fn[9];
             PlasticStep<float> R;
-            int st = FEAT == FEAT_NONE ? plastic_step<float, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R) : PLASTIC_RETRY;
+            int st = FEAT != FEAT_LOG ? plastic_step<float, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R) : PLASTIC_RETRY;
             if (st == PLASTIC_RETRY) {
               PlasticStep<double> R2;
               st = plastic_step<double, MODE == MODE_FUSED>(Md, F, M, Fn, tau, R2);
