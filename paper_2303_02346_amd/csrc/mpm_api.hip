@@ -512,7 +512,7 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
     // recompute: sorted s_ts .. s_{te-1}, each with its step's grid
     PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)seg * c->state_bytes), N);
     SortedState S0 = sorted_state(c, c->L.seg);
-    fast_sort_user(f, P, ck, S0, s);
+    fast_sort_user(f, P, ck, S0, s, true);   // (the padded import counters: the touched scan)
     for (int t = ts; t < te; t++) {
       const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
       SortedState Si = sorted_state(c, bi);

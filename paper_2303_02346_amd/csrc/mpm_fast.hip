@@ -133,98 +133,107 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
 }
 
 // Dense variant: exclusive scan of all counts -> offsets, the list of
-// occupied keys in key (Morton) order, and the counts zeroed.  Run by one
-// workgroup of NT threads; each thread owns a contiguous range of keys,
-// loaded as independent 16-byte loads (the counters of key k at
-// counts[k * stride]; with stride > 1, one load per key).
+// occupied keys in key (Morton) order, and the counts zeroed (the counter of
+// key k at counts[k * stride]).  Run by one workgroup of NT threads: each
+// wavefront owns a contiguous range of 256-key groups, one group per pass of
+// its lanes (4 keys a lane, one coalesced 16-byte load); a first pass sums
+// the range, the wavefront totals give each range its base, and a second
+// pass scans the groups in order.  Loads are issued eight groups at a time,
+// and the first eight groups stay in registers from the first pass to the
+// second (at 128^3, 32768 keys, that is every group: one round trip).
 template <int NT>
 __device__ void scan_keys(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, int4* __restrict__ list,
                           uint32_t* __restrict__ list_n, int n_keys, int stride = 1) {
   constexpr int NW = NT / 64;
-  __shared__ uint32_t s_sum[NW], s_nz[NW];
-  const int t = threadIdx.x;
-  const int per = ((n_keys + NT - 1) / NT + 3) & ~3;       // multiple of 4
-  const int k0 = t * per;
-  // batches of 32 keys as 8 independent 16-byte loads
-  auto load_batch = [&](int b, uint4* v) {
+  __shared__ uint32_t s_tot[NW], s_nzw[NW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int groups = (n_keys + 255) / 256;
+  const int gpw = (groups + NW - 1) / NW;
+  const int g0 = min(groups, wv * gpw), g1 = min(groups, g0 + gpw);
+  auto load4 = [&](int g, uint32_t* c) {
+    const int k = g * 256 + 4 * lane;
+    if (g < g1 && stride == 1 && k + 3 < n_keys) {
+      const uint4 v = *(const uint4*)(counts + k);
+      c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+    } else {
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-      const int k = k0 + b + 4 * u;
-      if (stride == 1 && b + 4 * u < per && k + 3 < n_keys) v[u] = *(const uint4*)(counts + k);
-      else {
-        const bool in = b + 4 * u < per;
-        v[u].x = (in && k < n_keys) ? counts[(size_t)k * stride] : 0u;
-        v[u].y = (in && k + 1 < n_keys) ? counts[(size_t)(k + 1) * stride] : 0u;
-        v[u].z = (in && k + 2 < n_keys) ? counts[(size_t)(k + 2) * stride] : 0u;
-        v[u].w = (in && k + 3 < n_keys) ? counts[(size_t)(k + 3) * stride] : 0u;
-      }
+      for (int q = 0; q < 4; q++) c[q] = (g < g1 && k + q < n_keys) ? counts[(size_t)(k + q) * stride] : 0u;
     }
   };
-  uint4 v0[8];
-  load_batch(0, v0);
+  constexpr int GB = 8;   // groups per batch of loads
+  uint32_t first[GB][4];
+#pragma unroll
+  for (int u = 0; u < GB; u++) load4(g0 + u, first[u]);
   uint32_t sum = 0, nz = 0;
-  for (int b = 0; b < per; b += 32) {
-    uint4 v[8];
-    if (b == 0) {
 #pragma unroll
-      for (int u = 0; u < 8; u++) v[u] = v0[u];
-    } else {
-      load_batch(b, v);
-    }
+  for (int u = 0; u < GB; u++)
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-      sum += v[u].x + v[u].y + v[u].z + v[u].w;
-      nz += (v[u].x > 0) + (v[u].y > 0) + (v[u].z > 0) + (v[u].w > 0);
-    }
+    for (int q = 0; q < 4; q++) { sum += first[u][q]; nz += first[u][q] > 0u ? 1u : 0u; }
+  for (int g = g0 + GB; g < g1; g += GB) {
+    uint32_t c[GB][4];
+#pragma unroll
+    for (int u = 0; u < GB; u++) load4(g + u, c[u]);
+#pragma unroll
+    for (int u = 0; u < GB; u++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) { sum += c[u][q]; nz += c[u][q] > 0u ? 1u : 0u; }
   }
-  // inclusive scan within the wavefront, then across the wavefronts
-  const int lane = t & 63, wv = t >> 6;
-  uint32_t is = sum, inz = nz;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t o = __shfl_up(is, off), o2 = __shfl_up(inz, off);
-    if (lane >= off) { is += o; inz += o2; }
-  }
-  if (lane == 63) { s_sum[wv] = is; s_nz[wv] = inz; }
+  for (int off = 32; off > 0; off >>= 1) { sum += __shfl_xor(sum, off); nz += __shfl_xor(nz, off); }
+  if (lane == 0) { s_tot[wv] = sum; s_nzw[wv] = nz; }
   __syncthreads();
-  uint32_t woff = 0, wnz = 0, totnz = 0;
+  uint32_t run = 0, li = 0, totnz = 0;
 #pragma unroll
   for (int q = 0; q < NW; q++) {
-    if (q < wv) { woff += s_sum[q]; wnz += s_nz[q]; }
-    totnz += s_nz[q];
+    if (q < wv) { run += s_tot[q]; li += s_nzw[q]; }
+    totnz += s_nzw[q];
   }
-  uint32_t run = woff + is - sum, li = wnz + inz - nz;
-  for (int b = 0; b < per; b += 32) {
-    uint4 v[8];
-    if (b == 0) {
+  for (int gb = g0; gb < g1; gb += GB) {
+    uint32_t cb[GB][4];
 #pragma unroll
-      for (int u = 0; u < 8; u++) v[u] = v0[u];
-    } else {
-      load_batch(b, v);
+    for (int u = 0; u < GB; u++) {
+      if (gb == g0) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) cb[u][q] = first[u][q];
+      } else {
+        load4(gb + u, cb[u]);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-      const int k = k0 + b + 4 * u;
-      if (b + 4 * u >= per || k >= n_keys) break;
-      const uint32_t c[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-      uint32_t o[4];
+    for (int u = 0; u < GB; u++) {
+      const int g = gb + u;
+      if (g >= g1) break;
+      const uint32_t* c = cb[u];
+      const uint32_t ls = c[0] + c[1] + c[2] + c[3];
+      const uint32_t ln = (c[0] > 0u) + (c[1] > 0u) + (c[2] > 0u) + (c[3] > 0u);
+      uint32_t is = ls, in = ln;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o1 = __shfl_up(is, off), o2 = __shfl_up(in, off);
+        if (lane >= off) { is += o1; in += o2; }
+      }
+      uint32_t o = run + is - ls, l = li + in - ln;
+      const int k = g * 256 + 4 * lane;
+      uint32_t offs[4];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        o[q] = run;
-        if (c[q] > 0) { list[li] = make_int4(k + q, (int)run, (int)c[q], 0); li++; }
-        run += c[q];
+        offs[q] = o;
+        if (c[q] > 0u) { list[l] = make_int4(k + q, (int)o, (int)c[q], 0); l++; }
+        o += c[q];
       }
-      if (k + 3 < n_keys && stride == 1) {
-        *(uint4*)(offsets + k) = make_uint4(o[0], o[1], o[2], o[3]);
-        *(uint4*)(counts + k) = make_uint4(0, 0, 0, 0);
+      if (stride == 1 && k + 3 < n_keys) {
+        *(uint4*)(offsets + k) = make_uint4(offs[0], offs[1], offs[2], offs[3]);
+        *(uint4*)(counts + k) = make_uint4(0u, 0u, 0u, 0u);
       } else {
 #pragma unroll
         for (int q = 0; q < 4; q++)
-          if (k + q < n_keys) { offsets[k + q] = o[q]; counts[(size_t)(k + q) * stride] = 0; }
+          if (k + q < n_keys) { offsets[k + q] = offs[q]; counts[(size_t)(k + q) * stride] = 0u; }
       }
+      run += (uint32_t)__shfl((int)is, 63);
+      li += (uint32_t)__shfl((int)in, 63);
     }
   }
-  if (t == NT - 1) list_n[0] = totnz;
+  if (threadIdx.x == 0) list_n[0] = totnz;
 }
 
 // The scan of a sort; also advances the per-call epoch of the step stamps
