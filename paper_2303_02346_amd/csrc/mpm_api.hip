@@ -171,7 +171,24 @@ struct mpm_ctx {
   KernelTimer timer;
   bool plain_adjoint;
   RigidCtx rigid;           // n_bodies = 0: no rigid bodies
+  // captured backward calls (tiled adjoint without rigid bodies, graph mode),
+  // keyed by the horizon, the gradient pointers and the launch shape
+  struct BwdGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int T = 0, part_wgs = 0, grid_wgs = 0;
+    const void* ptr[11] = {};
+    unsigned long long n_ep = 0;   // stamp epochs one call advances
+  };
+  std::vector<BwdGraph> bgraphs;
 };
+
+static void destroy_bwd_graph(mpm_ctx::BwdGraph& G) {
+  if (G.exec) hipGraphExecDestroy(G.exec);
+  if (G.graph) hipGraphDestroy(G.graph);
+  G.exec = nullptr;
+  G.graph = nullptr;
+}
 
 // Projection record slot i of the rigid bodies.
 static double* rigid_rec(mpm_ctx* c, int i) {
@@ -572,15 +589,13 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
   return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
 }
 
-int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_dev, mpm_state* grad_0) {
-  if (!c || !grad_T || !grad_T->x || !grad_T->v || !grad_actions_dev) return MPM_EINVAL;
-  if (!c->has_state || !c->d.requires_grad || c->t < 1) return MPM_ESTATE;
+// The work of one backward call, enqueued on the context's stream.
+static int enqueue_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_dev, mpm_state* grad_0) {
   const int N = c->d.n_particles;
   const int T = c->t;
   const int k = c->d.ckpt_every;
   const int S = c->d.n_scenes;
   StepParams P = make_params(c);
-  c->fast.last_buf = -1;   // the recompute reuses the forward's buffers
   size_t nodes = (size_t)c->d.n_grid * c->d.n_grid * c->d.n_grid * S;
   hipStream_t s = c->stream;
   PState a_cur = packed_state((float*)(c->ws + c->L.adj0), N);
@@ -634,11 +649,63 @@ int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_d
   launch_pose_adj(S, T, c->d.dt, (const float*)(c->ws + c->L.act), (const double*)(c->ws + c->L.pose), acc,
                   grad_actions_dev, s);
   if (grad_0) {
-    if (!grad_0->x || !grad_0->v || !grad_0->C || !grad_0->F || !grad_0->J) return MPM_EINVAL;
     PState g0 = user_pstate(grad_0, N);
     launch_copy_state(a_cur, g0, s);
   }
-  if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
+int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_dev, mpm_state* grad_0) {
+  if (!c || !grad_T || !grad_T->x || !grad_T->v || !grad_actions_dev) return MPM_EINVAL;
+  if (!c->has_state || !c->d.requires_grad || c->t < 1) return MPM_ESTATE;
+  if (grad_0 && (!grad_0->x || !grad_0->v || !grad_0->C || !grad_0->F || !grad_0->J)) return MPM_EINVAL;
+  c->fast.last_buf = -1;   // the recompute reuses the forward's buffers
+  FastPath& f = c->fast;
+  // Graph mode: the tiled backward (without rigid bodies, whose steps run
+  // eagerly) is captured once per horizon, gradient pointers and launch
+  // shape, then replayed.  The captured sorts advance the device epoch of
+  // the step stamps; the host keeps its count in step, clearing the stamps
+  // before a replay that crosses the epoch's 16-bit wrap.
+  if (f.use_graph && !c->plain_adjoint && c->rigid.n_bodies == 0) {
+    const void* key[11] = {grad_T->x, grad_T->v, grad_T->C, grad_T->F, grad_T->J, grad_actions_dev,
+                           grad_0 ? grad_0->x : nullptr, grad_0 ? grad_0->v : nullptr, grad_0 ? grad_0->C : nullptr,
+                           grad_0 ? grad_0->F : nullptr, grad_0 ? grad_0->J : nullptr};
+    mpm_ctx::BwdGraph* G = nullptr;
+    for (auto& g : c->bgraphs) {
+      bool same = g.exec && g.T == c->t && g.part_wgs == f.part_wgs && g.grid_wgs == f.grid_wgs;
+      for (int q = 0; q < 11 && same; q++) same = g.ptr[q] == key[q];
+      if (same) G = &g;
+    }
+    hipStream_t s = c->stream;
+    if (!G) {
+      mpm_ctx::BwdGraph g;
+      g.T = c->t;
+      g.part_wgs = f.part_wgs;
+      g.grid_wgs = f.grid_wgs;
+      for (int q = 0; q < 11; q++) g.ptr[q] = key[q];
+      const unsigned long long calls0 = f.calls;
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_EHIP;
+      const int rc = enqueue_backward(c, grad_T, grad_actions_dev, grad_0);
+      const hipError_t ec = hipStreamEndCapture(s, &g.graph);
+      if (rc != MPM_OK || ec != hipSuccess) { destroy_bwd_graph(g); return rc != MPM_OK ? rc : MPM_EHIP; }
+      if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) { destroy_bwd_graph(g); return MPM_EHIP; }
+      g.n_ep = f.calls - calls0;
+      if (c->bgraphs.size() >= 4) { destroy_bwd_graph(c->bgraphs.front()); c->bgraphs.erase(c->bgraphs.begin()); }
+      c->bgraphs.push_back(g);
+      G = &c->bgraphs.back();
+    } else {
+      if ((f.calls & 0xffffull) + G->n_ep >= 0x10000ull) {
+        launch_zero(f.claim, (size_t)f.g.n_keys * 4, s);
+        launch_zero(f.tile_box, (size_t)f.g.n_keys * NSUB * 8, s);
+      }
+      f.calls += G->n_ep;
+    }
+    if (hipGraphLaunch(G->exec, s) != hipSuccess) return MPM_EHIP;
+    if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+    return finish(c);
+  }
+  const int rc = enqueue_backward(c, grad_T, grad_actions_dev, grad_0);
+  if (rc != MPM_OK) return rc;
   return finish(c);
 }
 
@@ -847,6 +914,7 @@ int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name,
 
 int mpm_destroy(mpm_ctx* c) {
   if (!c) return MPM_EINVAL;
+  for (auto& g : c->bgraphs) destroy_bwd_graph(g);
   c->timer.destroy();
   fast_destroy(c->fast);
   delete c;

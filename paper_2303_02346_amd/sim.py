@@ -216,18 +216,24 @@ class Simulator:
         """grad_x, grad_v: (3, N) adjoints of the current state.  Returns
         dL/d(actions) (t, S, 6) and optionally dL/d(state_0) (25, N)."""
         T = self.clock()
-        gT = torch.zeros(STATE_ROWS, self.N, dtype=torch.float32, device=self.device)
+        # persistent argument buffers, so that a graph-mode context replays
+        # its captured backward (the capture is keyed by these pointers)
+        bufs = getattr(self, "_bwd_bufs", None)
+        if bufs is None or bufs[1].shape[0] != T:
+            gT = torch.zeros(STATE_ROWS, self.N, dtype=torch.float32, device=self.device)
+            ga = torch.zeros(T, self.S, 6, dtype=torch.float32, device=self.device)
+            g0 = torch.zeros_like(gT)
+            self._bwd_bufs = bufs = (gT, ga, g0)
+        gT, ga, g0 = bufs
         gT[0:3] = grad_x
         gT[3:6] = grad_v
         gs = self.state_struct(gT, with_mat=False)
-        ga = torch.zeros(T, self.S, 6, dtype=torch.float32, device=self.device)
-        g0 = torch.zeros_like(gT) if want_grad0 else None
         g0s = self.state_struct(g0, with_mat=False) if want_grad0 else None
         self._sync_in()
         _lib.check(_lib.lib().mpm_step_backward(self.ctx, ctypes.byref(gs), ctypes.c_void_p(ga.data_ptr()),
                                                 ctypes.byref(g0s) if g0s is not None else None),
                    "mpm_step_backward", self.ctx)
-        return (ga, g0) if want_grad0 else ga
+        return (ga.clone(), g0.clone()) if want_grad0 else ga.clone()
 
     def loss_blob(self, mu, sigma: float, want_grad: bool = True):
         loss = torch.zeros(1, dtype=torch.float32, device=self.device)
