@@ -526,11 +526,39 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
   const int n_seg = (T + k - 1) / k;
   for (int seg = n_seg - 1; seg >= 0; seg--) {
     const int ts = seg * k, te = ts + k < T ? ts + k : T;
-    // recompute: sorted s_ts .. s_{te-1}, each with its step's grid
+    // recompute: block-sorted records of s_ts .. s_{te-1}, each with its step's grid
     PState ck = packed_state((float*)(c->ws + c->L.ckpt + (size_t)seg * c->state_bytes), N);
     SortedState S0 = sorted_state(c, c->L.seg);
     fast_sort_user(f, P, ck, S0, s, true);   // (the padded import counters: the touched scan)
-    for (int t = ts; t < te; t++) {
+    // record of step t (record 1 keeps record 0's order: the first fused
+    // step places its output by the import's offsets)
+    auto rec = [&](int t) {
+      SortedState R = sorted_state(c, c->L.seg + (size_t)(t - ts) * rb);
+      if (!rigid && t - ts == 1) { R.list = S0.list; R.list_n = S0.list_n; }
+      return R;
+    };
+    if (!rigid) {
+      // P2G of s_ts, then one fused kernel per further step: each record is
+      // sorted by the block keys of the previous step's positions (the
+      // adjoint kernels' velocity and tile windows allow that drift) and the
+      // fused kernel records the row map, so the recompute needs no sort
+      uint32_t sid = fast_next_sid(f);
+      fast_p2g(f, P, S0, sid, s);
+      fast_grid_scan(f, P, S0, sid, ts, pose_at(c, 0), act_at(c, 0), te - ts > 1 ? rec(ts + 1).cl_count : nullptr,
+                     nullptr, nullptr, s);
+      for (int t = ts + 1; t < te; t++) {
+        const SortedState Sp = rec(t - 1), Si = rec(t);
+        sid = fast_next_sid(f);
+        fast_fused(f, P, Sp, Si, sorted_map(c, c->L.seg + (size_t)(t - 1 - ts) * rb), sid, s);
+        // the keys it counted describe record t + 1's order (or, after the
+        // segment's last step, only need clearing)
+        const bool more = t + 1 < te;
+        SortedState Sn = more ? rec(t + 1) : SortedState{};
+        fast_grid_scan(f, P, Si, sid, t, pose_at(c, 0), act_at(c, 0), more ? Sn.cl_count : nullptr,
+                       more ? Sn.list : f.list[0], more ? Sn.list_n : f.list_n, s);
+      }
+    }
+    for (int t = ts; t < te && rigid; t++) {
       const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
       SortedState Si = sorted_state(c, bi);
       const uint32_t sid = fast_next_sid(f);
@@ -550,7 +578,7 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
     // read through s_{te-1}'s ids, the later ones through the recorded maps
     for (int t = te - 1; t >= ts; t--) {
       const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
-      SortedState Si = sorted_state(c, bi);
+      SortedState Si = rec(t);
       AdjArgs A;
       A.st = Si.b;
       A.list = Si.list;

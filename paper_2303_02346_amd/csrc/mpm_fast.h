@@ -146,6 +146,19 @@ void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t 
 void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
                const float* act_base, hipStream_t s);
 void fast_g2p(FastPath& f, const StepParams& P, const SortedState& st, const PBuf& out, hipStream_t s);
+// The fused kernel on records: G2P of step t - 1 from `in` (with in's grid),
+// the update, and P2G of step t, the state written to `out` in the slots of
+// the latest scan (so `out` is sorted by the block keys of in's positions,
+// one step behind its own; map[j] = out's row of in's row j), its tiles under
+// `sid` and its block claims into out's claim list; the keys of the new
+// positions are counted for the next scan.  fast_grid_scan is fast_grid that
+// also clears the claim counter cl_zero and, with scan_list, scans those
+// counts into scan_list (each block listed once).
+void fast_fused(FastPath& f, const StepParams& P, const SortedState& in, const SortedState& out, uint32_t* map,
+                uint32_t sid, hipStream_t s);
+void fast_grid_scan(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t,
+                    const double* pose_base, const float* act_base, uint32_t* cl_zero, int4* scan_list,
+                    uint32_t* scan_list_n, hipStream_t s);
 // The path's own sorted state over buffer b (0 or 1) and list b, using the
 // path's shared grid arrays; and the scatter of a sorted buffer to user order.
 SortedState fast_own_state(FastPath& f, int b);

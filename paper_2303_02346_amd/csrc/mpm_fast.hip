@@ -390,6 +390,7 @@ struct PartArgs {
   float* log_buf;                      // samples of 9 floats: log sigma_tr (desc), alpha, c, kappa, eps'
   unsigned long long* log_count;
   unsigned long long log_cap;
+  uint32_t* map_out;                   // (records) output row of each input row, or nullptr
 };
 
 enum { FEAT_NONE = 0, FEAT_LOG = 1, FEAT_CLOSURE = 2 };
@@ -591,6 +592,7 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
           }
           O.id[dst] = A.in.id[j];
           O.mat[dst] = (uint8_t)m;
+          if (A.map_out) A.map_out[j] = dst;
         } else {
           ok = false;
         }
@@ -1172,6 +1174,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   A.log_buf = f.log_buf;
   A.log_count = f.log_count;
   A.log_cap = f.log_cap;
+  A.map_out = nullptr;
   // Bookkeeping: `rd` is the list describing buf[cur] (the buffer the next
   // particle kernel reads); `wr` is the list describing the order in which
   // the current offsets place particles (the buffer the next kernel writes).
@@ -1347,6 +1350,36 @@ static PartArgs sorted_args(FastPath& f, const SortedState& st, uint32_t sid) {
 void fast_p2g(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, hipStream_t s) {
   PartArgs A = sorted_args(f, st, sid);
   k_particles<MODE_P2G, 256, FEAT_NONE><<<f.part_wgs, 256, 0, s>>>(A, P, f.g);
+}
+
+void fast_fused(FastPath& f, const StepParams& P, const SortedState& in, const SortedState& out, uint32_t* map,
+                uint32_t sid, hipStream_t s) {
+  PartArgs A = sorted_args(f, in, sid);
+  A.out = out.b;
+  A.cl_list = out.cl_list ? out.cl_list : f.cl_list;
+  A.cl_count = out.cl_count ? out.cl_count : f.cl_count;
+  A.map_out = map;
+  k_particles<MODE_FUSED, 256, FEAT_NONE><<<f.part_wgs, 256, 0, s>>>(A, P, f.g);
+}
+
+void fast_grid_scan(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t,
+                    const double* pose_base, const float* act_base, uint32_t* cl_zero, int4* scan_list,
+                    uint32_t* scan_list_n, hipStream_t s) {
+  ScanArgs SA = {};
+  SA.counts = f.counts;
+  SA.offsets = f.offsets;
+  SA.touched = f.touched;
+  SA.n_touched = f.n_touched;
+  SA.list = scan_list;
+  SA.list_n = scan_list_n;
+  SA.n_keys = f.g.n_keys;
+  SA.split_nt = 0;       // the adjoint's records list each block once
+  SA.max_chunks = 0;
+  const int do_scan = scan_list ? 1 : 0;
+  k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, f.g, st.cl_list ? st.cl_list : f.cl_list,
+                                              st.cl_count ? st.cl_count : f.cl_count, cl_zero, f.tile_box, f.tiles,
+                                              f.gen, sid, st.vgrid ? st.vgrid : f.vgrid, pose_base, act_base, f.t0_dev,
+                                              do_scan, SA, t, st.mmv);
 }
 
 void fast_grid(FastPath& f, const StepParams& P, const SortedState& st, uint32_t sid, int t, const double* pose_base,
