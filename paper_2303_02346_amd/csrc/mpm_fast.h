@@ -42,6 +42,10 @@ struct FastGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int n = 0, part_threads = 0, part_wgs = 0, grid_wgs = 0, share_chunks = 0;
+  // the checkpoints the call writes (slots from its start time)
+  int ck_k = 0, ck_t0 = 0;
+  char* ck_base = nullptr;
+  size_t ck_stride = 0;
   bool timed = false, do_export = true;
   // every user pointer and logging argument the captured launches bake in
   const float *x = nullptr, *v = nullptr, *C = nullptr, *F = nullptr, *J = nullptr;

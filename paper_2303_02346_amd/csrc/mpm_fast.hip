@@ -1262,7 +1262,7 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
   // a timed call runs eagerly: its per-launch events bracket real launches
   // (events recorded inside a captured graph do not give elapsed times here)
   const bool timed = timer && timer->on;
-  if (!f.use_graph || timed || f.ck_k > 0) {
+  if (!f.use_graph || timed) {
     std::vector<hipEvent_t> ev;
     if (timed) {
       ev.resize(2 * (size_t)(n - 1));
@@ -1272,13 +1272,14 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
     if (timed) timer->adopt(ev, n - 1, true);
     return hipGetLastError() == hipSuccess ? 0 : -3;
   }
-  // graph mode: one captured call per (n, state pointers, launch shape),
-  // replayed with the clock taken from device memory
+  // graph mode: one captured call per (n, state pointers, launch shape,
+  // checkpoint slots), replayed with the clock taken from device memory
   FastGraph* G = nullptr;
   for (auto& c : f.graphs)
     if (c.exec && c.n == n && c.x == user.x && c.v == user.v && c.C == user.C && c.F == user.F && c.J == user.J &&
         c.mat == P.mat && c.part_threads == f.part_threads && c.part_wgs == f.part_wgs && c.grid_wgs == f.grid_wgs &&
-        c.share_chunks == f.share_chunks &&
+        c.share_chunks == f.share_chunks && c.ck_k == f.ck_k && c.ck_t0 == f.ck_t0 && c.ck_base == f.ck_base &&
+        c.ck_stride == f.ck_stride &&
         c.timed == timed && c.do_export == f.do_export && c.mlp == f.mlp_blob && c.log == f.log_buf &&
         c.log_count == f.log_count && c.log_cap == f.log_cap && c.tol == f.closure_tol)
       G = &c;
@@ -1286,6 +1287,7 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
     FastGraph c;
     c.n = n; c.x = user.x; c.v = user.v; c.C = user.C; c.F = user.F; c.J = user.J; c.mat = P.mat;
     c.part_threads = f.part_threads; c.part_wgs = f.part_wgs; c.share_chunks = f.share_chunks;
+    c.ck_k = f.ck_k; c.ck_t0 = f.ck_t0; c.ck_base = f.ck_base; c.ck_stride = f.ck_stride;
     c.grid_wgs = f.grid_wgs; c.timed = timed; c.do_export = f.do_export;
     c.mlp = f.mlp_blob; c.log = f.log_buf; c.log_count = f.log_count; c.log_cap = f.log_cap; c.tol = f.closure_tol;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -3;

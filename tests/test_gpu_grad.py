@@ -154,10 +154,11 @@ def test_config3_gradient_vs_oracle_fd():
 
 
 def test_backward_graph_replays_match_eager():
-    """Graph mode captures the tiled backward once per horizon and gradient
-    pointers and replays it: three replays (with the forward, the loss and
-    eager work between them, and a changed seed gradient on the last) give
-    the eager backward's gradients."""
+    """Graph mode captures the checkpointed forward call and the tiled
+    backward once per horizon and gradient pointers and replays them: three
+    replays (with the loss and eager work between them, and a changed seed
+    gradient each time) give the eager forward's loss and backward's
+    gradients."""
     sc = scenes.tiny(n_particles=1500, n_grid=24, steps=12, seed=3)
     eager = sim_of(sc, requires_grad=True, ckpt_every=5)
     graph = sim_of(sc, requires_grad=True, ckpt_every=5, graph=True)
