@@ -219,11 +219,13 @@ def test_paper_operating_point_vs_oracle(threads):
 # gradients
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("adjoint", ["tiled", "plain"])
-@pytest.mark.parametrize("seed", [0, 1])
-def test_gradient_tiny_vs_oracle(seed, adjoint):
+@pytest.mark.parametrize("seed,ckpt", [(0, 3), (1, 3), (0, 1), (1, 8)])
+def test_gradient_tiny_vs_oracle(seed, ckpt, adjoint):
+    """Segments of 3, 3 and 2 steps, of one step each (no fused recompute
+    step), and one segment of all 8 steps."""
     sc = scenes.tiny(n_particles=90, n_grid=16, steps=8, seed=seed)
-    say(f"gradient tiny seed {seed}, {adjoint} adjoint")
-    sim = sim_of(sc, requires_grad=True, ckpt_every=3, adjoint=adjoint)
+    say(f"gradient tiny seed {seed}, checkpoint every {ckpt}, {adjoint} adjoint")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=ckpt, adjoint=adjoint)
     sim.step(sc.horizon)
     loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
     ga = sim.backward(g[0:3], torch.zeros_like(g[0:3]))[:, 0].double().cpu().numpy()
