@@ -34,6 +34,8 @@ void launch_g2p_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom&
 void launch_grid_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, const double* pose_t,
                            const float* act_t, double* acc_t, hipStream_t s);
 void launch_p2g_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom& g, int n_wgs, hipStream_t s);
-void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, bool to_user, hipStream_t s);
+// adjoint rows in sorted order (row j of particle id[j]) -> user order; pos:
+// N words of scratch
+void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, uint32_t* pos, hipStream_t s);
 
 }  // namespace mpm

@@ -603,17 +603,23 @@ __global__ __launch_bounds__(REDO_NT) void k_p2g_adj_redo(AdjArgs A, StepParams 
   }
 }
 
-// state adjoint rows: sorted order -> user order (out[id[j]] = in[j]), or the
-// reverse (out[j] = in[id[j]])
-__global__ __launch_bounds__(256) void k_adj_reorder(const float* __restrict__ in, float* __restrict__ out,
-                                                     const uint32_t* __restrict__ id, int N, int to_user) {
+// state adjoint rows from sorted order to user order, as a gather:
+// k_adj_pos records the sorted row of every user index (one scattered word
+// per particle), then every row is read through it and written in order
+__global__ __launch_bounds__(256) void k_adj_pos(const uint32_t* __restrict__ id, int N, uint32_t* __restrict__ pos) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
   const uint32_t p = id[j];
-  if (p >= (uint32_t)N) return;
-  const size_t src = to_user ? (size_t)j : (size_t)p, dst = to_user ? (size_t)p : (size_t)j;
+  if (p < (uint32_t)N) pos[p] = (uint32_t)j;
+}
+__global__ __launch_bounds__(256) void k_adj_gather(const float* __restrict__ in, float* __restrict__ out,
+                                                    const uint32_t* __restrict__ pos, int N) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const uint32_t j = pos[p];
+  if (j >= (uint32_t)N) return;
 #pragma unroll
-  for (int k = 0; k < STATE_FLOATS; k++) out[k * (size_t)N + dst] = in[k * (size_t)N + src];
+  for (int k = 0; k < STATE_FLOATS; k++) out[k * (size_t)N + p] = in[k * (size_t)N + j];
 }
 
 static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
@@ -630,8 +636,9 @@ void launch_p2g_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom&
   k_p2g_adj_tiled<256><<<n_wgs, 256, 0, s>>>(A, P, g);
   k_p2g_adj_redo<<<REDO_WGS, REDO_NT, 0, s>>>(A, P, g);
 }
-void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, bool to_user, hipStream_t s) {
-  k_adj_reorder<<<nblk(N, 256), 256, 0, s>>>(in, out, id, N, to_user ? 1 : 0);
+void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, uint32_t* pos, hipStream_t s) {
+  k_adj_pos<<<nblk(N, 256), 256, 0, s>>>(id, N, pos);
+  k_adj_gather<<<nblk(N, 256), 256, 0, s>>>(in, out, pos, N);
 }
 
 }  // namespace mpm

@@ -104,7 +104,7 @@ Layout plan(const mpm_desc* d) {
   L.vgrid = take(nodes * sizeof(float4));
   L.pose = take((T + 1) * S * POSE_DOUBLES * sizeof(double));
   L.act = take(T * S * 6 * sizeof(float));
-  L.scratch = take(64);
+  L.scratch = take((2 + 2 * LOSS_SLOTS) * sizeof(double));
   L.cstats = take(64);
   L.fast = take(fast_workspace_bytes(d->n_grid, (int)S, (int)N));
   if (d->requires_grad) {
@@ -611,7 +611,7 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
       PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
     }
     // back to user order for the previous segment
-    launch_adj_reorder(a_cur.x, a_nxt.x, S0.b.id, N, true, s);
+    launch_adj_reorder(a_cur.x, a_nxt.x, S0.b.id, N, f.inv, s);   // (the import's map is free here)
     PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
   }
   return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
@@ -743,7 +743,7 @@ int mpm_loss_blob(mpm_ctx* c, const float mu_g[3], float sigma_g, float* loss_de
   StepParams P = make_params(c);
   PState us = user_pstate(&c->user, c->d.n_particles);
   double* scratch = (double*)(c->ws + c->L.scratch);
-  launch_zero(scratch, 64, c->stream);
+  launch_zero(scratch, align_up((2 + 2 * LOSS_SLOTS) * sizeof(double)), c->stream);
   launch_loss_blob(P, us, mu_g[0], mu_g[1], mu_g[2], sigma_g, scratch, loss_dev,
                    (grad_out && grad_out->x) ? grad_out->x : nullptr, c->stream);
   if (hipGetLastError() != hipSuccess) return MPM_EHIP;

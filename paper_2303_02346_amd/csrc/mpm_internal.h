@@ -136,6 +136,8 @@ void launch_p2g_adj_plain(const PState& st, const PState& bar, const StepParams&
 void launch_pose_adj(int n_scenes, int T, float dt, const float* act, const double* pose, const double* acc,
                      float* grad_act, hipStream_t s);
 
+// blob loss: scratch holds 2 + 2 LOSS_SLOTS doubles, zeroed by the caller
+constexpr int LOSS_SLOTS = 128;
 void launch_loss_blob(const StepParams& P, const PState& st, float mx, float my, float mz, float sigma,
                       double* scratch, float* loss, float* gx, hipStream_t s);
 void launch_copy_state(const PState& src, const PState& dst, hipStream_t s);

@@ -411,15 +411,28 @@ __global__ __launch_bounds__(256) void k_loss_sum(StepParams P, PState st, float
     sq += __shfl_xor(sq, off);
     cnt += __shfl_xor(cnt, off);
   }
+  // one FP64 atomic pair per wavefront, into one of LOSS_SLOTS copies (by
+  // wavefront index) so that the atomics do not queue on one address
   if ((threadIdx.x & 63) == 0 && cnt > 0) {
-    atomicAdd(scratch, sq);
-    atomicAdd(scratch + 1, cnt);
+    const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) % LOSS_SLOTS;
+    atomicAdd(scratch + 2 + 2 * w, sq);
+    atomicAdd(scratch + 3 + 2 * w, cnt);
   }
 }
 
-__global__ void k_loss_final(double* scratch, float sigma, float* loss) {
-  double cnt = scratch[1];
-  loss[0] = (float)((cnt > 0 ? scratch[0] / cnt : 0.0) + 3.0 * (double)sigma * sigma);
+// sums the copies into scratch[0] (squared distances) and scratch[1] (count)
+__global__ __launch_bounds__(64) void k_loss_final(double* scratch, float sigma, float* loss) {
+  double sq = 0.0, cnt = 0.0;
+  for (int w = threadIdx.x; w < LOSS_SLOTS; w += 64) { sq += scratch[2 + 2 * w]; cnt += scratch[3 + 2 * w]; }
+  for (int off = 32; off > 0; off >>= 1) {
+    sq += __shfl_xor(sq, off);
+    cnt += __shfl_xor(cnt, off);
+  }
+  if (threadIdx.x == 0) {
+    scratch[0] = sq;
+    scratch[1] = cnt;
+    loss[0] = (float)((cnt > 0 ? sq / cnt : 0.0) + 3.0 * (double)sigma * sigma);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_loss_grad(StepParams P, PState st, float mx, float my, float mz,
@@ -499,7 +512,7 @@ void launch_pose_adj(int n_scenes, int T, float dt, const float* act, const doub
 void launch_loss_blob(const StepParams& P, const PState& st, float mx, float my, float mz, float sigma,
                       double* scratch, float* loss, float* gx, hipStream_t s) {
   k_loss_sum<<<blocks_for(st.N, 256), 256, 0, s>>>(P, st, mx, my, mz, scratch);
-  k_loss_final<<<1, 1, 0, s>>>(scratch, sigma, loss);
+  k_loss_final<<<1, 64, 0, s>>>(scratch, sigma, loss);
   if (gx) k_loss_grad<<<blocks_for(st.N, 256), 256, 0, s>>>(P, st, mx, my, mz, scratch, gx);
 }
 void launch_copy_state(const PState& src, const PState& dst, hipStream_t s) {
