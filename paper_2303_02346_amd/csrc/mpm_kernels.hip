@@ -20,18 +20,69 @@ namespace mpm {
 // ---------------------------------------------------------------------------
 // Manipulator pose: c_{t+1} = c_t + dt u_t ; R_{t+1} = exp(dt [w_t]x) R_t
 // ---------------------------------------------------------------------------
-__global__ void k_pose(int n_scenes, int t0, int n, float dt, const float* __restrict__ act, double* __restrict__ pose) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+// Poses of steps t0 + 1 .. t0 + n of every scene (one workgroup per scene):
+// c_{t+1} = c_t + dt u_t and R_{t+1} = E_t R_t with E_t = exp(dt [w_t]x).
+// Chunks of POSE_NT steps: every thread forms its step's E_t, then
+// inclusive prefix products (later steps on the left) and prefix sums by
+// doubling in LDS, applied to the pose carried in from the previous chunk.
+constexpr int POSE_NT = 256;
+__global__ __launch_bounds__(POSE_NT) void k_pose(int n_scenes, int t0, int n, float dt, const float* __restrict__ act,
+                                                  double* __restrict__ pose) {
+  __shared__ double sP[2][POSE_NT][12];   // {prefix product (9), prefix sum of dt u (3)}
+  __shared__ double s_carry[12];          // pose at the chunk's start: c (3), R (9)
+  const int s = blockIdx.x, tid = threadIdx.x;
   if (s >= n_scenes) return;
-  for (int t = t0; t < t0 + n; t++) {
-    const double* P = pose + ((size_t)t * n_scenes + s) * POSE_DOUBLES;
-    double* Q = pose + ((size_t)(t + 1) * n_scenes + s) * POSE_DOUBLES;
-    const float* a = act + ((size_t)t * n_scenes + s) * 6;
-    double th[3] = {dt * (double)a[3], dt * (double)a[4], dt * (double)a[5]};
-    double E[9];
-    rodrigues(th, E);
-    for (int k = 0; k < 3; k++) Q[k] = P[k] + dt * (double)a[k];
-    matmul(E, P + 3, Q + 3);
+  if (tid < 12) s_carry[tid] = pose[((size_t)t0 * n_scenes + s) * POSE_DOUBLES + tid];
+  for (int ch = 0; ch < n; ch += POSE_NT) {
+    const int m = min(POSE_NT, n - ch);
+    double v[12];
+    if (tid < m) {
+      const float* a = act + ((size_t)(t0 + ch + tid) * n_scenes + s) * 6;
+      const double th[3] = {dt * (double)a[3], dt * (double)a[4], dt * (double)a[5]};
+      rodrigues(th, v);
+#pragma unroll
+      for (int k = 0; k < 3; k++) v[9 + k] = dt * (double)a[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; k++) v[k] = (k % 4 == 0 && k < 9) ? 1.0 : 0.0;
+    }
+    int buf = 0;
+#pragma unroll
+    for (int k = 0; k < 12; k++) sP[0][tid][k] = v[k];
+    __syncthreads();
+    for (int off = 1; off < POSE_NT; off <<= 1) {
+      if (tid >= off) {
+        const double* L = sP[buf][tid - off];
+        double w[12];
+        matmul(v, L, w);   // (steps tid - 2 off + 1 .. tid) = (later block) (earlier block)
+#pragma unroll
+        for (int k = 0; k < 3; k++) w[9 + k] = v[9 + k] + L[9 + k];
+#pragma unroll
+        for (int k = 0; k < 12; k++) v[k] = w[k];
+      }
+      buf ^= 1;
+#pragma unroll
+      for (int k = 0; k < 12; k++) sP[buf][tid][k] = v[k];
+      __syncthreads();
+    }
+    if (tid < m) {
+      double* Q = pose + ((size_t)(t0 + ch + tid + 1) * n_scenes + s) * POSE_DOUBLES;
+#pragma unroll
+      for (int k = 0; k < 3; k++) Q[k] = s_carry[k] + v[9 + k];
+      matmul(v, s_carry + 3, Q + 3);
+    }
+    __syncthreads();
+    if (tid == m - 1) {
+      double c1[3], R1[9];
+#pragma unroll
+      for (int k = 0; k < 3; k++) c1[k] = s_carry[k] + v[9 + k];
+      matmul(v, s_carry + 3, R1);
+#pragma unroll
+      for (int k = 0; k < 3; k++) s_carry[k] = c1[k];
+#pragma unroll
+      for (int k = 0; k < 9; k++) s_carry[3 + k] = R1[k];
+    }
+    __syncthreads();
   }
 }
 
@@ -364,34 +415,66 @@ __global__ __launch_bounds__(256) void k_p2g_adj_plain(PState st, PState bo, Ste
 // Pose adjoint: backpropagate the per-step local partials through
 // c_{t+1} = c_t + dt u_t and R_{t+1} = exp(dt [w_t]x) R_t.
 // ---------------------------------------------------------------------------
-__global__ void k_pose_adj(int n_scenes, int T, float dt, const float* __restrict__ act, const double* __restrict__ pose,
-                           const double* __restrict__ acc, float* __restrict__ grad_act) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per scene, in chunks of PADJ_NT steps from the last: the
+// step rotations E_t are formed in parallel, one thread then runs the
+// recursion of the pose adjoints (Rbar_t = E_t^T Rbar_{t+1} + abar e_y^T,
+// cbar_t = cbar_{t+1} + local), keeping the values that enter every step,
+// and the action adjoints of all steps are formed in parallel from them.
+constexpr int PADJ_NT = 128;
+__global__ __launch_bounds__(PADJ_NT) void k_pose_adj(int n_scenes, int T, float dt, const float* __restrict__ act,
+                                                      const double* __restrict__ pose, const double* __restrict__ acc,
+                                                      float* __restrict__ grad_act) {
+  __shared__ double sE[PADJ_NT][9], sRb[PADJ_NT][9], scb[PADJ_NT][3], sA[PADJ_NT][6];
+  __shared__ double s_Rb[9], s_cb[3];   // the adjoints entering the chunk's last step
+  const int s = blockIdx.x, tid = threadIdx.x;
   if (s >= n_scenes) return;
-  double cb[3] = {0, 0, 0}, Rb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int t = T - 1; t >= 0; t--) {
-    const double* A = acc + ((size_t)t * n_scenes + s) * ACC_DOUBLES;
-    const float* a = act + ((size_t)t * n_scenes + s) * 6;
-    const double* Rt = pose + ((size_t)t * n_scenes + s) * POSE_DOUBLES + 3;
-    double th[3] = {dt * (double)a[3], dt * (double)a[4], dt * (double)a[5]};
-    double E[9];
-    rodrigues(th, E);
-    // Ebar = Rbar_{t+1} R_t^T ; m = vee(Ebar E^T) ; thbar = J_l(th)^T m
-    double Eb[9], T1[9];
-    matmul_nt(Rb, Rt, Eb);
-    matmul_nt(Eb, E, T1);
-    double m[3] = {T1[7] - T1[5], T1[2] - T1[6], T1[3] - T1[1]};
-    double thb[3];
-    left_jacobian_T(th, m, thb);
-    float* g = grad_act + ((size_t)t * n_scenes + s) * 6;
-    for (int k = 0; k < 3; k++) g[k] = (float)(A[k] + dt * cb[k]);
-    for (int k = 0; k < 3; k++) g[3 + k] = (float)(A[3 + k] + dt * thb[k]);
-    // cbar_t = cbar_{t+1} + local ; Rbar_t = E^T Rbar_{t+1} + abar e_y^T
-    for (int k = 0; k < 3; k++) cb[k] += A[6 + k];
-    double Rn[9];
-    matmul_tn(E, Rb, Rn);
-    for (int k = 0; k < 9; k++) Rb[k] = Rn[k];
-    for (int k = 0; k < 3; k++) Rb[k * 3 + 1] += A[9 + k];
+  if (tid < 9) s_Rb[tid] = 0.0;
+  if (tid < 3) s_cb[tid] = 0.0;
+  for (int hi = T; hi > 0; hi -= PADJ_NT) {
+    const int lo = hi > PADJ_NT ? hi - PADJ_NT : 0, m = hi - lo;
+    if (tid < m) {
+      const int t = lo + tid;
+      const float* a = act + ((size_t)t * n_scenes + s) * 6;
+      const double th[3] = {dt * (double)a[3], dt * (double)a[4], dt * (double)a[5]};
+      rodrigues(th, sE[tid]);
+      const double* A = acc + ((size_t)t * n_scenes + s) * ACC_DOUBLES;
+      for (int k = 0; k < 6; k++) sA[tid][k] = A[6 + k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double Rb[9], cb[3];
+      for (int k = 0; k < 9; k++) Rb[k] = s_Rb[k];
+      for (int k = 0; k < 3; k++) cb[k] = s_cb[k];
+      for (int i = m - 1; i >= 0; i--) {
+        for (int k = 0; k < 9; k++) sRb[i][k] = Rb[k];
+        for (int k = 0; k < 3; k++) { scb[i][k] = cb[k]; cb[k] += sA[i][k]; }
+        double Rn[9];
+        matmul_tn(sE[i], Rb, Rn);
+        for (int k = 0; k < 9; k++) Rb[k] = Rn[k];
+        for (int k = 0; k < 3; k++) Rb[k * 3 + 1] += sA[i][3 + k];
+      }
+      for (int k = 0; k < 9; k++) s_Rb[k] = Rb[k];
+      for (int k = 0; k < 3; k++) s_cb[k] = cb[k];
+    }
+    __syncthreads();
+    if (tid < m) {
+      const int t = lo + tid;
+      const float* a = act + ((size_t)t * n_scenes + s) * 6;
+      const double th[3] = {dt * (double)a[3], dt * (double)a[4], dt * (double)a[5]};
+      const double* A = acc + ((size_t)t * n_scenes + s) * ACC_DOUBLES;
+      const double* Rt = pose + ((size_t)t * n_scenes + s) * POSE_DOUBLES + 3;
+      // Ebar = Rbar_{t+1} R_t^T ; m = vee(Ebar E^T) ; thbar = J_l(th)^T m
+      double Eb[9], T1[9];
+      matmul_nt(sRb[tid], Rt, Eb);
+      matmul_nt(Eb, sE[tid], T1);
+      const double mv[3] = {T1[7] - T1[5], T1[2] - T1[6], T1[3] - T1[1]};
+      double thb[3];
+      left_jacobian_T(th, mv, thb);
+      float* g = grad_act + ((size_t)t * n_scenes + s) * 6;
+      for (int k = 0; k < 3; k++) g[k] = (float)(A[k] + dt * scb[tid][k]);
+      for (int k = 0; k < 3; k++) g[3 + k] = (float)(A[3 + k] + dt * thb[k]);
+    }
+    __syncthreads();
   }
 }
 
@@ -474,7 +557,7 @@ __global__ void k_scene_index(const int64_t* offs, int n_scenes, int N, int* psc
 static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_pose(int n_scenes, int t0, int n, float dt, const float* act, double* pose, hipStream_t s) {
-  k_pose<<<blocks_for(n_scenes, 64), 64, 0, s>>>(n_scenes, t0, n, dt, act, pose);
+  if (n > 0) k_pose<<<n_scenes, POSE_NT, 0, s>>>(n_scenes, t0, n, dt, act, pose);
 }
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
   size_t n4 = bytes / 16;
@@ -507,7 +590,7 @@ void launch_p2g_adj_plain(const PState& st, const PState& bar, const StepParams&
 }
 void launch_pose_adj(int n_scenes, int T, float dt, const float* act, const double* pose, const double* acc,
                      float* grad_act, hipStream_t s) {
-  k_pose_adj<<<blocks_for(n_scenes, 64), 64, 0, s>>>(n_scenes, T, dt, act, pose, acc, grad_act);
+  if (T > 0) k_pose_adj<<<n_scenes, PADJ_NT, 0, s>>>(n_scenes, T, dt, act, pose, acc, grad_act);
 }
 void launch_loss_blob(const StepParams& P, const PState& st, float mx, float my, float mz, float sigma,
                       double* scratch, float* loss, float* gx, hipStream_t s) {
