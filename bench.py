@@ -540,6 +540,7 @@ def main():
             ga = simg.backward(g[0:3], torch.zeros_like(g[0:3]))
             torch.cuda.synchronize()
             t_fb = time.perf_counter() - t0
+        simg.close()
         fb_bytes = 680.0 * N * T
         fwd_bwd = {"value": N * T / t_fb, "unit": "particle-steps/s", "steps": T, "ckpt_every": 16,
                    "adjoint": args.adjoint,
@@ -547,6 +548,24 @@ def main():
                    "grad_norm": float(ga.norm().item()),
                    "hbm_frac_algorithmic": round(fb_bytes / t_fb / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"[bench] fwd+bwd {t_fb * 1e3 / T:.3f} ms/step, {N * T / t_fb:.3e} particle-steps/s")
+        if args.adjoint == "tiled":
+            # the same with a record of every step kept by the forward
+            # (ckpt_every = 0): the backward recomputes nothing
+            simr = Simulator(sc, requires_grad=True, ckpt_every=0, horizon=T, graph=not args.no_graph)
+            for rep in range(2):
+                simr.reset()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                simr.step(T)
+                loss_r, g = simr.loss_blob(sc.target_mu, sc.target_sigma)
+                ga_r = simr.backward(g[0:3], torch.zeros_like(g[0:3]))
+                torch.cuda.synchronize()
+                t_r = time.perf_counter() - t0
+            simr.close()
+            fwd_bwd["no_recompute"] = {"ckpt_every": 0, "value": N * T / t_r, "ms_per_step": t_r * 1e3 / T,
+                                       "loss": float(loss_r.item()), "grad_norm": float(ga_r.norm().item())}
+            log(f"[bench] fwd+bwd with every step's record kept {t_r * 1e3 / T:.3f} ms/step, "
+                f"{N * T / t_r:.3e} particle-steps/s")
 
     batched = None
     if not args.no_batched:

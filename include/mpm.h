@@ -138,7 +138,11 @@ typedef struct {
   float contact_band;        /* contact threshold epsilon, in cells (3) */
   float contact_friction;    /* Coulomb coefficient (0.5) */
   int32_t horizon;           /* maximum number of steps between mpm_set_state calls */
-  int32_t ckpt_every;        /* checkpoint period k for the backward (16) */
+  int32_t ckpt_every;        /* checkpoint period k for the backward (16); 0 = keep a block-sorted
+                                 record of every step during the forward, so that the backward
+                                 recomputes nothing (tiled adjoint, no rigid bodies; the workspace
+                                 then holds horizon records of about 113 B per particle plus
+                                 2 x 1 KB per grid block) */
   int32_t requires_grad;     /* record checkpoints during mpm_step */
 } mpm_desc;
 

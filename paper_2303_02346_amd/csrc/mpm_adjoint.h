@@ -37,5 +37,9 @@ void launch_p2g_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom&
 // adjoint rows in sorted order (row j of particle id[j]) -> user order; pos:
 // N words of scratch
 void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, uint32_t* pos, hipStream_t s);
+// map[j] = the row of particle prev_id[j] in the order cur_id lists (pos: N
+// words of scratch); a map past N marks an id that is out of range
+void launch_row_map(const uint32_t* prev_id, const uint32_t* cur_id, int N, uint32_t* pos, uint32_t* map,
+                    hipStream_t s);
 
 }  // namespace mpm

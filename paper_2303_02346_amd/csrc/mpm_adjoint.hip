@@ -636,6 +636,20 @@ void launch_p2g_adj_tiled(const AdjArgs& A, const StepParams& P, const FastGeom&
   k_p2g_adj_tiled<256><<<n_wgs, 256, 0, s>>>(A, P, g);
   k_p2g_adj_redo<<<REDO_WGS, REDO_NT, 0, s>>>(A, P, g);
 }
+__global__ __launch_bounds__(256) void k_row_map(const uint32_t* __restrict__ prev_id, const uint32_t* __restrict__ pos,
+                                                 int N, uint32_t* __restrict__ map) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const uint32_t p = prev_id[j];
+  map[j] = p < (uint32_t)N ? pos[p] : 0xffffffffu;
+}
+
+void launch_row_map(const uint32_t* prev_id, const uint32_t* cur_id, int N, uint32_t* pos, uint32_t* map,
+                    hipStream_t s) {
+  k_adj_pos<<<nblk(N, 256), 256, 0, s>>>(cur_id, N, pos);
+  k_row_map<<<nblk(N, 256), 256, 0, s>>>(prev_id, pos, N, map);
+}
+
 void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, uint32_t* pos, hipStream_t s) {
   k_adj_pos<<<nblk(N, 256), 256, 0, s>>>(id, N, pos);
   k_adj_gather<<<nblk(N, 256), 256, 0, s>>>(in, out, pos, N);

@@ -77,7 +77,10 @@ bool desc_ok(const mpm_desc* d) {
   if (!d->cyl_radius || !d->cyl_pos0 || !d->cyl_rot0) return false;
   if (!(d->dt > 0.f) || d->horizon < 1 || d->bound < 0) return false;
   // (the tiled adjoint hands out 2 k + 1 step stamps per 16-bit epoch)
-  if (d->requires_grad && (d->ckpt_every < 1 || d->ckpt_every > 16384)) return false;
+  if (d->requires_grad && (d->ckpt_every < 0 || d->ckpt_every > 16384)) return false;
+  // (ckpt_every = 0, a record of every step, is the tiled adjoint's; rigid
+  // bodies need the checkpointed recompute)
+  if (d->requires_grad && d->ckpt_every == 0 && count_bodies(d) > 0) return false;
   if (d->scene_offsets) {
     if (d->scene_offsets[0] != 0 || d->scene_offsets[d->n_scenes] != d->n_particles) return false;
     for (int s = 0; s < d->n_scenes; s++)
@@ -108,8 +111,9 @@ Layout plan(const mpm_desc* d) {
   L.cstats = take(64);
   L.fast = take(fast_workspace_bytes(d->n_grid, (int)S, (int)N));
   if (d->requires_grad) {
-    int k = d->ckpt_every;
-    L.n_ckpt = (int)((T + k - 1) / k) + 1;
+    const int k = d->ckpt_every;
+    const bool keep_all = k == 0;   // a block-sorted record of every step, no recompute
+    L.n_ckpt = keep_all ? 1 : (int)((T + k - 1) / k) + 1;
     L.vbar = take(nodes * sizeof(float4));
     L.mmvb = take(nodes * sizeof(float4));
     L.acc = take(T * S * ACC_DOUBLES * sizeof(double));
@@ -119,7 +123,7 @@ Layout plan(const mpm_desc* d) {
     size_t n_keys = (size_t)fast_n_keys(d->n_grid, (int)S);
     L.rec = sorted_rec(N, n_keys, true);
     L.tmp_rec = sorted_rec(N, n_keys, false);
-    size_t plain_seg = st * (size_t)(k + 1), tiled_seg = L.rec.bytes * (size_t)k;
+    size_t plain_seg = keep_all ? 0 : st * (size_t)(k + 1), tiled_seg = L.rec.bytes * (size_t)(keep_all ? T : k);
     L.seg = take(plain_seg > tiled_seg ? plain_seg : tiled_seg);
     L.tmp = take(L.tmp_rec.bytes);
     L.mmvb_blk = take(n_keys * 64 * sizeof(float4));
@@ -134,7 +138,7 @@ Layout plan(const mpm_desc* d) {
     L.rec = L.tmp_rec = SortedRec{};
   }
   L.n_bodies = count_bodies(d);
-  L.n_rec = d->requires_grad ? d->ckpt_every : 1;
+  L.n_rec = (d->requires_grad && d->ckpt_every > 0) ? d->ckpt_every : 1;
   if (L.n_bodies > 0) {
     size_t B = L.n_bodies;
     L.r_rest = take(3 * N * sizeof(float));
@@ -440,6 +444,8 @@ static void rigid_tiled_run(mpm_ctx* c, const StepParams& P, const PState& us, i
   if (f.do_export) fast_export(f, P, tmp, us, s);
 }
 
+static int record_run(mpm_ctx* c, const StepParams& P, const PState& us, int t0, int n);
+
 int mpm_step(mpm_ctx* c, int32_t n_steps) {
   if (!c || n_steps < 0) return MPM_EINVAL;
   if (!c->has_state) return MPM_ESTATE;
@@ -463,6 +469,9 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
       }
       plain_step(c, P, us, us, t, 0);
     }
+  } else if (c->d.requires_grad && c->d.ckpt_every == 0) {
+    const int rc = record_run(c, P, us, c->t, n_steps);
+    if (rc != MPM_OK) return rc;
   } else if (c->d.requires_grad) {
     // tiled path in one call; the checkpoints inside it are written by the
     // call itself, the one at its start is copied here
@@ -511,6 +520,107 @@ static SortedState sorted_state(mpm_ctx* c, size_t base, bool tmp = false) {
 }
 static uint32_t* sorted_map(mpm_ctx* c, size_t base) { return (uint32_t*)(c->ws + base + c->L.rec.map); }
 
+// Forward with ckpt_every = 0: the steps t0 .. t0 + n - 1 of one call run as
+// the tiled adjoint's recompute does, each step's state kept as its record
+// (block-sorted, with its grid, claims and the row map to the next record),
+// so that the backward recomputes nothing.  The call imports the user state
+// into record t0 (and maps record t0 - 1, left by the previous call, onto
+// it), runs the P2G of step t0, one fused kernel per further step, and the
+// G2P of the last step, whose output it exports to the user arrays.
+static int record_run(mpm_ctx* c, const StepParams& P, const PState& us, int t0, int n) {
+  FastPath& f = c->fast;
+  hipStream_t s = c->stream;
+  const int N = c->d.n_particles;
+  const size_t rb = c->L.rec.bytes;
+  auto rec = [&](int t) { return sorted_state(c, c->L.seg + (size_t)t * rb); };
+  SortedState R0 = rec(t0);
+  fast_sort_user(f, P, us, R0, s, true);
+  if (t0 > 0) launch_row_map(rec(t0 - 1).b.id, R0.b.id, N, f.inv, sorted_map(c, c->L.seg + (size_t)(t0 - 1) * rb), s);
+  uint32_t sid = fast_next_sid(f);
+  fast_p2g(f, P, R0, sid, s);
+  if (n > 1) {
+    // the first fused step places its output by the import's offsets:
+    // record t0 + 1 keeps record t0's order and list
+    const SortedState R1 = rec(t0 + 1);
+    if (hipMemcpyAsync(R1.list, R0.list, (size_t)f.g.n_keys * sizeof(int4), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(R1.list_n, R0.list_n, sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return MPM_EHIP;
+  }
+  fast_grid_scan(f, P, R0, sid, t0, pose_at(c, 0), act_at(c, 0), n > 1 ? rec(t0 + 1).cl_count : nullptr, nullptr,
+                 nullptr, s);
+  for (int t = t0 + 1; t < t0 + n; t++) {
+    const SortedState Sp = rec(t - 1), Si = rec(t);
+    sid = fast_next_sid(f);
+    fast_fused(f, P, Sp, Si, sorted_map(c, c->L.seg + (size_t)(t - 1) * rb), sid, s);
+    const bool more = t + 1 < t0 + n;
+    SortedState Sn = more ? rec(t + 1) : SortedState{};
+    fast_grid_scan(f, P, Si, sid, t, pose_at(c, 0), act_at(c, 0), more ? Sn.cl_count : nullptr,
+                   more ? Sn.list : f.list[0], more ? Sn.list_n : f.list_n, s);
+  }
+  // G2P of the last step (in the order the latest scan gives), exported
+  const SortedState tmp = sorted_state(c, c->L.tmp, true);
+  fast_g2p(f, P, rec(t0 + n - 1), tmp.b, s);
+  fast_export(f, P, tmp.b, us, s);
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
+// The tiled adjoint of step t on its block-sorted record Si: the adjoint of
+// s_{t+1} (a_cur, read through `map`: Si's row -> s_{t+1}'s row) becomes
+// that of s_t (a_nxt, Si's rows); the pose partials of step t go to acc.
+// With rigid bodies, rrec is the step's projection record.  Swaps a_cur and
+// a_nxt.
+static void adjoint_step(mpm_ctx* c, const StepParams& P, const SortedState& Si, const uint32_t* map, int t,
+                         double* rrec, PState& a_cur, PState& a_nxt, double* acc) {
+  FastPath& f = c->fast;
+  const int N = c->d.n_particles;
+  hipStream_t s = c->stream;
+  AdjArgs A;
+  A.st = Si.b;
+  A.list = Si.list;
+  A.list_n = Si.list_n;
+  A.N = N;
+  A.abar_next = a_cur.x;
+  A.map = map;
+  A.abar = a_nxt.x;
+  A.vgrid = Si.vgrid;
+  A.tiles = f.tiles;
+  A.tile_box = f.tile_box;
+  A.gen = f.gen;
+  A.sid = fast_next_sid(f);
+  A.cl_list = Si.cl_list;
+  A.cl_count = Si.cl_count;
+  A.mmv = Si.mmv;
+  A.mmvb = G(c, c->L.mmvb_blk);
+  A.redo = (uint2*)(c->ws + c->L.redo);
+  A.redo_n = (uint32_t*)(c->ws + c->L.redo_n) + 2 * t;
+  // the adjoint of the rigid projection turns the body rows of the adjoint
+  // of s_{t+1} into the adjoint of the G2P output
+  if (rrec)
+    rigid_adjoint(c->rigid, P, RigidRows{packed_state(Si.b.f, N), Si.b.mat, Si.b.id}, A.map, a_cur.x, rrec, Si.vgrid,
+                  &f.g, s);
+  launch_g2p_adj_tiled(A, P, f.g, f.part_wgs, s);
+  launch_grid_adj_tiled(A, P, f.g, f.grid_wgs, pose_at(c, t), act_at(c, t), acc + (size_t)t * c->d.n_scenes * ACC_DOUBLES,
+                        s);
+  A.redo_n += 1;
+  launch_p2g_adj_tiled(A, P, f.g, f.part_wgs, s);
+  PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
+}
+
+// With ckpt_every = 0 the forward keeps a record of every step (see
+// record_run), so the adjoint walks them all without recomputing anything.
+static int backward_records(mpm_ctx* c, const StepParams& P, PState& a_cur, PState& a_nxt, double* acc) {
+  const int N = c->d.n_particles, T = c->t;
+  const size_t rb = c->L.rec.bytes;
+  for (int t = T - 1; t >= 0; t--) {
+    const size_t bi = c->L.seg + (size_t)t * rb;
+    const SortedState Si = sorted_state(c, bi);
+    adjoint_step(c, P, Si, (t == T - 1) ? Si.b.id : sorted_map(c, bi), t, nullptr, a_cur, a_nxt, acc);
+  }
+  launch_adj_reorder(a_cur.x, a_nxt.x, sorted_state(c, c->L.seg).b.id, N, c->fast.inv, c->stream);
+  PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
 // Tiled adjoint over all segments, last first.  On entry a_cur holds the
 // adjoint of the final state in user order; on return it holds the adjoint
 // of the initial state in user order (a_cur / a_nxt swapped as needed).
@@ -520,7 +630,6 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
   hipStream_t s = c->stream;
   const size_t rb = c->L.rec.bytes;
   SortedState tmp = sorted_state(c, c->L.tmp, true);
-  float4* mmvb_blk = G(c, c->L.mmvb_blk);
   const bool rigid = c->rigid.n_bodies > 0;
   const RigidRows trows{packed_state(tmp.b.f, N), tmp.b.mat, tmp.b.id};
   const int n_seg = (T + k - 1) / k;
@@ -578,37 +687,9 @@ static int backward_tiled(mpm_ctx* c, const StepParams& P, PState& a_cur, PState
     // read through s_{te-1}'s ids, the later ones through the recorded maps
     for (int t = te - 1; t >= ts; t--) {
       const size_t bi = c->L.seg + (size_t)(t - ts) * rb;
-      SortedState Si = rec(t);
-      AdjArgs A;
-      A.st = Si.b;
-      A.list = Si.list;
-      A.list_n = Si.list_n;
-      A.N = N;
-      A.abar_next = a_cur.x;
-      A.map = (t == te - 1) ? Si.b.id : sorted_map(c, bi);
-      A.abar = a_nxt.x;
-      A.vgrid = Si.vgrid;
-      A.tiles = f.tiles;
-      A.tile_box = f.tile_box;
-      A.gen = f.gen;
-      A.sid = fast_next_sid(f);
-      A.cl_list = Si.cl_list;
-      A.cl_count = Si.cl_count;
-      A.mmv = Si.mmv;
-      A.mmvb = mmvb_blk;
-      A.redo = (uint2*)(c->ws + c->L.redo);
-      A.redo_n = (uint32_t*)(c->ws + c->L.redo_n) + 2 * t;
-      // the adjoint of the rigid projection turns the body rows of the
-      // adjoint of s_{t+1} into the adjoint of the G2P output
-      if (rigid)
-        rigid_adjoint(c->rigid, P, RigidRows{packed_state(Si.b.f, N), Si.b.mat, Si.b.id}, A.map, a_cur.x,
-                      rigid_rec(c, t - ts), Si.vgrid, &f.g, s);
-      launch_g2p_adj_tiled(A, P, f.g, f.part_wgs, s);
-      launch_grid_adj_tiled(A, P, f.g, f.grid_wgs, pose_at(c, t), act_at(c, t),
-                            acc + (size_t)t * c->d.n_scenes * ACC_DOUBLES, s);
-      A.redo_n += 1;
-      launch_p2g_adj_tiled(A, P, f.g, f.part_wgs, s);
-      PState tsw = a_cur; a_cur = a_nxt; a_nxt = tsw;
+      const SortedState Si = rec(t);
+      adjoint_step(c, P, Si, (t == te - 1) ? Si.b.id : sorted_map(c, bi), t, rigid ? rigid_rec(c, t - ts) : nullptr,
+                   a_cur, a_nxt, acc);
     }
     // back to user order for the previous segment
     launch_adj_reorder(a_cur.x, a_nxt.x, S0.b.id, N, f.inv, s);   // (the import's map is free here)
@@ -638,10 +719,10 @@ static int enqueue_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_act
   if (grad_T->J && hipMemcpyAsync(a_cur.J, grad_T->J, fN, hipMemcpyDeviceToDevice, s) != hipSuccess) return MPM_EHIP;
   double* acc = (double*)(c->ws + c->L.acc);
   launch_zero(acc, align_up((size_t)T * S * ACC_DOUBLES * sizeof(double)), s);
-  int n_seg = (T + k - 1) / k;
+  int n_seg = k > 0 ? (T + k - 1) / k : 0;
   if (!c->plain_adjoint) {
     launch_zero(c->ws + c->L.redo_n, align_up(2 * (size_t)T * sizeof(uint32_t)), s);
-    int rc = backward_tiled(c, P, a_cur, a_nxt, acc);
+    int rc = k > 0 ? backward_tiled(c, P, a_cur, a_nxt, acc) : backward_records(c, P, a_cur, a_nxt, acc);
     if (rc != MPM_OK) return rc;
     n_seg = 0;
   }
@@ -780,6 +861,7 @@ int mpm_set_option(mpm_ctx* c, int32_t key, int32_t value) {
       return MPM_OK;
     case MPM_OPT_ADJOINT:
       if (value != 0 && value != 1) return MPM_EINVAL;
+      if (value == 1 && c->d.requires_grad && c->d.ckpt_every == 0) return MPM_EINVAL;   // (records are tiled)
       c->plain_adjoint = value == 1;
       return MPM_OK;
     case MPM_OPT_SHARE_CHUNKS:

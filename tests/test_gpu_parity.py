@@ -440,3 +440,33 @@ def test_long_horizon_pose_chunks_vs_oracle(adjoint):
     say(f"  loss gpu {loss.item():.8f} ref {L.item():.8f}; grad rel err {e:.2e}")
     assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
     assert e <= 3e-4   # (1.0e-4 measured: FP32 over 300 steps)
+
+
+def test_records_of_every_step_vs_oracle():
+    """ckpt_every = 0: the forward keeps a block-sorted record of every step
+    and the backward recomputes nothing.  The rollout runs in three calls
+    (3 + 1 + 4 steps), so that the row maps across call boundaries are used;
+    loss, action gradient and dL/d(x0, v0) against the oracle, and the plain
+    adjoint is refused for such a context."""
+    sc = scenes.tiny(n_particles=90, n_grid=16, steps=8, seed=1)
+    say("records of every step: 8 steps in calls of 3, 1 and 4")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=0)
+    for n in (3, 1, 4):
+        sim.step(n)
+    loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
+    ga, g0 = sim.backward(g[0:3], torch.zeros_like(g[0:3]), want_grad0=True)
+    ga = ga[:, 0].double().cpu().numpy()
+    p = O.params_from_scene(sc)
+    st0 = O.state_from_scene(sc, requires_grad=True)
+    acts = torch.tensor(sc.actions, dtype=torch.float64, requires_grad=True)
+    st = O.rollout(sc, state=st0, params=p, actions=acts)
+    L = O.blob_loss(st["x"], p.kind == O.LIQUID, torch.tensor(sc.target_mu, dtype=torch.float64), sc.target_sigma)
+    L.backward()
+    ea = rel(ga, acts.grad.numpy())
+    ex = rel(g0[0:3].T.double().cpu().numpy(), st0["x"].grad.numpy())
+    ev = rel(g0[3:6].T.double().cpu().numpy(), st0["v"].grad.numpy())
+    say(f"  loss gpu {loss.item():.8f} ref {L.item():.8f}; actions {ea:.2e} dL/dx0 {ex:.2e} dL/dv0 {ev:.2e}")
+    assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
+    assert ea <= 1e-4 and ex <= 1e-4 and ev <= 1e-4
+    with pytest.raises(RuntimeError):
+        sim.set_option(_lib.MPM_OPT_ADJOINT, 1)
