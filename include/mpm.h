@@ -283,7 +283,9 @@ int mpm_autotune(mpm_ctx* c, int32_t n_steps, int32_t* best);
  * records of 9 floats (log sigma_tr[3], alpha, c, kappa, projected[3]) are
  * appended to buf_dev (capacity records) and *count_dev (device uint64) is
  * advanced (it may exceed the capacity; records beyond it are dropped).
- * buf_dev == NULL stops logging.  Not combined with an active closure. */
+ * buf_dev == NULL stops logging.  Returns MPM_ESTATE with an active closure,
+ * with rigid bodies, and in a requires_grad context with ckpt_every == 0
+ * (that context's forward keeps each step's record and runs no logging). */
 int mpm_log_samples(mpm_ctx* c, float* buf_dev, uint64_t capacity, uint64_t* count_dev);
 
 /* Use the trained MLP (mlp_state_dev; NULL disables) for the cone case of

@@ -975,6 +975,8 @@ int mpm_log_samples(mpm_ctx* c, float* buf_dev, uint64_t capacity, uint64_t* cou
   if (!c) return MPM_EINVAL;
   if (buf_dev && (!count_dev || capacity == 0)) return MPM_EINVAL;
   if (buf_dev && (c->fast.mlp_blob || c->rigid.n_bodies > 0)) return MPM_ESTATE;
+  // (a context that keeps every step's record runs its forward without the logging kernel)
+  if (buf_dev && c->d.requires_grad && c->d.ckpt_every == 0) return MPM_ESTATE;
   c->fast.log_buf = buf_dev;
   c->fast.log_count = (unsigned long long*)count_dev;
   c->fast.log_cap = buf_dev ? capacity : 0;

@@ -447,7 +447,7 @@ def test_records_of_every_step_vs_oracle():
     and the backward recomputes nothing.  The rollout runs in three calls
     (3 + 1 + 4 steps), so that the row maps across call boundaries are used;
     loss, action gradient and dL/d(x0, v0) against the oracle, and the plain
-    adjoint is refused for such a context."""
+    adjoint and sample logging are refused for such a context."""
     sc = scenes.tiny(n_particles=90, n_grid=16, steps=8, seed=1)
     say("records of every step: 8 steps in calls of 3, 1 and 4")
     sim = sim_of(sc, requires_grad=True, ckpt_every=0)
@@ -470,3 +470,8 @@ def test_records_of_every_step_vs_oracle():
     assert ea <= 1e-4 and ex <= 1e-4 and ev <= 1e-4
     with pytest.raises(RuntimeError):
         sim.set_option(_lib.MPM_OPT_ADJOINT, 1)
+    buf = torch.zeros(16, 9, dtype=torch.float32, device=sim.device)
+    count = torch.zeros(1, dtype=torch.int64, device=sim.device)
+    with pytest.raises(_lib.MpmError) as e:
+        sim.log_samples(buf, count)
+    assert e.value.status == _lib.MPM_ESTATE
