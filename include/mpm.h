@@ -229,7 +229,8 @@ int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name,
  * both the forward and the adjoint).  Both record the same checkpoints. */
 enum {
   MPM_OPT_GRAPH = 1,          /* 1: capture each call shape in a HIP graph and replay it (forward calls
-                                 without rigid bodies; tiled backward calls without rigid bodies) */
+                                 without rigid bodies, including those that keep every step's record;
+                                 tiled backward calls without rigid bodies) */
   MPM_OPT_PART_THREADS = 2,   /* 128, 256 or 512 threads per particle workgroup */
   MPM_OPT_PART_WGS = 3,       /* particle workgroups per launch (persistent, 64..65536) */
   MPM_OPT_GRID_WGS = 4,       /* grid-update workgroups per launch (64..65536) */

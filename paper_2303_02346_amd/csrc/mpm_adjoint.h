@@ -41,5 +41,8 @@ void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, 
 // words of scratch); a map past N marks an id that is out of range
 void launch_row_map(const uint32_t* prev_id, const uint32_t* cur_id, int N, uint32_t* pos, uint32_t* map,
                     hipStream_t s);
+// dst[0 .. n) = src[0 .. n) and *dst_n = n, for n = *src_n (a block list and
+// its length; dst holds as many rows as src)
+void launch_copy_list(const int4* src, const uint32_t* src_n, int4* dst, uint32_t* dst_n, hipStream_t s);
 
 }  // namespace mpm

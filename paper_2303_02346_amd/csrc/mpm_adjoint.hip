@@ -650,6 +650,17 @@ void launch_row_map(const uint32_t* prev_id, const uint32_t* cur_id, int N, uint
   k_row_map<<<nblk(N, 256), 256, 0, s>>>(prev_id, pos, N, map);
 }
 
+__global__ __launch_bounds__(256) void k_copy_list(const int4* __restrict__ src, const uint32_t* __restrict__ src_n,
+                                                   int4* __restrict__ dst, uint32_t* __restrict__ dst_n) {
+  const uint32_t n = src_n[0];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) dst_n[0] = n;
+}
+
+void launch_copy_list(const int4* src, const uint32_t* src_n, int4* dst, uint32_t* dst_n, hipStream_t s) {
+  k_copy_list<<<16, 256, 0, s>>>(src, src_n, dst, dst_n);
+}
+
 void launch_adj_reorder(const float* in, float* out, const uint32_t* id, int N, uint32_t* pos, hipStream_t s) {
   k_adj_pos<<<nblk(N, 256), 256, 0, s>>>(id, N, pos);
   k_adj_gather<<<nblk(N, 256), 256, 0, s>>>(in, out, pos, N);

@@ -175,23 +175,68 @@ struct mpm_ctx {
   KernelTimer timer;
   bool plain_adjoint;
   RigidCtx rigid;           // n_bodies = 0: no rigid bodies
-  // captured backward calls (tiled adjoint without rigid bodies, graph mode),
-  // keyed by the horizon, the gradient pointers and the launch shape
-  struct BwdGraph {
+  // captured calls (graph mode), keyed by their start, steps, pointers and
+  // launch shape: the tiled backward without rigid bodies (bgraphs: the
+  // horizon and the gradient pointers) and the forward of a context that
+  // keeps every step's record (rgraphs: start, steps and state pointers)
+  struct CallGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int T = 0, part_wgs = 0, grid_wgs = 0;
+    int t0 = 0, n = 0, part_wgs = 0, grid_wgs = 0;
     const void* ptr[11] = {};
     unsigned long long n_ep = 0;   // stamp epochs one call advances
   };
-  std::vector<BwdGraph> bgraphs;
+  std::vector<CallGraph> bgraphs, rgraphs;
 };
 
-static void destroy_bwd_graph(mpm_ctx::BwdGraph& G) {
+static void destroy_call_graph(mpm_ctx::CallGraph& G) {
   if (G.exec) hipGraphExecDestroy(G.exec);
   if (G.graph) hipGraphDestroy(G.graph);
   G.exec = nullptr;
   G.graph = nullptr;
+}
+
+// Run the work that enq() puts on the context's stream as a graph: captured
+// the first time `key` is seen (the newest 4 kept in `cache`), replayed
+// after.  The captured sorts advance the device epoch of the step stamps; the
+// host keeps its count in step, clearing the stamps before a replay that
+// crosses the epoch's 16-bit wrap.
+template <class Enq>
+static int graph_call(mpm_ctx* c, std::vector<mpm_ctx::CallGraph>& cache, const mpm_ctx::CallGraph& key, Enq enq) {
+  FastPath& f = c->fast;
+  hipStream_t s = c->stream;
+  mpm_ctx::CallGraph* G = nullptr;
+  for (auto& g : cache) {
+    bool same = g.exec && g.t0 == key.t0 && g.n == key.n && g.part_wgs == key.part_wgs && g.grid_wgs == key.grid_wgs;
+    for (int q = 0; q < 11 && same; q++) same = g.ptr[q] == key.ptr[q];
+    if (same) G = &g;
+  }
+  if (!G) {
+    mpm_ctx::CallGraph g = key;
+    g.graph = nullptr;
+    g.exec = nullptr;
+    const unsigned long long calls0 = f.calls;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_EHIP;
+    const int rc = enq();
+    const hipError_t ec = hipStreamEndCapture(s, &g.graph);
+    if (rc != MPM_OK || ec != hipSuccess || hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) {
+      f.calls = calls0;   // nothing of the capture ran
+      destroy_call_graph(g);
+      return rc != MPM_OK ? rc : MPM_EHIP;
+    }
+    g.n_ep = f.calls - calls0;
+    if (cache.size() >= 4) { destroy_call_graph(cache.front()); cache.erase(cache.begin()); }
+    cache.push_back(g);
+    G = &cache.back();
+  } else {
+    if ((f.calls & 0xffffull) + G->n_ep >= 0x10000ull) {
+      launch_zero(f.claim, (size_t)f.g.n_keys * 4, s);
+      launch_zero(f.tile_box, (size_t)f.g.n_keys * NSUB * 8, s);
+    }
+    f.calls += G->n_ep;
+  }
+  if (hipGraphLaunch(G->exec, s) != hipSuccess) return MPM_EHIP;
+  return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
 }
 
 // Projection record slot i of the rigid bodies.
@@ -470,7 +515,21 @@ int mpm_step(mpm_ctx* c, int32_t n_steps) {
       plain_step(c, P, us, us, t, 0);
     }
   } else if (c->d.requires_grad && c->d.ckpt_every == 0) {
-    const int rc = record_run(c, P, us, c->t, n_steps);
+    // (graph mode: captured once per start, steps, state pointers and launch shape)
+    int rc;
+    if (c->fast.use_graph && !c->timer.on) {
+      mpm_ctx::CallGraph key;
+      key.t0 = c->t;
+      key.n = n_steps;
+      key.part_wgs = c->fast.part_wgs;
+      key.grid_wgs = c->fast.grid_wgs;
+      const void* ptr[6] = {us.x, us.v, us.C, us.F, us.J, P.mat};
+      for (int q = 0; q < 6; q++) key.ptr[q] = ptr[q];
+      const int t0 = c->t;
+      rc = graph_call(c, c->rgraphs, key, [&] { return record_run(c, P, us, t0, n_steps); });
+    } else {
+      rc = record_run(c, P, us, c->t, n_steps);
+    }
     if (rc != MPM_OK) return rc;
   } else if (c->d.requires_grad) {
     // tiled path in one call; the checkpoints inside it are written by the
@@ -542,9 +601,7 @@ static int record_run(mpm_ctx* c, const StepParams& P, const PState& us, int t0,
     // the first fused step places its output by the import's offsets:
     // record t0 + 1 keeps record t0's order and list
     const SortedState R1 = rec(t0 + 1);
-    if (hipMemcpyAsync(R1.list, R0.list, (size_t)f.g.n_keys * sizeof(int4), hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(R1.list_n, R0.list_n, sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
-      return MPM_EHIP;
+    launch_copy_list(R0.list, R0.list_n, R1.list, R1.list_n, s);
   }
   fast_grid_scan(f, P, R0, sid, t0, pose_at(c, 0), act_at(c, 0), n > 1 ? rec(t0 + 1).cl_count : nullptr, nullptr,
                  nullptr, s);
@@ -770,47 +827,19 @@ int mpm_step_backward(mpm_ctx* c, const mpm_state* grad_T, float* grad_actions_d
   if (grad_0 && (!grad_0->x || !grad_0->v || !grad_0->C || !grad_0->F || !grad_0->J)) return MPM_EINVAL;
   c->fast.last_buf = -1;   // the recompute reuses the forward's buffers
   FastPath& f = c->fast;
-  // Graph mode: the tiled backward (without rigid bodies, whose steps run
-  // eagerly) is captured once per horizon, gradient pointers and launch
-  // shape, then replayed.  The captured sorts advance the device epoch of
-  // the step stamps; the host keeps its count in step, clearing the stamps
-  // before a replay that crosses the epoch's 16-bit wrap.
+  // graph mode: the tiled backward (without rigid bodies, whose steps run
+  // eagerly) is captured once per horizon, gradient pointers and launch shape
   if (f.use_graph && !c->plain_adjoint && c->rigid.n_bodies == 0) {
-    const void* key[11] = {grad_T->x, grad_T->v, grad_T->C, grad_T->F, grad_T->J, grad_actions_dev,
+    mpm_ctx::CallGraph key;
+    key.n = c->t;
+    key.part_wgs = f.part_wgs;
+    key.grid_wgs = f.grid_wgs;
+    const void* ptr[11] = {grad_T->x, grad_T->v, grad_T->C, grad_T->F, grad_T->J, grad_actions_dev,
                            grad_0 ? grad_0->x : nullptr, grad_0 ? grad_0->v : nullptr, grad_0 ? grad_0->C : nullptr,
                            grad_0 ? grad_0->F : nullptr, grad_0 ? grad_0->J : nullptr};
-    mpm_ctx::BwdGraph* G = nullptr;
-    for (auto& g : c->bgraphs) {
-      bool same = g.exec && g.T == c->t && g.part_wgs == f.part_wgs && g.grid_wgs == f.grid_wgs;
-      for (int q = 0; q < 11 && same; q++) same = g.ptr[q] == key[q];
-      if (same) G = &g;
-    }
-    hipStream_t s = c->stream;
-    if (!G) {
-      mpm_ctx::BwdGraph g;
-      g.T = c->t;
-      g.part_wgs = f.part_wgs;
-      g.grid_wgs = f.grid_wgs;
-      for (int q = 0; q < 11; q++) g.ptr[q] = key[q];
-      const unsigned long long calls0 = f.calls;
-      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_EHIP;
-      const int rc = enqueue_backward(c, grad_T, grad_actions_dev, grad_0);
-      const hipError_t ec = hipStreamEndCapture(s, &g.graph);
-      if (rc != MPM_OK || ec != hipSuccess) { destroy_bwd_graph(g); return rc != MPM_OK ? rc : MPM_EHIP; }
-      if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) { destroy_bwd_graph(g); return MPM_EHIP; }
-      g.n_ep = f.calls - calls0;
-      if (c->bgraphs.size() >= 4) { destroy_bwd_graph(c->bgraphs.front()); c->bgraphs.erase(c->bgraphs.begin()); }
-      c->bgraphs.push_back(g);
-      G = &c->bgraphs.back();
-    } else {
-      if ((f.calls & 0xffffull) + G->n_ep >= 0x10000ull) {
-        launch_zero(f.claim, (size_t)f.g.n_keys * 4, s);
-        launch_zero(f.tile_box, (size_t)f.g.n_keys * NSUB * 8, s);
-      }
-      f.calls += G->n_ep;
-    }
-    if (hipGraphLaunch(G->exec, s) != hipSuccess) return MPM_EHIP;
-    if (hipGetLastError() != hipSuccess) return MPM_EHIP;
+    for (int q = 0; q < 11; q++) key.ptr[q] = ptr[q];
+    const int rc = graph_call(c, c->bgraphs, key, [&] { return enqueue_backward(c, grad_T, grad_actions_dev, grad_0); });
+    if (rc != MPM_OK) return rc;
     return finish(c);
   }
   const int rc = enqueue_backward(c, grad_T, grad_actions_dev, grad_0);
@@ -1026,7 +1055,8 @@ int mpm_timing_read(mpm_ctx* c, double* total_ms, int64_t* launches, char* name,
 
 int mpm_destroy(mpm_ctx* c) {
   if (!c) return MPM_EINVAL;
-  for (auto& g : c->bgraphs) destroy_bwd_graph(g);
+  for (auto& g : c->bgraphs) destroy_call_graph(g);
+  for (auto& g : c->rgraphs) destroy_call_graph(g);
   c->timer.destroy();
   fast_destroy(c->fast);
   delete c;

@@ -32,13 +32,14 @@ def sim_of(sc, **kw):
     return Simulator(sc, **kw)
 
 
-@pytest.mark.parametrize("adjoint", ["tiled", "plain"])
-def test_config3_gradient_vs_oracle(adjoint):
+@pytest.mark.parametrize("adjoint,ckpt", [("tiled", 16), ("plain", 16), ("tiled", 0)])
+def test_config3_gradient_vs_oracle(adjoint, ckpt):
+    """ckpt = 0 keeps a record of every step and recomputes nothing."""
     with open(GOLDEN) as f:
         gold = json.load(f)
     sc = scenes.config3()
-    say(f"config 3 gradient (100k particles, 64 steps, checkpoint 16), {adjoint} adjoint")
-    sim = sim_of(sc, requires_grad=True, ckpt_every=16, adjoint=adjoint)
+    say(f"config 3 gradient (100k particles, 64 steps, checkpoint {ckpt}), {adjoint} adjoint")
+    sim = sim_of(sc, requires_grad=True, ckpt_every=ckpt, adjoint=adjoint)
     sim.step(64)
     loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
     ga = sim.backward(g[0:3], torch.zeros_like(g[0:3]))[:, 0].double().cpu().numpy()
@@ -153,20 +154,25 @@ def test_config3_gradient_vs_oracle_fd():
         assert abs(ana - item["fd"]) <= 1e-2 * abs(item["fd"]) + 1e-3 * float(np.abs(ga).sum()) * 1e-3
 
 
-def test_backward_graph_replays_match_eager():
-    """Graph mode captures the checkpointed forward call and the tiled
-    backward once per horizon and gradient pointers and replays them: three
-    replays (with the loss and eager work between them, and a changed seed
-    gradient each time) give the eager forward's loss and backward's
-    gradients."""
+@pytest.mark.parametrize("ckpt,calls", [(5, (12,)), (0, (5, 7))])
+def test_backward_graph_replays_match_eager(ckpt, calls):
+    """Graph mode captures the forward calls (checkpointed, or keeping every
+    step's record with ckpt = 0, there in two calls) and the tiled backward
+    once per call shape and pointers and replays them: three replays (with
+    the loss and eager work between them, and a changed seed gradient each
+    time) give the eager forward's positions and loss and the eager
+    backward's gradients."""
     sc = scenes.tiny(n_particles=1500, n_grid=24, steps=12, seed=3)
-    eager = sim_of(sc, requires_grad=True, ckpt_every=5)
-    graph = sim_of(sc, requires_grad=True, ckpt_every=5, graph=True)
+    eager = sim_of(sc, requires_grad=True, ckpt_every=ckpt)
+    graph = sim_of(sc, requires_grad=True, ckpt_every=ckpt, graph=True)
     for rep in range(3):
         outs = []
+        xs = []
         for sim in (eager, graph):
             sim.reset()
-            sim.step(sc.horizon)
+            for n in calls:
+                sim.step(n)
+            xs.append(sim.positions())
             loss, g = sim.loss_blob(sc.target_mu, sc.target_sigma)
             gx = g[0:3] * (1.0 + rep)   # (the simulator copies it into its persistent seed buffer)
             ga, g0 = sim.backward(gx, torch.zeros_like(gx), want_grad0=True)
@@ -174,5 +180,6 @@ def test_backward_graph_replays_match_eager():
             outs.append((ga.double().cpu().numpy(), g0.double().cpu().numpy()))
         ea = rel(outs[1][0], outs[0][0])
         e0 = rel(outs[1][1], outs[0][1])
-        say(f"  replay {rep}: graph vs eager, actions {ea:.2e}, state_0 {e0:.2e}")
-        assert ea <= 1e-6 and e0 <= 1e-6
+        ex = float(np.abs(xs[1] - xs[0]).max())
+        say(f"  replay {rep}: graph vs eager, positions {ex:.1e} (max abs), actions {ea:.2e}, state_0 {e0:.2e}")
+        assert ex <= 1e-6 and ea <= 1e-6 and e0 <= 1e-6
