@@ -73,63 +73,95 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
 
 // Exclusive scan of the counts of the touched keys -> their offsets, the
 // list of occupied keys {key, offset, count, sub}, and the counts and the
-// touched counter cleared.  Run by one workgroup of NT threads.  The blocks
-// follow the order in which their keys were first touched; only contiguity
-// matters.  With split_nt > 0 a block of more than max_chunks chunks of
-// split_nt particles is listed twice, sub 0 with the first ceil(chunks / 2)
-// chunks and sub 1 with the rest, so that two workgroups share it (each
-// publishes its own tile slot).
+// touched counter cleared.  Run by one workgroup of NT threads.  The
+// particles of the blocks follow the order in which their keys were first
+// touched; only contiguity matters.  With split_nt > 0 a block of more than
+// max_chunks chunks of split_nt particles is listed twice, sub 0 with the
+// first ceil(chunks / 2) chunks and sub 1 with the rest, so that two
+// workgroups share it (each publishes its own tile slot).  Entries of two or
+// more chunks (of split_nt particles, else of order_nt; none if both are 0)
+// are listed before those of one: the particle kernels' workgroups are
+// dispatched round-robin over the CUs, so each CU then receives about as
+// many chunks as the others, the longest first.
 template <int NT>
 __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
                              const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                              int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys, int stride = 1,
-                             int split_nt = 0, int max_chunks = 2) {
+                             int split_nt = 0, int max_chunks = 2, int order_nt = 0) {
   constexpr int NW = NT / 64;
-  __shared__ uint32_t s_sum[NW], s_sp[NW];
-  __shared__ uint32_t s_run, s_runsp;
+  __shared__ uint32_t s_sum[NW], s_big[NW], s_sm[NW];
+  __shared__ uint32_t s_run, s_runbig, s_runsm, s_nbig;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const uint32_t n = min(n_touched[0], (uint32_t)n_keys);
-  if (t == 0) { s_run = 0; s_runsp = 0; }
+  // the entries of a key with c particles: their chunk counts and classes
+  const uint32_t cs = (uint32_t)(split_nt > 0 ? split_nt : order_nt);
+  auto entries = [&](uint32_t c, bool valid, uint32_t& sp, uint32_t& ch0, bool& big0, bool& big1) {
+    const uint32_t nch = cs > 0 ? (c + cs - 1) / cs : 0u;
+    sp = (valid && split_nt > 0 && nch > (uint32_t)max_chunks) ? 1u : 0u;
+    ch0 = sp ? (nch + 1) / 2 : nch;
+    big0 = valid && ch0 >= 2u;
+    big1 = sp && (nch - ch0) >= 2u;
+  };
+  if (t == 0) { s_run = 0; s_runbig = 0; s_runsm = 0; s_nbig = 0; }
   __syncthreads();
+  if (cs > 0) {
+    // first pass: the number of entries of two or more chunks
+    uint32_t nb = 0;
+    for (uint32_t i = t; i < n; i += NT) {
+      uint32_t sp, ch0;
+      bool b0, b1;
+      entries(counts[(size_t)touched[i] * stride], true, sp, ch0, b0, b1);
+      nb += (b0 ? 1u : 0u) + (b1 ? 1u : 0u);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nb += __shfl_xor(nb, off);
+    if (lane == 0 && nb) atomicAdd(&s_nbig, nb);
+    __syncthreads();
+  }
+  const uint32_t nbig = s_nbig;
   for (uint32_t c0 = 0; c0 < n; c0 += NT) {
     const uint32_t i = c0 + t;
     uint32_t key = 0, c = 0;
     if (i < n) { key = touched[i]; c = counts[(size_t)key * stride]; }
-    const uint32_t nch = split_nt > 0 ? (c + (uint32_t)split_nt - 1) / (uint32_t)split_nt : 0u;
-    const uint32_t sp = nch > (uint32_t)max_chunks ? 1u : 0u;
-    uint32_t is = c, isp = sp;
+    uint32_t sp, ch0;
+    bool big0, big1;
+    entries(c, i < n, sp, ch0, big0, big1);
+    const uint32_t eb = (big0 ? 1u : 0u) + (big1 ? 1u : 0u);
+    const uint32_t es = (i < n ? 1u : 0u) + sp - eb;
+    uint32_t is = c, ib = eb, ism = es;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t o = __shfl_up(is, off), o2 = __shfl_up(isp, off);
-      if (lane >= off) { is += o; isp += o2; }
+      const uint32_t o = __shfl_up(is, off), o2 = __shfl_up(ib, off), o3 = __shfl_up(ism, off);
+      if (lane >= off) { is += o; ib += o2; ism += o3; }
     }
-    if (lane == 63) { s_sum[wv] = is; s_sp[wv] = isp; }
+    if (lane == 63) { s_sum[wv] = is; s_big[wv] = ib; s_sm[wv] = ism; }
     __syncthreads();
-    uint32_t woff = s_run, tot = s_run, wsp = s_runsp, totsp = s_runsp;
+    uint32_t woff = s_run, tot = s_run, wb = s_runbig, totb = s_runbig, wsm = s_runsm, totsm = s_runsm;
 #pragma unroll
     for (int q = 0; q < NW; q++) {
-      if (q < wv) { woff += s_sum[q]; wsp += s_sp[q]; }
+      if (q < wv) { woff += s_sum[q]; wb += s_big[q]; wsm += s_sm[q]; }
       tot += s_sum[q];
-      totsp += s_sp[q];
+      totb += s_big[q];
+      totsm += s_sm[q];
     }
     if (i < n) {
       const uint32_t o = woff + is - c;
-      const uint32_t li = i + wsp + isp - sp;
+      uint32_t pb = wb + ib - eb, ps = nbig + wsm + ism - es;
       offsets[key] = o;
       counts[(size_t)key * stride] = 0u;
       if (sp) {
-        const uint32_t c1 = ((nch + 1) / 2) * (uint32_t)split_nt;
-        list[li] = make_int4((int)key, (int)o, (int)c1, 0);
-        list[li + 1] = make_int4((int)key, (int)(o + c1), (int)(c - c1), 1);
+        const uint32_t c1 = ch0 * (uint32_t)split_nt;
+        list[big0 ? pb++ : ps++] = make_int4((int)key, (int)o, (int)c1, 0);
+        list[big1 ? pb : ps] = make_int4((int)key, (int)(o + c1), (int)(c - c1), 1);
       } else {
-        list[li] = make_int4((int)key, (int)o, (int)c, 0);
+        list[big0 ? pb : ps] = make_int4((int)key, (int)o, (int)c, 0);
       }
     }
     __syncthreads();
-    if (t == 0) { s_run = tot; s_runsp = totsp; }
+    if (t == 0) { s_run = tot; s_runbig = totb; s_runsm = totsm; }
     __syncthreads();
   }
-  if (t == 0) { list_n[0] = n + s_runsp; n_touched[0] = 0u; }
+  if (t == 0) { list_n[0] = s_runbig + s_runsm; n_touched[0] = 0u; }
 }
 
 // Dense variant: exclusive scan of all counts -> offsets, the list of
@@ -246,13 +278,14 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, ui
                                                const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
                                                uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count,
-                                               int mode, int stride, int split_nt, int max_chunks) {
+                                               int mode, int stride, int split_nt, int max_chunks, int order_nt) {
   constexpr int NT = 1024;
   if (mode == SCAN_DENSE) {
     scan_keys<NT>(counts, offsets, list, list_n, n_keys, stride);
     if (threadIdx.x == 0) n_touched[0] = 0u;
   } else {
-    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride, split_nt, max_chunks);
+    scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride, split_nt, max_chunks,
+                       order_nt);
   }
   if (threadIdx.x == 0) { epoch[0] = epoch[0] + 1; cl_count[0] = 0u; cl_count[1] = 0u; }
 }
@@ -891,6 +924,7 @@ struct ScanArgs {
   int n_keys;
   int split_nt;     // particles per chunk of the particle kernel that reads the list (0: no sharing)
   int max_chunks;   // chunks above which a block is shared by two workgroups
+  int order_nt;     // chunk size that orders the entries when split_nt is 0 (0: first-touch order)
 };
 
 // With do_scan, workgroup 0 scans the key counts of this step's particle
@@ -904,7 +938,7 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
                                               int do_scan, ScanArgs SA, int t_fixed, float4* __restrict__ mmv_out) {
   if (do_scan && blockIdx.x == 0) {
     scan_touched<256>(SA.counts, SA.offsets, SA.touched, SA.n_touched, SA.list, SA.list_n, SA.n_keys, 1, SA.split_nt,
-                      SA.max_chunks);
+                      SA.max_chunks, SA.order_nt);
     return;
   }
   const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
@@ -1153,7 +1187,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   const int N = f.N;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
-                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD, f.share_chunks > 0 ? NT : 0, f.share_chunks);
+                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD, f.share_chunks > 0 ? NT : 0, f.share_chunks, NT);
   import_permute(f, user, P.mat, f.buf[0], s);
   PartArgs A;
   A.N = N;
@@ -1224,6 +1258,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     SA.n_keys = g.n_keys;
     SA.split_nt = f.share_chunks > 0 ? NT : 0;
     SA.max_chunks = f.share_chunks;
+    SA.order_nt = NT;
     k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.cl_list, f.cl_count + ((step + 1) & 1),
                                                f.cl_count + ((step + 2) & 1), f.tile_box, f.tiles, f.gen,
                                                (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA, -1, nullptr);
@@ -1304,6 +1339,10 @@ int fast_run(FastPath& f, const StepParams& P, const PState& user, int t0, int n
 
 uint32_t fast_next_sid(FastPath& f) { return ++f.sid; }
 
+// workgroup size of the kernels that read the lists of sorted states (the
+// records' forward kernels and the tiled adjoint's)
+constexpr int SORTED_NT = 256;
+
 void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, SortedState& out, hipStream_t s,
                     bool touched) {
   const int N = f.N;
@@ -1311,7 +1350,7 @@ void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, Sorted
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
                             out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE,
-                            IMPORT_PAD, 0, 0);
+                            IMPORT_PAD, 0, 0, SORTED_NT);
   import_permute(f, user, P.mat, out.b, s);
 }
 
@@ -1322,7 +1361,8 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
   k_keys_next<<<nblk(N, 256), 256, 0, s>>>(next.f, prev.b.key, N, P, f.g, f.counts, f.key_tmp, f.rank_tmp,
                                            touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
-                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1, 0, 0);
+                            out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1, 0, 0,
+                            SORTED_NT);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 
@@ -1377,6 +1417,7 @@ void fast_grid_scan(FastPath& f, const StepParams& P, const SortedState& st, uin
   SA.n_keys = f.g.n_keys;
   SA.split_nt = 0;       // the adjoint's records list each block once
   SA.max_chunks = 0;
+  SA.order_nt = SORTED_NT;
   const int do_scan = scan_list ? 1 : 0;
   k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, f.g, st.cl_list ? st.cl_list : f.cl_list,
                                               st.cl_count ? st.cl_count : f.cl_count, cl_zero, f.tile_box, f.tiles,
