@@ -40,8 +40,10 @@ def block_keys(x, n_grid, scene):
 
 
 def check_sort(sim, x, n_grid, scene, which=0):
-    """which = 2: the sort of the adjoint's recompute, whose block list must
-    also be in increasing key order (the scan over all keys)."""
+    """which = 0: the import of a call, whose block list gives the blocks of
+    more than 256 particles first; which = 2: the sort of the adjoint's
+    recompute, whose block list must be in increasing key order (the scan
+    over all keys)."""
     ids, keys, lst = sim.sort_snapshot(which)
     N = x.shape[0]
     # every particle exactly once
@@ -56,6 +58,11 @@ def check_sort(sim, x, n_grid, scene, which=0):
     assert (cnt > 0).all() and len(np.unique(lk)) == len(lk)
     if which == 2:
         assert (np.diff(lk) > 0).all()
+    else:
+        # longest first: the blocks of more than one 256-particle chunk are
+        # listed before those of one
+        big = cnt > 256
+        assert not (big[1:] & ~big[:-1]).any()
     for k, o, c in zip(lk, lo, cnt):
         assert (keys[o:o + c] == k).all()
     # counts equal the histogram of the keys
