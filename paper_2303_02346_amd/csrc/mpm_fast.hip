@@ -78,56 +78,95 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
 // touched; only contiguity matters.  With split_nt > 0 a block of more than
 // max_chunks chunks of split_nt particles is listed twice, sub 0 with the
 // first ceil(chunks / 2) chunks and sub 1 with the rest, so that two
-// workgroups share it (each publishes its own tile slot).  Entries of two or
-// more chunks (of split_nt particles, else of order_nt; none if both are 0)
-// are listed before those of one: the particle kernels' workgroups are
-// dispatched round-robin over the CUs, so each CU then receives about as
-// many chunks as the others, the longest first.
+// workgroups share it (each publishes its own tile slot); with fill_slots >
+// 0 as well, blocks of two chunks are split too (the first ones in touch
+// order) while the list has fewer entries than fill_slots, the particle
+// kernel's resident workgroups.  Entries of two or more chunks (of split_nt
+// particles, else of order_nt; none if both are 0) are listed before those
+// of one: the particle kernels' workgroups are dispatched round-robin over
+// the CUs, so each CU then receives about as many chunks as the others, the
+// longest first.
 template <int NT>
 __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
                              const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                              int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys, int stride = 1,
-                             int split_nt = 0, int max_chunks = 2, int order_nt = 0) {
+                             int split_nt = 0, int max_chunks = 2, int order_nt = 0, int fill_slots = 0) {
   constexpr int NW = NT / 64;
-  __shared__ uint32_t s_sum[NW], s_big[NW], s_sm[NW];
-  __shared__ uint32_t s_run, s_runbig, s_runsm, s_nbig;
+  __shared__ uint32_t s_sum[NW], s_big[NW], s_sm[NW], s_cand[NW];
+  __shared__ uint32_t s_run, s_runbig, s_runsm, s_runcand, s_nbig, s_nent, s_ncand;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const uint32_t n = min(n_touched[0], (uint32_t)n_keys);
-  // the entries of a key with c particles: their chunk counts and classes
+  // the chunks of a key with c particles, whether it is split by size, and
+  // whether it may be split to fill the resident workgroups
   const uint32_t cs = (uint32_t)(split_nt > 0 ? split_nt : order_nt);
-  auto entries = [&](uint32_t c, bool valid, uint32_t& sp, uint32_t& ch0, bool& big0, bool& big1) {
-    const uint32_t nch = cs > 0 ? (c + cs - 1) / cs : 0u;
-    sp = (valid && split_nt > 0 && nch > (uint32_t)max_chunks) ? 1u : 0u;
+  auto chunks = [&](uint32_t c) { return cs > 0 ? (c + cs - 1) / cs : 0u; };
+  auto size_split = [&](uint32_t nch) { return split_nt > 0 && nch > (uint32_t)max_chunks; };
+  auto fill_candidate = [&](uint32_t nch) { return fill_slots > 0 && split_nt > 0 && nch == 2u && !size_split(nch); };
+  // its entries' classes (two or more chunks: big)
+  auto classes = [&](uint32_t nch, bool valid, bool sp, uint32_t& ch0, bool& big0, bool& big1) {
     ch0 = sp ? (nch + 1) / 2 : nch;
     big0 = valid && ch0 >= 2u;
     big1 = sp && (nch - ch0) >= 2u;
   };
-  if (t == 0) { s_run = 0; s_runbig = 0; s_runsm = 0; s_nbig = 0; }
+  if (t == 0) { s_run = 0; s_runbig = 0; s_runsm = 0; s_runcand = 0; s_nbig = 0; s_nent = 0; s_ncand = 0; }
   __syncthreads();
   if (cs > 0) {
-    // first pass: the number of entries of two or more chunks
-    uint32_t nb = 0;
+    // first pass: the entries (big ones, all) and the fill candidates
+    uint32_t nb = 0, ne = 0, nc = 0;
     for (uint32_t i = t; i < n; i += NT) {
-      uint32_t sp, ch0;
+      const uint32_t nch = chunks(counts[(size_t)touched[i] * stride]);
+      const bool sp = size_split(nch);
+      uint32_t ch0;
       bool b0, b1;
-      entries(counts[(size_t)touched[i] * stride], true, sp, ch0, b0, b1);
+      classes(nch, true, sp, ch0, b0, b1);
       nb += (b0 ? 1u : 0u) + (b1 ? 1u : 0u);
+      ne += sp ? 2u : 1u;
+      nc += fill_candidate(nch) ? 1u : 0u;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) nb += __shfl_xor(nb, off);
-    if (lane == 0 && nb) atomicAdd(&s_nbig, nb);
+    for (int off = 32; off > 0; off >>= 1) {
+      nb += __shfl_xor(nb, off);
+      ne += __shfl_xor(ne, off);
+      nc += __shfl_xor(nc, off);
+    }
+    if (lane == 0) {
+      atomicAdd(&s_nbig, nb);
+      atomicAdd(&s_nent, ne);
+      atomicAdd(&s_ncand, nc);
+    }
     __syncthreads();
   }
-  const uint32_t nbig = s_nbig;
+  // the first `fill` candidates are split: each turns one big entry into two
+  // of one chunk
+  const uint32_t fill = (fill_slots > 0 && (uint32_t)fill_slots > s_nent) ? min((uint32_t)fill_slots - s_nent, s_ncand) : 0u;
+  const uint32_t nbig = s_nbig - fill;
   for (uint32_t c0 = 0; c0 < n; c0 += NT) {
     const uint32_t i = c0 + t;
+    const bool valid = i < n;
     uint32_t key = 0, c = 0;
-    if (i < n) { key = touched[i]; c = counts[(size_t)key * stride]; }
-    uint32_t sp, ch0;
+    if (valid) { key = touched[i]; c = counts[(size_t)key * stride]; }
+    const uint32_t nch = valid ? chunks(c) : 0u;
+    const bool cand = valid && fill_candidate(nch);
+    uint32_t icand = cand ? 1u : 0u;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = __shfl_up(icand, off);
+      if (lane >= off) icand += o;
+    }
+    if (lane == 63) s_cand[wv] = icand;
+    __syncthreads();
+    uint32_t wcand = s_runcand, totcand = s_runcand;
+#pragma unroll
+    for (int q = 0; q < NW; q++) {
+      if (q < wv) wcand += s_cand[q];
+      totcand += s_cand[q];
+    }
+    const bool sp = valid && (size_split(nch) || (cand && wcand + icand - 1u < fill));
+    uint32_t ch0;
     bool big0, big1;
-    entries(c, i < n, sp, ch0, big0, big1);
+    classes(nch, valid, sp, ch0, big0, big1);
     const uint32_t eb = (big0 ? 1u : 0u) + (big1 ? 1u : 0u);
-    const uint32_t es = (i < n ? 1u : 0u) + sp - eb;
+    const uint32_t es = (valid ? 1u : 0u) + (sp ? 1u : 0u) - eb;
     uint32_t is = c, ib = eb, ism = es;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -144,7 +183,7 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
       totb += s_big[q];
       totsm += s_sm[q];
     }
-    if (i < n) {
+    if (valid) {
       const uint32_t o = woff + is - c;
       uint32_t pb = wb + ib - eb, ps = nbig + wsm + ism - es;
       offsets[key] = o;
@@ -158,7 +197,7 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
       }
     }
     __syncthreads();
-    if (t == 0) { s_run = tot; s_runbig = totb; s_runsm = totsm; }
+    if (t == 0) { s_run = tot; s_runbig = totb; s_runsm = totsm; s_runcand = totcand; }
     __syncthreads();
   }
   if (t == 0) { list_n[0] = s_runbig + s_runsm; n_touched[0] = 0u; }
@@ -278,14 +317,15 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ counts, ui
                                                const uint32_t* __restrict__ touched, uint32_t* __restrict__ n_touched,
                                                int4* __restrict__ list, uint32_t* __restrict__ list_n, int n_keys,
                                                uint32_t* __restrict__ epoch, uint32_t* __restrict__ cl_count,
-                                               int mode, int stride, int split_nt, int max_chunks, int order_nt) {
+                                               int mode, int stride, int split_nt, int max_chunks, int order_nt,
+                                               int fill_slots) {
   constexpr int NT = 1024;
   if (mode == SCAN_DENSE) {
     scan_keys<NT>(counts, offsets, list, list_n, n_keys, stride);
     if (threadIdx.x == 0) n_touched[0] = 0u;
   } else {
     scan_touched<1024>(counts, offsets, touched, n_touched, list, list_n, n_keys, stride, split_nt, max_chunks,
-                       order_nt);
+                       order_nt, fill_slots);
   }
   if (threadIdx.x == 0) { epoch[0] = epoch[0] + 1; cl_count[0] = 0u; cl_count[1] = 0u; }
 }
@@ -925,6 +965,7 @@ struct ScanArgs {
   int split_nt;     // particles per chunk of the particle kernel that reads the list (0: no sharing)
   int max_chunks;   // chunks above which a block is shared by two workgroups
   int order_nt;     // chunk size that orders the entries when split_nt is 0 (0: first-touch order)
+  int fill_slots;   // resident workgroups of the particle kernel that split blocks may fill (0: none)
 };
 
 // With do_scan, workgroup 0 scans the key counts of this step's particle
@@ -938,7 +979,7 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
                                               int do_scan, ScanArgs SA, int t_fixed, float4* __restrict__ mmv_out) {
   if (do_scan && blockIdx.x == 0) {
     scan_touched<256>(SA.counts, SA.offsets, SA.touched, SA.n_touched, SA.list, SA.list_n, SA.n_keys, 1, SA.split_nt,
-                      SA.max_chunks, SA.order_nt);
+                      SA.max_chunks, SA.order_nt, SA.fill_slots);
     return;
   }
   const uint32_t wg = blockIdx.x - (do_scan ? 1 : 0), n_wg = gridDim.x - (do_scan ? 1 : 0);
@@ -1151,6 +1192,18 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.grid_wgs = 2048;
   f.valid = false;
   f.sid = 0;
+  {
+    int dev = 0, cus = 0, occ[3] = {0, 0, 0};
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_particles<MODE_FUSED, 128, FEAT_NONE>, 128, 0) != hipSuccess)
+      occ[0] = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_particles<MODE_FUSED, 256, FEAT_NONE>, 256, 0) != hipSuccess)
+      occ[1] = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_particles<MODE_FUSED, 512, FEAT_NONE>, 512, 0) != hipSuccess)
+      occ[2] = 0;
+    for (int q = 0; q < 3; q++) f.fused_slots[q] = cus * occ[q];
+  }
   // zero the bookkeeping (counts, stamps, counters, velocity grid)
   launch_zero(ws + L.counts, a256((size_t)f.g.n_keys * 4), s);
   launch_zero(ws + L.cpad, a256((size_t)f.g.n_keys * IMPORT_PAD * 4), s);
@@ -1185,9 +1238,16 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
                          const float* act, hipStream_t s, std::vector<hipEvent_t>* ev) {
   const FastGeom g = f.g;
   const int N = f.N;
+  // blocks of two chunks are also split while the list has fewer entries
+  // than the particle kernel has resident workgroups (without the closure
+  // features, whose kernels have other occupancies)
+  const int fill_slots = (FEAT == FEAT_NONE && f.share_chunks > 0)
+                             ? std::min(f.part_wgs, f.fused_slots[NT == 128 ? 0 : (NT == 256 ? 1 : 2)])
+                             : 0;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
-                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD, f.share_chunks > 0 ? NT : 0, f.share_chunks, NT);
+                            f.cl_count, SCAN_TOUCHED, IMPORT_PAD, f.share_chunks > 0 ? NT : 0, f.share_chunks, NT,
+                            fill_slots);
   import_permute(f, user, P.mat, f.buf[0], s);
   PartArgs A;
   A.N = N;
@@ -1259,6 +1319,7 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
     SA.split_nt = f.share_chunks > 0 ? NT : 0;
     SA.max_chunks = f.share_chunks;
     SA.order_nt = NT;
+    SA.fill_slots = fill_slots;
     k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, g, f.cl_list, f.cl_count + ((step + 1) & 1),
                                                f.cl_count + ((step + 2) & 1), f.tile_box, f.tiles, f.gen,
                                                (uint32_t)(step + 1), f.vgrid, pose, act, f.t0_dev, do_scan, SA, -1, nullptr);
@@ -1350,7 +1411,7 @@ void fast_sort_user(FastPath& f, const StepParams& P, const PState& user, Sorted
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, f.g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
                             out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE,
-                            IMPORT_PAD, 0, 0, SORTED_NT);
+                            IMPORT_PAD, 0, 0, SORTED_NT, 0);
   import_permute(f, user, P.mat, out.b, s);
 }
 
@@ -1362,7 +1423,7 @@ void fast_sort_next(FastPath& f, const StepParams& P, const SortedState& prev, c
                                            touched ? f.touched : nullptr, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.counts, f.offsets, f.touched, f.n_touched, out.list, out.list_n, f.g.n_keys, f.gen,
                             out.cl_count ? out.cl_count : f.cl_count, touched ? SCAN_TOUCHED : SCAN_DENSE, 1, 0, 0,
-                            SORTED_NT);
+                            SORTED_NT, 0);
   k_sort_permute<<<nblk(N, 256), 256, 0, s>>>(next, out.b, N, f.key_tmp, f.rank_tmp, f.offsets, map);
 }
 
@@ -1418,6 +1479,7 @@ void fast_grid_scan(FastPath& f, const StepParams& P, const SortedState& st, uin
   SA.split_nt = 0;       // the adjoint's records list each block once
   SA.max_chunks = 0;
   SA.order_nt = SORTED_NT;
+  SA.fill_slots = 0;
   const int do_scan = scan_list ? 1 : 0;
   k_grid<<<f.grid_wgs + do_scan, 256, 0, s>>>(P, f.g, st.cl_list ? st.cl_list : f.cl_list,
                                               st.cl_count ? st.cl_count : f.cl_count, cl_zero, f.tile_box, f.tiles,
