@@ -74,7 +74,7 @@ struct FastPath {
   uint32_t* cl_list;       // keys of the blocks claimed in the current step
   uint32_t* cl_count;      // [2]: claims of odd and even step ids
   int2* tile_box;          // {packed lo/hi, stamp} per tile slot
-  float* tiles;            // NSUB n_keys slots x 4 x TILE_NODES
+  float* tiles;            // NSUB n_keys slots of 4 TILE_NODES floats (forward: a float4 (m, mv) per node)
   float4* vgrid;           // n_keys x 64
   uint32_t* gen;           // device per-call epoch of the step stamps
   int* t0_dev;             // device clock at the start of the call

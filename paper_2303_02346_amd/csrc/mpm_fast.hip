@@ -904,12 +904,12 @@ k_particles(PartArgs A, StepParams P, FastGeom g) {
       if (lo0 <= hi0 - 2) {
         const int ex = hi0 - lo0 + 1, ey = hi1 - lo1 + 1, ez = hi2 - lo2 + 1;
         const int cnt = ex * ey * ez;
-        float* T = A.tiles + slot * 4 * TILE_NODES;
+        // in global memory a node's (m, mv) is one 16-byte word
+        float4* T = reinterpret_cast<float4*>(A.tiles + slot * 4 * TILE_NODES);
         for (int r = tid; r < cnt; r += NT) {
           int qi = lo0 + r / (ey * ez), qj = lo1 + (r / ez) % ey, qk = lo2 + r % ez;
           int q = (qi * TILE + qj) * TILE + qk;
-#pragma unroll
-          for (int c = 0; c < 4; c++) T[c * TILE_NODES + q] = s_tile[c * TILE_NODES + q];
+          T[q] = make_float4(s_tile[q], s_tile[TILE_NODES + q], s_tile[2 * TILE_NODES + q], s_tile[3 * TILE_NODES + q]);
         }
         if (tid == 0) {
           int packed = lo0 | (lo1 << 4) | (lo2 << 8) | (hi0 << 12) | (hi1 << 16) | (hi2 << 20);
@@ -1030,12 +1030,11 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
         const int hi0 = (bxv >> 12) & 15, hi1 = (bxv >> 16) & 15, hi2 = (bxv >> 20) & 15;
         const bool in = valid && qi >= lo0 && qi <= hi0 && qj >= lo1 && qj <= hi1 && qk >= lo2 && qk <= hi2;
         const int q = in ? (qi * TILE + qj) * TILE + qk : 0;
-        const float* T = tiles + (size_t)(in ? kk : 0u) * 4 * TILE_NODES;
-        const float t0 = T[q], t1 = T[TILE_NODES + q], t2 = T[2 * TILE_NODES + q], t3 = T[3 * TILE_NODES + q];
-        acc.w += in ? t0 : 0.f;
-        acc.x += in ? t1 : 0.f;
-        acc.y += in ? t2 : 0.f;
-        acc.z += in ? t3 : 0.f;
+        const float4 tv = reinterpret_cast<const float4*>(tiles + (size_t)(in ? kk : 0u) * 4 * TILE_NODES)[q];
+        acc.w += in ? tv.x : 0.f;
+        acc.x += in ? tv.y : 0.f;
+        acc.y += in ? tv.z : 0.f;
+        acc.z += in ? tv.w : 0.f;
       }
       // the few valid second slots, one at a time
       unsigned long long m1 = __ballot(lane >= 32 && nbox.y != 0);
@@ -1050,11 +1049,11 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
         const int lo0 = bxv & 15, lo1 = (bxv >> 4) & 15, lo2 = (bxv >> 8) & 15;
         const int hi0 = (bxv >> 12) & 15, hi1 = (bxv >> 16) & 15, hi2 = (bxv >> 20) & 15;
         if (qi >= lo0 && qi <= hi0 && qj >= lo1 && qj <= hi1 && qk >= lo2 && qk <= hi2) {
-          const float* T = tiles + (size_t)kk * 4 * TILE_NODES + (qi * TILE + qj) * TILE + qk;
-          acc.w += T[0];
-          acc.x += T[TILE_NODES];
-          acc.y += T[2 * TILE_NODES];
-          acc.z += T[3 * TILE_NODES];
+          const float4 tv = reinterpret_cast<const float4*>(tiles + (size_t)kk * 4 * TILE_NODES)[(qi * TILE + qj) * TILE + qk];
+          acc.w += tv.x;
+          acc.x += tv.y;
+          acc.y += tv.z;
+          acc.z += tv.w;
         }
       }
       float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
