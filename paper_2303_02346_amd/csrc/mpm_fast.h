@@ -82,7 +82,7 @@ struct FastPath {
   // launch shape and mode (set by mpm_set_option / the autotuner)
   int part_threads;        // 128, 256 or 512 threads (particles per chunk) per particle workgroup
   int share_chunks;        // a block of more chunks than this is shared by two workgroups (0: never)
-  int fused_slots[3];      // resident workgroups of the fused kernel (CUs x occupancy) at 128, 256, 512 threads
+  int fused_slots;         // resident 256-thread workgroups of the fused kernel (CUs x occupancy)
   bool use_graph;          // capture each call shape once and replay it
   bool do_export;          // write the result back to the user arrays
   std::vector<FastGraph> graphs;

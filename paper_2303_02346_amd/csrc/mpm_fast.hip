@@ -137,8 +137,11 @@ __device__ void scan_touched(uint32_t* __restrict__ counts, uint32_t* __restrict
     __syncthreads();
   }
   // the first `fill` candidates are split: each turns one big entry into two
-  // of one chunk
-  const uint32_t fill = (fill_slots > 0 && (uint32_t)fill_slots > s_nent) ? min((uint32_t)fill_slots - s_nent, s_ncand) : 0u;
+  // of one chunk.  At most one entry in 16 is added (every split adds a
+  // second tile slot that the grid kernel reads one at a time)
+  const uint32_t fill = (fill_slots > 0 && (uint32_t)fill_slots > s_nent)
+                            ? min(min((uint32_t)fill_slots - s_nent, s_ncand), s_nent / 16u)
+                            : 0u;
   const uint32_t nbig = s_nbig - fill;
   for (uint32_t c0 = 0; c0 < n; c0 += NT) {
     const uint32_t i = c0 + t;
@@ -1192,16 +1195,13 @@ int fast_init(FastPath& f, char* ws, int n_grid, int n_scenes, int N, hipStream_
   f.valid = false;
   f.sid = 0;
   {
-    int dev = 0, cus = 0, occ[3] = {0, 0, 0};
+    // resident 256-thread workgroups of the fused kernel: CUs x occupancy
+    int dev = 0, cus = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_particles<MODE_FUSED, 128, FEAT_NONE>, 128, 0) != hipSuccess)
-      occ[0] = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_particles<MODE_FUSED, 256, FEAT_NONE>, 256, 0) != hipSuccess)
-      occ[1] = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_particles<MODE_FUSED, 512, FEAT_NONE>, 512, 0) != hipSuccess)
-      occ[2] = 0;
-    for (int q = 0; q < 3; q++) f.fused_slots[q] = cus * occ[q];
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_particles<MODE_FUSED, 256, FEAT_NONE>, 256, 0) != hipSuccess)
+      occ = 0;
+    f.fused_slots = cus * occ;
   }
   // zero the bookkeeping (counts, stamps, counters, velocity grid)
   launch_zero(ws + L.counts, a256((size_t)f.g.n_keys * 4), s);
@@ -1238,11 +1238,9 @@ static void enqueue_call(FastPath& f, const StepParams& P, const PState& user, i
   const FastGeom g = f.g;
   const int N = f.N;
   // blocks of two chunks are also split while the list has fewer entries
-  // than the particle kernel has resident workgroups (without the closure
-  // features, whose kernels have other occupancies)
-  const int fill_slots = (FEAT == FEAT_NONE && f.share_chunks > 0)
-                             ? std::min(f.part_wgs, f.fused_slots[NT == 128 ? 0 : (NT == 256 ? 1 : 2)])
-                             : 0;
+  // than the particle kernel has resident workgroups, in 256-thread
+  // workgroups (three resident per CU) without the closure features
+  const int fill_slots = (NT == 256 && FEAT == FEAT_NONE && f.share_chunks > 0) ? std::min(f.part_wgs, f.fused_slots) : 0;
   k_import_keys<<<nblk(N, 256), 256, 0, s>>>(user, P, g, f.cpad, f.key_tmp, f.rank_tmp, f.touched, f.n_touched);
   k_scan<<<1, 1024, 0, s>>>(f.cpad, f.offsets, f.touched, f.n_touched, f.list[0], f.list_n + 0, g.n_keys, f.gen,
                             f.cl_count, SCAN_TOUCHED, IMPORT_PAD, f.share_chunks > 0 ? NT : 0, f.share_chunks, NT,
