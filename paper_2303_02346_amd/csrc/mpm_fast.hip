@@ -80,8 +80,9 @@ __global__ __launch_bounds__(256) void k_import_keys(PState u, StepParams P, Fas
 // first ceil(chunks / 2) chunks and sub 1 with the rest, so that two
 // workgroups share it (each publishes its own tile slot); with fill_slots >
 // 0 as well, blocks of two chunks are split too (the first ones in touch
-// order) while the list has fewer entries than fill_slots, the particle
-// kernel's resident workgroups.  Entries of two or more chunks (of split_nt
+// order, at most one added entry in 16) while the list has fewer entries
+// than fill_slots, the particle kernel's resident workgroups.  Entries of
+// two or more chunks (of split_nt
 // particles, else of order_nt; none if both are 0) are listed before those
 // of one: the particle kernels' workgroups are dispatched round-robin over
 // the CUs, so each CU then receives about as many chunks as the others, the
@@ -992,16 +993,21 @@ __global__ __launch_bounds__(256) void k_grid(StepParams P, FastGeom g, const ui
   const size_t t = t_fixed >= 0 ? (size_t)t_fixed : (size_t)t0_dev[0] + step_id - 1;
   const double* pose_t = pose_base + t * g.S * POSE_DOUBLES;
   const float* act_t = act_base + t * g.S * 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane >> 4, lj = (lane >> 2) & 3, lk = lane & 3;
+  // one claimed block per wavefront; a wavefront's first key is loaded
+  // together with the claim count (a list row past the count is stale and
+  // not used)
+  const uint32_t n_waves = 4u * n_wg;
+  uint32_t it = 4u * wg + (uint32_t)wv;
+  uint32_t key_it = it < (uint32_t)g.n_keys ? cl_list[it] : 0u;
   const uint32_t n_cl = cl_count[0];
   // the counter of the next step's claims starts at zero (nothing reads it now)
   if (cl_zero && wg == 0 && threadIdx.x == 0) cl_zero[0] = 0u;
   const uint32_t stamp = (gen[0] << 16) | step_id;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane >> 4, lj = (lane >> 2) & 3, lk = lane & 3;
-  // one claimed block per wavefront
-  const uint32_t n_waves = 4u * n_wg;
-  for (uint32_t it = 4u * wg + (uint32_t)wv; it < n_cl && it < (uint32_t)g.n_keys; it += n_waves) {
-    const uint32_t key = cl_list[it];
+  for (; it < n_cl && it < (uint32_t)g.n_keys; it += n_waves) {
+    const uint32_t key = key_it;
+    if (it + n_waves < (uint32_t)g.n_keys) key_it = cl_list[it + n_waves];
     int sc, cx, cy, cz;
     key_decode(g, key, sc, cx, cy, cz);
     {
